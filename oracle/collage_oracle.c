@@ -1,0 +1,508 @@
+/*
+ * collage_oracle.c -- plain FP64 CPU oracle of the image-space collage hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code, header, table or helper with the HIP path.
+ *
+ * What it computes, for every layout b of a batch and every pixel centre p = (i + 1/2, j + 1/2)
+ * (level pixels, y down), following the paper:
+ *
+ *   - Rigid transform of each item (Sec. 3, eq. 2 with a uniform scale as in Sec. 4 "Data
+ *     Visualization"):  v' = k * (R(theta) * (s * v) + t), k = level scale, rotation about the item's
+ *     area centroid (the local origin).
+ *   - Soft rasterization (Sec. 2 "Differentiable Rendering": an anti-aliased, continuous scene
+ *     function).  Reading used here: per item a coverage alpha = sigmoid(sd / tau), where sd is the
+ *     Euclidean signed distance to the closed outline (positive inside by the even-odd rule), with a
+ *     hard zero once sd < -r_cut; a padded coverage alpha_pad = sigmoid((sd + r_pad) / tau) with the
+ *     same cut-off on sd + r_pad.  S = sum_i alpha_i, S_pad = sum_i alpha_pad_i.
+ *   - Image-space losses (Sec. 3.2, eqs. for containment and non-overlap, in their differentiable
+ *     reading) plus padding and the downward force of Sec. 4 ("Force Attraction"):
+ *        L_ov   = sum_p relu(S - 1)^2           L_cont = sum_p S (1 - M)
+ *        L_fill = sum_p M relu(1 - S)^2         L_pad  = sum_p relu(S_pad - 1)^2
+ *        L_down = sum_p S (H - y_p)
+ *     reported weighted: loss[b][term] = w_term * L_term.
+ *   - The gradient of sum_b sum_term dloss[b][term] * loss[b][term] with respect to every item's
+ *     (t_x, t_y, theta, s) (Sec. 3, eq. 4 needs dL/dt, dL/dr, dL/ds), by the chain rule through the
+ *     two end points of each pixel's nearest edge and then through eq. 2.
+ *   - Adam on those gradients (the update of eq. 4 with Adam's moment estimates).
+ *
+ * All arithmetic is double precision; inputs are float32 values widened exactly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+  int32_t B;                /* layouts */
+  int32_t N;                /* items (all layouts) */
+  int32_t V;                /* outline vertices (all items) */
+  const int32_t *width;     /* [B] canvas width, level px */
+  const int32_t *height;    /* [B] canvas height, level px */
+  const double *scale;      /* [B] k */
+  const int32_t *shape_off; /* [B+1] item ranges */
+  const int32_t *vert_off;  /* [N+1] vertex ranges */
+  const double *verts;      /* [V*2] local frame, canonical px */
+  const double *mask;       /* packed masks, layout b at pixel offset sum_{c<b} W_c*H_c */
+  double tau, r_cut, r_pad;
+  double w[5];              /* overlap, contain, fill, pad, down */
+  int32_t use_cutoff;       /* 1: hard zero below -r_cut (the definition); 0: no cut-off */
+  int32_t use_bbox;         /* 1: skip pixels provably beyond the cut-off support (needs use_cutoff) */
+} oracle_scene;
+
+static int64_t pixel_offset(const oracle_scene *sc, int b) {
+  int64_t off = 0;
+  for (int c = 0; c < b; ++c) off += (int64_t)sc->width[c] * sc->height[c];
+  return off;
+}
+
+static int layout_of(const oracle_scene *sc, int i) {
+  for (int b = 0; b < sc->B; ++b)
+    if (i >= sc->shape_off[b] && i < sc->shape_off[b + 1]) return b;
+  return -1;
+}
+
+/* eq. 2: transformed vertices of item i in level pixels. */
+static void transform_item(const oracle_scene *sc, const double *params, int i, double k, double *out) {
+  const double tx = params[4 * i + 0], ty = params[4 * i + 1];
+  const double th = params[4 * i + 2], s = params[4 * i + 3];
+  const double c = cos(th), sn = sin(th);
+  for (int m = sc->vert_off[i]; m < sc->vert_off[i + 1]; ++m) {
+    const double x = s * sc->verts[2 * m], y = s * sc->verts[2 * m + 1];
+    out[2 * (m - sc->vert_off[i]) + 0] = k * (c * x - sn * y + tx);
+    out[2 * (m - sc->vert_off[i]) + 1] = k * (sn * x + c * y + ty);
+  }
+}
+
+typedef struct {
+  double sd;     /* signed distance, + inside */
+  double d;      /* unsigned distance */
+  int edge;      /* nearest edge (lowest index on exact ties) */
+  double u;      /* clamped parameter of the nearest point on that edge */
+  double qx, qy; /* nearest point */
+  int inside;
+} sd_result;
+
+/* Euclidean distance to the closed polygon and even-odd inside test with the half-open rule. */
+static sd_result signed_distance(double px, double py, const double *P, int n) {
+  sd_result r;
+  double best = INFINITY;
+  int best_m = 0;
+  double best_u = 0.0;
+  int inside = 0;
+  for (int m = 0; m < n; ++m) {
+    const double ax = P[2 * m], ay = P[2 * m + 1];
+    const int mn = (m + 1 == n) ? 0 : m + 1;
+    const double bx = P[2 * mn], by = P[2 * mn + 1];
+    const double ex = bx - ax, ey = by - ay;
+    const double ee = ex * ex + ey * ey;
+    double u = 0.0;
+    if (ee > 0.0) {
+      u = ((px - ax) * ex + (py - ay) * ey) / ee;
+      if (u < 0.0) u = 0.0;
+      if (u > 1.0) u = 1.0;
+    }
+    const double qx = ax + u * ex, qy = ay + u * ey;
+    const double d2 = (px - qx) * (px - qx) + (py - qy) * (py - qy);
+    if (d2 < best) {
+      best = d2;
+      best_m = m;
+      best_u = u;
+    }
+    if ((ay > py) != (by > py)) {
+      const double xc = ax + (py - ay) * ex / ey;
+      if (px < xc) inside = !inside;
+    }
+  }
+  r.d = sqrt(best);
+  r.sd = inside ? r.d : -r.d;
+  r.edge = best_m;
+  r.u = best_u;
+  {
+    const double ax = P[2 * best_m], ay = P[2 * best_m + 1];
+    const int mn = (best_m + 1 == n) ? 0 : best_m + 1;
+    r.qx = ax + best_u * (P[2 * mn] - ax);
+    r.qy = ay + best_u * (P[2 * mn + 1] - ay);
+  }
+  r.inside = inside;
+  return r;
+}
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Coverage of one item at one pixel and its derivative with respect to sd. */
+static void coverage(const oracle_scene *sc, double sd, double *a, double *da, double *ap, double *dap) {
+  const double x = sd / sc->tau, xp = (sd + sc->r_pad) / sc->tau;
+  if (sc->use_cutoff && sd < -sc->r_cut) {
+    *a = 0.0;
+    *da = 0.0;
+  } else {
+    *a = sigmoid(x);
+    *da = *a * (1.0 - *a) / sc->tau;
+  }
+  if (sc->use_cutoff && sd + sc->r_pad < -sc->r_cut) {
+    *ap = 0.0;
+    *dap = 0.0;
+  } else {
+    *ap = sigmoid(xp);
+    *dap = *ap * (1.0 - *ap) / sc->tau;
+  }
+}
+
+/* Pixel index range that can receive non-zero coverage from polygon P (cut-off on), inclusive. */
+static void support_box(const oracle_scene *sc, const double *P, int n, int W, int H, int *x0, int *y0, int *x1,
+                        int *y1) {
+  double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  for (int m = 0; m < n; ++m) {
+    if (P[2 * m] < mnx) mnx = P[2 * m];
+    if (P[2 * m] > mxx) mxx = P[2 * m];
+    if (P[2 * m + 1] < mny) mny = P[2 * m + 1];
+    if (P[2 * m + 1] > mxy) mxy = P[2 * m + 1];
+  }
+  const double ext = sc->r_cut + (sc->r_pad > 0.0 ? sc->r_pad : 0.0) + 1.0;
+  double fx0 = floor(mnx - ext - 0.5), fx1 = ceil(mxx + ext - 0.5);
+  double fy0 = floor(mny - ext - 0.5), fy1 = ceil(mxy + ext - 0.5);
+  if (fx0 < 0) fx0 = 0;
+  if (fy0 < 0) fy0 = 0;
+  if (fx1 > W - 1) fx1 = W - 1;
+  if (fy1 > H - 1) fy1 = H - 1;
+  if (!(fx0 <= fx1) || !(fy0 <= fy1) || n == 0) {
+    *x0 = 1;
+    *x1 = 0;
+    *y0 = 1;
+    *y1 = 0;
+    return;
+  }
+  *x0 = (int)fx0;
+  *x1 = (int)fx1;
+  *y0 = (int)fy0;
+  *y1 = (int)fy1;
+}
+
+typedef struct {
+  double *P;  /* transformed vertices of all items, [V*2] */
+  int *box;   /* [N*4] x0, y0, x1, y1 */
+} prepared;
+
+static void prepare(const oracle_scene *sc, const double *params, prepared *pr) {
+  pr->P = (double *)malloc(sizeof(double) * 2 * (sc->V > 0 ? sc->V : 1));
+  pr->box = (int *)malloc(sizeof(int) * 4 * (sc->N > 0 ? sc->N : 1));
+  for (int b = 0; b < sc->B; ++b) {
+    for (int i = sc->shape_off[b]; i < sc->shape_off[b + 1]; ++i) {
+      const int n = sc->vert_off[i + 1] - sc->vert_off[i];
+      double *P = pr->P + 2 * sc->vert_off[i];
+      transform_item(sc, params, i, sc->scale[b], P);
+      if (sc->use_bbox && sc->use_cutoff) {
+        support_box(sc, P, n, sc->width[b], sc->height[b], &pr->box[4 * i], &pr->box[4 * i + 1],
+                    &pr->box[4 * i + 2], &pr->box[4 * i + 3]);
+      } else {
+        pr->box[4 * i] = 0;
+        pr->box[4 * i + 1] = 0;
+        pr->box[4 * i + 2] = sc->width[b] - 1;
+        pr->box[4 * i + 3] = sc->height[b] - 1;
+      }
+    }
+  }
+}
+
+static void release(prepared *pr) {
+  free(pr->P);
+  free(pr->box);
+}
+
+static int in_box(const int *bx, int i, int j) { return i >= bx[0] && i <= bx[2] && j >= bx[1] && j <= bx[3]; }
+
+/* S and S_pad for all layouts (packed), and the weighted loss terms [B*5]. */
+static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, double *Sp, double *loss) {
+  for (int b = 0; b < sc->B; ++b) {
+    const int W = sc->width[b], H = sc->height[b];
+    const int64_t off = pixel_offset(sc, b);
+    /* per-row partial sums, added in row order afterwards, so the result does not depend on threads */
+    double *rows = (double *)calloc((size_t)5 * (H > 0 ? H : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j) {
+      double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0;
+      for (int i = 0; i < W; ++i) {
+        const double px = i + 0.5, py = j + 0.5;
+        double s = 0.0, spad = 0.0;
+        for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) {
+          if (!in_box(pr->box + 4 * q, i, j)) continue;
+          const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+          if (n == 0) continue;
+          const sd_result r = signed_distance(px, py, pr->P + 2 * sc->vert_off[q], n);
+          double a, da, ap, dap;
+          coverage(sc, r.sd, &a, &da, &ap, &dap);
+          s += a;
+          spad += ap;
+        }
+        const int64_t idx = off + (int64_t)j * W + i;
+        if (S) S[idx] = s;
+        if (Sp) Sp[idx] = spad;
+        const double M = sc->mask ? sc->mask[idx] : 0.0;
+        const double ov = s > 1.0 ? s - 1.0 : 0.0;
+        const double un = s < 1.0 ? 1.0 - s : 0.0;
+        const double pv = spad > 1.0 ? spad - 1.0 : 0.0;
+        lo += ov * ov;
+        lc += s * (1.0 - M);
+        lf += M * un * un;
+        lp += pv * pv;
+        ld += s * (H - py);
+      }
+      rows[5 * j + 0] = lo;
+      rows[5 * j + 1] = lc;
+      rows[5 * j + 2] = lf;
+      rows[5 * j + 3] = lp;
+      rows[5 * j + 4] = ld;
+    }
+    double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0;
+    for (int j = 0; j < H; ++j) {
+      lo += rows[5 * j + 0];
+      lc += rows[5 * j + 1];
+      lf += rows[5 * j + 2];
+      lp += rows[5 * j + 3];
+      ld += rows[5 * j + 4];
+    }
+    free(rows);
+    if (loss) {
+      loss[5 * b + 0] = sc->w[0] * lo;
+      loss[5 * b + 1] = sc->w[1] * lc;
+      loss[5 * b + 2] = sc->w[2] * lf;
+      loss[5 * b + 3] = sc->w[3] * lp;
+      loss[5 * b + 4] = sc->w[4] * ld;
+    }
+  }
+}
+
+int oracle_forward(const oracle_scene *sc, const double *params, double *S, double *Sp, double *loss) {
+  if (!sc || !params) return -1;
+  if (sc->use_bbox && !sc->use_cutoff) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  forward_impl(sc, &pr, S, Sp, loss);
+  release(&pr);
+  return 0;
+}
+
+/* Per-item coverage images alpha (and alpha_pad) for items [first, first+count), each on its own
+ * layout's canvas, written consecutively. */
+int oracle_render(const oracle_scene *sc, const double *params, int first, int count, double *alpha, double *alpha_pad) {
+  if (!sc || !params || first < 0 || count < 0 || first + count > sc->N) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  int64_t out = 0;
+  for (int q = first; q < first + count; ++q) {
+    const int b = layout_of(sc, q);
+    const int W = sc->width[b], H = sc->height[b];
+    const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j) {
+      for (int i = 0; i < W; ++i) {
+        double a = 0.0, ap = 0.0, da, dap;
+        if (n > 0 && in_box(pr.box + 4 * q, i, j)) {
+          const sd_result r = signed_distance(i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
+          coverage(sc, r.sd, &a, &da, &ap, &dap);
+        }
+        if (alpha) alpha[out + (int64_t)j * W + i] = a;
+        if (alpha_pad) alpha_pad[out + (int64_t)j * W + i] = ap;
+      }
+    }
+    out += (int64_t)W * H;
+  }
+  release(&pr);
+  return 0;
+}
+
+/* Signed distances of items [first, first+count) at every pixel (for tests of the geometry). */
+int oracle_signed_distance(const oracle_scene *sc, const double *params, int first, int count, double *sd,
+                           int32_t *edge) {
+  if (!sc || !params || first < 0 || count < 0 || first + count > sc->N) return -1;
+  oracle_scene full = *sc;
+  full.use_bbox = 0;
+  prepared pr;
+  prepare(&full, params, &pr);
+  int64_t out = 0;
+  for (int q = first; q < first + count; ++q) {
+    const int b = layout_of(sc, q);
+    const int W = sc->width[b], H = sc->height[b];
+    const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < W; ++i) {
+        sd_result r;
+        if (n > 0) {
+          r = signed_distance(i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
+        } else {
+          r.sd = -INFINITY;
+          r.edge = -1;
+        }
+        sd[out + (int64_t)j * W + i] = r.sd;
+        if (edge) edge[out + (int64_t)j * W + i] = r.edge;
+      }
+    out += (int64_t)W * H;
+  }
+  release(&pr);
+  return 0;
+}
+
+/*
+ * Gradient of sum_b sum_t dloss[b,t] * loss[b,t] with respect to params [N*4].
+ *
+ * dLoss/dS(p) and dLoss/dS_pad(p) follow from the loss definitions (relu'(0) = 0).  Each item's
+ * contribution at pixel p is omega * dsd/dparam, omega = G * dalpha/dsd + G_pad * dalpha_pad/dsd.
+ * dsd/dparam is taken through the vertices: for the nearest point q = a + u (b - a) on the nearest
+ * edge (a, b), with g = (p - q)/|p - q| and sign +1 inside / -1 outside,
+ *     dsd/da = -sign (1 - u) g,  dsd/db = -sign u g          (0 < u < 1)
+ *     dsd/da = -sign g (u = 0),  dsd/db = -sign g (u = 1)    (nearest point is an end point)
+ * and through eq. 2, v' = k (R(theta) s v + t):
+ *     dv'/dt = k I,   dv'/dtheta = k s R'(theta) v,   dv'/ds = k R(theta) v.
+ * A pixel centre lying exactly on the outline (|p - q| = 0) contributes nothing.
+ */
+int oracle_backward(const oracle_scene *sc, const double *params, const double *dloss, double *grad) {
+  if (!sc || !params || !dloss || !grad) return -1;
+  if (sc->use_bbox && !sc->use_cutoff) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  int64_t total = pixel_offset(sc, sc->B);
+  double *S = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Sp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *G = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Gp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  forward_impl(sc, &pr, S, Sp, NULL);
+  for (int b = 0; b < sc->B; ++b) {
+    const int W = sc->width[b], H = sc->height[b];
+    const int64_t off = pixel_offset(sc, b);
+    const double c_ov = dloss[5 * b + 0] * sc->w[0], c_c = dloss[5 * b + 1] * sc->w[1];
+    const double c_f = dloss[5 * b + 2] * sc->w[2], c_p = dloss[5 * b + 3] * sc->w[3];
+    const double c_d = dloss[5 * b + 4] * sc->w[4];
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < W; ++i) {
+        const int64_t idx = off + (int64_t)j * W + i;
+        const double s = S[idx], sp = Sp[idx];
+        const double M = sc->mask ? sc->mask[idx] : 0.0;
+        const double ov = s > 1.0 ? s - 1.0 : 0.0;
+        const double un = s < 1.0 ? 1.0 - s : 0.0;
+        const double pv = sp > 1.0 ? sp - 1.0 : 0.0;
+        G[idx] = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * M * un + c_d * (H - (j + 0.5));
+        Gp[idx] = 2.0 * c_p * pv;
+      }
+  }
+  for (int b = 0; b < sc->B; ++b) {
+    const int W = sc->width[b];
+    const int64_t off = pixel_offset(sc, b);
+    const double k = sc->scale[b];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) {
+      const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+      double g[4] = {0, 0, 0, 0};
+      if (n > 0) {
+        const double *P = pr.P + 2 * sc->vert_off[q];
+        const double th = params[4 * q + 2], s = params[4 * q + 3];
+        const double c = cos(th), sn = sin(th);
+        const int *bx = pr.box + 4 * q;
+        for (int j = bx[1]; j <= bx[3]; ++j)
+          for (int i = bx[0]; i <= bx[2]; ++i) {
+            const int64_t idx = off + (int64_t)j * W + i;
+            const double px = i + 0.5, py = j + 0.5;
+            const sd_result r = signed_distance(px, py, P, n);
+            double a, da, ap, dap;
+            coverage(sc, r.sd, &a, &da, &ap, &dap);
+            const double omega = G[idx] * da + Gp[idx] * dap;
+            if (omega == 0.0 || r.d == 0.0) continue;
+            const double sgn = r.inside ? 1.0 : -1.0;
+            const double gx = (px - r.qx) / r.d, gy = (py - r.qy) / r.d;
+            /* dsd/d(vertex) for the two end points of the nearest edge */
+            double wa, wb;
+            if (r.u <= 0.0) {
+              wa = 1.0;
+              wb = 0.0;
+            } else if (r.u >= 1.0) {
+              wa = 0.0;
+              wb = 1.0;
+            } else {
+              wa = 1.0 - r.u;
+              wb = r.u;
+            }
+            const int ma = r.edge, mb = (r.edge + 1 == n) ? 0 : r.edge + 1;
+            const int vm[2] = {ma, mb};
+            const double wv[2] = {wa, wb};
+            for (int e = 0; e < 2; ++e) {
+              if (wv[e] == 0.0) continue;
+              const double dvx = -sgn * wv[e] * gx, dvy = -sgn * wv[e] * gy; /* dsd/dv' */
+              const double lx = sc->verts[2 * (sc->vert_off[q] + vm[e])];
+              const double ly = sc->verts[2 * (sc->vert_off[q] + vm[e]) + 1];
+              /* dv'/dt = k I */
+              g[0] += omega * dvx * k;
+              g[1] += omega * dvy * k;
+              /* dv'/dtheta = k s R'(theta) v,  R' = [[-sin, -cos], [cos, -sin]] */
+              const double rtx = k * s * (-sn * lx - c * ly), rty = k * s * (c * lx - sn * ly);
+              g[2] += omega * (dvx * rtx + dvy * rty);
+              /* dv'/ds = k R(theta) v */
+              const double rsx = k * (c * lx - sn * ly), rsy = k * (sn * lx + c * ly);
+              g[3] += omega * (dvx * rsx + dvy * rsy);
+            }
+          }
+      }
+      for (int e = 0; e < 4; ++e) grad[4 * q + e] = g[e];
+    }
+  }
+  free(S);
+  free(Sp);
+  free(G);
+  free(Gp);
+  release(&pr);
+  return 0;
+}
+
+/*
+ * One Adam step (moment estimates with bias correction, no weight decay) on n parameters with a
+ * per-parameter learning rate.  t is the 1-based step number after this update.
+ */
+int oracle_adam(int n, double *param, const double *grad, double *m, double *v, int t, const double *lr,
+                double beta1, double beta2, double eps) {
+  if (n < 0 || t < 1) return -1;
+  const double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
+  for (int i = 0; i < n; ++i) {
+    m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+    v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+    const double mhat = m[i] / bc1, vhat = v[i] / bc2;
+    param[i] -= lr[i] * mhat / (sqrt(vhat) + eps);
+  }
+  return 0;
+}
+
+/*
+ * Per-parameter learning rates of the collage update: translations move lr_px level pixels per step
+ * (lr_px / k canonical px); rotation and scale move the item's rim (radius rho_i canonical px) by
+ * lr_px level pixels: lr = lr_px / (k * rho_i).
+ */
+int oracle_collage_lr(const oracle_scene *sc, const double *rho, double lr_px, double *lr) {
+  for (int b = 0; b < sc->B; ++b) {
+    const double k = sc->scale[b];
+    for (int i = sc->shape_off[b]; i < sc->shape_off[b + 1]; ++i) {
+      lr[4 * i + 0] = lr_px / k;
+      lr[4 * i + 1] = lr_px / k;
+      lr[4 * i + 2] = rho[i] > 0.0 ? lr_px / (k * rho[i]) : 0.0;
+      lr[4 * i + 3] = rho[i] > 0.0 ? lr_px / (k * rho[i]) : 0.0;
+    }
+  }
+  return 0;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
