@@ -134,6 +134,13 @@ static sd_result signed_distance(double px, double py, const double *P, int n) {
 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
+/* Derivative of the logistic function, sigma'(x) = sigma(x) (1 - sigma(x)), written as
+ * e^-|x| / (1 + e^-|x|)^2 (the same function; no cancellation when sigma(x) is close to 1). */
+static double sigmoid_prime(double x) {
+  const double t = exp(-fabs(x));
+  return t / ((1.0 + t) * (1.0 + t));
+}
+
 /* Coverage of one item at one pixel and its derivative with respect to sd. */
 static void coverage(const oracle_scene *sc, double sd, double *a, double *da, double *ap, double *dap) {
   const double x = sd / sc->tau, xp = (sd + sc->r_pad) / sc->tau;
@@ -142,14 +149,14 @@ static void coverage(const oracle_scene *sc, double sd, double *a, double *da, d
     *da = 0.0;
   } else {
     *a = sigmoid(x);
-    *da = *a * (1.0 - *a) / sc->tau;
+    *da = sigmoid_prime(x) / sc->tau;
   }
   if (sc->use_cutoff && sd + sc->r_pad < -sc->r_cut) {
     *ap = 0.0;
     *dap = 0.0;
   } else {
     *ap = sigmoid(xp);
-    *dap = *ap * (1.0 - *ap) / sc->tau;
+    *dap = sigmoid_prime(xp) / sc->tau;
   }
 }
 

@@ -216,7 +216,12 @@ def jittered_bezier(rng: np.random.Generator, segments: int, radius: float, max_
 
 
 def recentre(P: np.ndarray) -> np.ndarray:
-    _, c = polygon_area_centroid(P)
+    """Moves the area centroid to the origin (the vertex mean for outlines without area)."""
+    if P.shape[0] < 3:
+        return P - P.mean(0)
+    A, c = polygon_area_centroid(P)
+    if not (abs(A) > 1e-12 and np.all(np.isfinite(c))):
+        return P - P.mean(0)
     return P - c
 
 
