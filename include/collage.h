@@ -1,0 +1,180 @@
+/*
+ * collage.h -- C ABI of the MI355X (gfx950) image-space collage hot path.
+ *
+ * The operations are those of "Image-Space Collage and Packing with Differentiable Rendering"
+ * (arXiv 2406.04008):
+ *   - the collage problem of Sec. 2 ("Collage Problem"): items G_i with a translation t_i, a rotation
+ *     r_i and a scale s_i each, arranged in a container C;
+ *   - the per-epoch pipeline of Sec. 3 (Fig. 2): transform every item (eq. 2), rasterize the items
+ *     differentiably into a w x h image, evaluate image-space losses against the container image
+ *     (eq. 3, Sec. 3.2), back-propagate to (t, r, s) and update them (eq. 4);
+ *   - the coarse-to-fine resolution schedule of Sec. 3.3, driven by the caller level by level.
+ *
+ * Conventions shared by every entry point
+ *   - Pixel (i, j), i the column and j the row, has centre (i + 1/2, j + 1/2) in level pixels; y points
+ *     down; images are row-major.  A level has scale k (level px per canonical px).
+ *   - Item parameters are float32 [N,4] rows (t_x, t_y, theta, s): translation in canonical px,
+ *     rotation in radians about the item's local origin, uniform scale.  Transformed vertex:
+ *     v' = k * (R(theta) * (s * v) + t).
+ *   - Coverage of item i at pixel p: alpha = sigmoid(sd / tau) where sd is the Euclidean signed
+ *     distance from p to the item's closed outline (positive inside, even-odd rule), set to 0 once
+ *     sd < -r_cut; padded coverage alpha_pad = sigmoid((sd + r_pad) / tau), 0 once sd + r_pad < -r_cut.
+ *     S = sum_i alpha_i and S_pad = sum_i alpha_pad_i per pixel of a layout.
+ *   - Loss terms per layout, in this order (weighted by the scene's weights):
+ *       [0] overlap  w_overlap * sum_p relu(S - 1)^2
+ *       [1] contain  w_contain * sum_p S (1 - M)
+ *       [2] fill     w_fill    * sum_p M relu(1 - S)^2
+ *       [3] pad      w_pad     * sum_p relu(S_pad - 1)^2
+ *       [4] down     w_down    * sum_p S (H - y_p)
+ *     M is the container mask (1 inside), the complement of the paper's container image I_C.
+ *   - All buffers passed to compute calls are DEVICE memory owned by the caller, float32 unless stated,
+ *     contiguous.  Packed images hold the layouts one after another, layout b starting at pixel
+ *     sum_{c<b} W_c * H_c.  Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream)
+ *     and never synchronize the host.
+ *   - Return value: COLLAGE_OK or a negative code; argument errors are detected on the host before any
+ *     launch, and collage_last_error() then describes the failure (thread-local).
+ *   - Results are deterministic: the same inputs give bitwise the same outputs on the same device.
+ *   - Precision: the nearest edge of every (pixel, item) is found by a float32 scan of the item's
+ *     edges; the signed distance to that edge, the coverage, the loss sums and the gradient terms
+ *     are then evaluated in double precision and returned as float32.
+ */
+#ifndef COLLAGE_H_
+#define COLLAGE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COLLAGE_OK 0
+#define COLLAGE_ERR_INVALID (-1)     /* null pointer, out-of-range value, inconsistent offsets */
+#define COLLAGE_ERR_SIZE (-2)        /* a size or count does not match the scene */
+#define COLLAGE_ERR_WORKSPACE (-3)   /* workspace missing or smaller than collage_workspace_size() */
+#define COLLAGE_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
+#define COLLAGE_ERR_UNSUPPORTED (-5) /* unknown flag or tile size */
+
+/* Scene flags. */
+#define COLLAGE_FLAG_NONE 0u
+#define COLLAGE_FLAG_QUEUE 1u /* batched form: tiles are taken from a device work queue, heaviest first */
+
+typedef struct collage_scene collage_scene; /* opaque host handle */
+
+/*
+ * Description of a batch of B independent layouts (one level of the schedule).  Host arrays are
+ * copied by collage_scene_create; device pointers are borrowed and must stay valid while the scene
+ * is used.
+ */
+typedef struct collage_scene_desc {
+  int32_t num_layouts;          /* B >= 1 */
+  int32_t num_shapes;           /* N >= 0, items of all layouts */
+  int32_t num_verts;            /* V >= 0, outline vertices of all items */
+  const int32_t *layout_width;  /* host [B], canvas width in level px, 1..32768 */
+  const int32_t *layout_height; /* host [B], canvas height in level px, 1..32768 */
+  const float *layout_scale;    /* host [B], k > 0 */
+  const int32_t *layout_shapes; /* host [B+1], item ranges: [0] = 0, nondecreasing, [B] = N */
+  const int32_t *vert_offset;   /* host [N+1], vertex ranges: [0] = 0, nondecreasing, [N] = V;
+                                   at most 32767 vertices per item */
+  const float *verts;           /* device [V,2], closed outlines in the item frame (canonical px),
+                                   edge m joins vertex m and vertex m+1 (the last joins the first) */
+  const float *rho;             /* device [N], rim radius of each item (canonical px); used only by
+                                   the update (rotation and scale learning rates); may be NULL */
+  const float *mask;            /* device, packed [sum W*H] container masks in [0, 1] */
+  float tau;                    /* sigmoid temperature, level px, > 0 */
+  float r_cut;                  /* coverage cut-off, level px, >= 0 */
+  float r_pad;                  /* padding offset, level px, >= 0 */
+  float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
+  int32_t tile;                 /* screen tile edge in px: 8 or 16; 0 = default (16) */
+  int32_t cache_slots;          /* items per tile whose nearest-edge index is kept on chip between
+                                   the coverage and adjoint passes of the fused call; -1 = default */
+  int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
+  uint32_t flags;               /* COLLAGE_FLAG_* */
+} collage_scene_desc;
+
+/* Validates `desc`, copies its host arrays and allocates the scene's small device tables.
+ * On success *out owns them until collage_scene_destroy. */
+int collage_scene_create(const collage_scene_desc *desc, collage_scene **out);
+void collage_scene_destroy(collage_scene *scene);
+
+/* Bytes of device workspace the compute calls need for this scene (256-byte aligned base expected). */
+int collage_workspace_size(const collage_scene *scene, size_t *bytes);
+
+/* Number of pixels over all layouts (length of packed images) and of screen tiles. */
+int collage_scene_info(const collage_scene *scene, int64_t *num_pixels, int64_t *num_tiles);
+
+/*
+ * Forward pass (Sec. 3, eqs. 2-3): coverage sums and the weighted loss terms.
+ *   params  [N,4]        item parameters
+ *   cov     [pixels]     S, written (may be NULL)
+ *   cov_pad [pixels]     S_pad, written (may be NULL)
+ *   loss    [B,5]        weighted loss terms, written
+ */
+int collage_forward(const collage_scene *scene, const float *params, float *cov, float *cov_pad, float *loss,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Backward pass (the gradient used by eq. 4): d(sum_b sum_t dloss[b,t] * loss[b,t]) / d params.
+ * Recomputes the coverage and every pixel's nearest edge from params (no per-pixel, per-item
+ * intermediates are stored between calls, and no image from the forward pass is needed).
+ *   dloss [B,5]  upstream gradient of each loss term
+ *   grad  [N,4]  overwritten
+ */
+int collage_backward(const collage_scene *scene, const float *params, const float *dloss, float *grad,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Forward and backward of the total loss sum_b sum_t loss[b,t] in one pass over the pixels
+ * (dloss = 1).  Outputs as in collage_forward plus grad [N,4] (overwritten).
+ */
+int collage_forward_backward(const collage_scene *scene, const float *params, float *cov, float *cov_pad,
+                             float *loss, float *grad, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Adam update of the parameters (eq. 4 with Adam moments, bias-corrected, no weight decay).
+ * step is a device int32 counter: this call uses t = *step + 1 and stores it back.  Learning rates:
+ * lr_px / k for t_x, t_y (lr_px level px per step); lr_px / (k * rho_i) for theta and s (the item's
+ * rim moves by lr_px level px).  m, v [N,4] are the moment buffers (zero before the first step).
+ */
+int collage_step(const collage_scene *scene, float *params, const float *grad, float *m, float *v, int32_t *step,
+                 float lr_px, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * One optimization epoch of Fig. 2: forward, loss, backward and the Adam update of collage_step,
+ * in three kernel launches with fixed grids (safe to capture in a hipGraph and replay).
+ * cov / cov_pad may be NULL.  loss [B,5] and grad [N,4] receive this epoch's values (before the update).
+ */
+int collage_iterate(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
+                    float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Per-item coverage images for items [first, first + count): alpha and (optionally) alpha_pad,
+ * each image the size of the item's layout canvas, written one after another.
+ */
+int collage_render_shapes(const collage_scene *scene, const float *params, int32_t first, int32_t count, float *alpha,
+                          float *alpha_pad, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * hipGraph of `replays_per_launch` consecutive collage_iterate epochs captured on `stream` (which must
+ * not be the NULL stream).  collage_graph_launch replays it `count` times on `stream`.
+ */
+typedef struct collage_graph collage_graph;
+int collage_graph_create(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss,
+                         float *grad, float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2,
+                         float eps, void *workspace, size_t workspace_bytes, int32_t replays_per_launch, void *stream,
+                         collage_graph **out);
+int collage_graph_launch(collage_graph *graph, int32_t count, void *stream);
+void collage_graph_destroy(collage_graph *graph);
+
+/* Thread-local description of the last non-zero return on this thread. */
+const char *collage_last_error(void);
+
+/* Library version string. */
+const char *collage_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLLAGE_H_ */

@@ -1,0 +1,463 @@
+// Host side of the C ABI declared in include/collage.h: argument validation, workspace planning,
+// kernel dispatch and hipGraph capture.  No compute happens here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "collage.h"
+#include "collage_internal.h"
+
+using namespace collage;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(COLLAGE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct collage_scene {
+  int32_t B = 0, N = 0, V = 0;
+  int32_t tile = kDefaultTile;
+  int32_t cache_slots = kDefaultCacheSlots;
+  int32_t bin_chunk = kDefaultBinChunk;
+  uint32_t flags = 0;
+  std::vector<LayoutRec> layouts;
+  std::vector<int32_t> vert_off;
+  const float *verts = nullptr, *rho = nullptr, *mask = nullptr;
+  float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
+  float w[5] = {1, 1, 1, 0, 0};
+  int64_t total_pixels = 0, total_tiles = 0, list_total = 0;
+  int32_t max_canvas = 0;
+  // device tables owned by the scene
+  LayoutRec *d_layouts = nullptr;
+  int32_t *d_vert_off = nullptr;
+  // workspace layout
+  size_t off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0, off_list = 0,
+         off_partial = 0;
+  size_t ws_bytes = 0;
+};
+
+struct collage_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int validate_desc(const collage_scene_desc *d) {
+  if (!d) return fail(COLLAGE_ERR_INVALID, "desc is NULL");
+  if (d->num_layouts < 1) return fail(COLLAGE_ERR_INVALID, "num_layouts must be >= 1 (got %d)", d->num_layouts);
+  if (d->num_shapes < 0 || d->num_verts < 0) return fail(COLLAGE_ERR_INVALID, "negative num_shapes or num_verts");
+  if (!d->layout_width || !d->layout_height || !d->layout_scale || !d->layout_shapes || !d->vert_offset)
+    return fail(COLLAGE_ERR_INVALID, "a host layout or offset array is NULL");
+  for (int b = 0; b < d->num_layouts; ++b) {
+    if (d->layout_width[b] < 1 || d->layout_width[b] > 32768 || d->layout_height[b] < 1 ||
+        d->layout_height[b] > 32768)
+      return fail(COLLAGE_ERR_INVALID, "layout %d: canvas %dx%d outside 1..32768", b, d->layout_width[b],
+                  d->layout_height[b]);
+    if (!(d->layout_scale[b] > 0.0f) || !std::isfinite(d->layout_scale[b]))
+      return fail(COLLAGE_ERR_INVALID, "layout %d: scale must be finite and > 0", b);
+  }
+  if (d->layout_shapes[0] != 0) return fail(COLLAGE_ERR_INVALID, "layout_shapes[0] must be 0");
+  for (int b = 0; b < d->num_layouts; ++b)
+    if (d->layout_shapes[b + 1] < d->layout_shapes[b])
+      return fail(COLLAGE_ERR_INVALID, "layout_shapes must be nondecreasing (at %d)", b);
+  if (d->layout_shapes[d->num_layouts] != d->num_shapes)
+    return fail(COLLAGE_ERR_SIZE, "layout_shapes[B] = %d but num_shapes = %d", d->layout_shapes[d->num_layouts],
+                d->num_shapes);
+  if (d->vert_offset[0] != 0) return fail(COLLAGE_ERR_INVALID, "vert_offset[0] must be 0");
+  for (int i = 0; i < d->num_shapes; ++i) {
+    const int n = d->vert_offset[i + 1] - d->vert_offset[i];
+    if (n < 0) return fail(COLLAGE_ERR_INVALID, "vert_offset must be nondecreasing (at item %d)", i);
+    if (n > kMaxVertsPerItem) return fail(COLLAGE_ERR_INVALID, "item %d has %d vertices (max %d)", i, n, kMaxVertsPerItem);
+  }
+  if (d->vert_offset[d->num_shapes] != d->num_verts)
+    return fail(COLLAGE_ERR_SIZE, "vert_offset[N] = %d but num_verts = %d", d->vert_offset[d->num_shapes], d->num_verts);
+  if (d->num_verts > 0 && !d->verts) return fail(COLLAGE_ERR_INVALID, "verts is NULL");
+  if (!d->mask) return fail(COLLAGE_ERR_INVALID, "mask is NULL");
+  if (!(d->tau > 0.0f) || !std::isfinite(d->tau)) return fail(COLLAGE_ERR_INVALID, "tau must be finite and > 0");
+  if (!(d->r_cut >= 0.0f) || !std::isfinite(d->r_cut)) return fail(COLLAGE_ERR_INVALID, "r_cut must be finite and >= 0");
+  if (!(d->r_pad >= 0.0f) || !std::isfinite(d->r_pad)) return fail(COLLAGE_ERR_INVALID, "r_pad must be finite and >= 0");
+  const float ws[5] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down};
+  for (float x : ws)
+    if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
+  if (d->tile != 0 && d->tile != 8 && d->tile != 16)
+    return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8 or 16 (got %d)", d->tile);
+  if (d->cache_slots < -1 || d->cache_slots > kMaxCacheSlots)
+    return fail(COLLAGE_ERR_INVALID, "cache_slots must be -1 or 0..%d", kMaxCacheSlots);
+  if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)
+    return fail(COLLAGE_ERR_INVALID, "bin_chunk must be 0..%d", kMaxBinChunk);
+  if (d->flags & ~COLLAGE_FLAG_QUEUE) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  return COLLAGE_OK;
+}
+
+KArgs base_args(const collage_scene *s, void *ws) {
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  char *w = static_cast<char *>(ws);
+  a.layouts = s->d_layouts;
+  a.num_layouts = s->B;
+  a.num_shapes = s->N;
+  a.total_tiles = (int32_t)s->total_tiles;
+  a.tile = s->tile;
+  a.cache_slots = s->cache_slots;
+  a.bin_chunk = s->bin_chunk;
+  a.vert_off = s->d_vert_off;
+  a.verts = s->verts;
+  a.rho = s->rho;
+  a.mask = s->mask;
+  a.shapes = reinterpret_cast<ShapeRec *>(w + s->off_shapes);
+  a.bbox = reinterpret_cast<int4 *>(w + s->off_bbox);
+  a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
+  a.edges_d = reinterpret_cast<EdgeD *>(w + s->off_edges_d);
+  a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
+  a.tile_loss = reinterpret_cast<double *>(w + s->off_loss);
+  a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
+  a.tile_partial = reinterpret_cast<double4 *>(w + s->off_partial);
+  a.tau = s->tau;
+  a.inv_tau = 1.0f / s->tau;
+  a.r_cut = s->r_cut;
+  a.r_pad = s->r_pad;
+  for (int i = 0; i < 5; ++i) a.w[i] = s->w[i];
+  return a;
+}
+
+int check_ws(const collage_scene *s, void *ws, size_t bytes) {
+  if (!ws) return fail(COLLAGE_ERR_WORKSPACE, "workspace is NULL");
+  if (bytes < s->ws_bytes)
+    return fail(COLLAGE_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", bytes, s->ws_bytes);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(COLLAGE_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return COLLAGE_OK;
+}
+
+int check_adam(float lr, float b1, float b2, float eps) {
+  if (!std::isfinite(lr) || lr < 0.0f) return fail(COLLAGE_ERR_INVALID, "lr_px must be finite and >= 0");
+  if (!(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f)) return fail(COLLAGE_ERR_INVALID, "betas must be in [0, 1)");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(COLLAGE_ERR_INVALID, "eps must be finite and > 0");
+  return COLLAGE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *collage_last_error(void) { return g_err; }
+
+const char *collage_version(void) { return "collage-mi355x 0.1 (gfx950)"; }
+
+int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
+  if (!out) return fail(COLLAGE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  collage_scene *s = new (std::nothrow) collage_scene();
+  if (!s) return fail(COLLAGE_ERR_INVALID, "out of host memory");
+  s->B = desc->num_layouts;
+  s->N = desc->num_shapes;
+  s->V = desc->num_verts;
+  s->tile = desc->tile == 0 ? kDefaultTile : desc->tile;
+  s->cache_slots = desc->cache_slots < 0 ? kDefaultCacheSlots : desc->cache_slots;
+  s->bin_chunk = desc->bin_chunk == 0 ? kDefaultBinChunk : desc->bin_chunk;
+  s->flags = desc->flags;
+  s->verts = desc->verts;
+  s->rho = desc->rho;
+  s->mask = desc->mask;
+  s->tau = desc->tau;
+  s->r_cut = desc->r_cut;
+  s->r_pad = desc->r_pad;
+  s->w[0] = desc->w_overlap;
+  s->w[1] = desc->w_contain;
+  s->w[2] = desc->w_fill;
+  s->w[3] = desc->w_pad;
+  s->w[4] = desc->w_down;
+  s->vert_off.assign(desc->vert_offset, desc->vert_offset + s->N + 1);
+  s->layouts.resize(s->B);
+  int64_t pix = 0, tiles = 0, list = 0;
+  for (int b = 0; b < s->B; ++b) {
+    LayoutRec &L = s->layouts[b];
+    std::memset(&L, 0, sizeof(L));
+    L.W = desc->layout_width[b];
+    L.H = desc->layout_height[b];
+    L.ntx = (L.W + s->tile - 1) / s->tile;
+    L.nty = (L.H + s->tile - 1) / s->tile;
+    L.tile_off = (int32_t)tiles;
+    L.shape_begin = desc->layout_shapes[b];
+    L.shape_end = desc->layout_shapes[b + 1];
+    L.pix_off = pix;
+    L.list_off = list;
+    L.k = desc->layout_scale[b];
+    pix += (int64_t)L.W * L.H;
+    tiles += (int64_t)L.ntx * L.nty;
+    list += (int64_t)L.ntx * L.nty * (L.shape_end - L.shape_begin);
+    if (L.W * L.H > s->max_canvas) s->max_canvas = L.W * L.H;
+  }
+  if (tiles > (int64_t)0x7fffffff) {
+    delete s;
+    return fail(COLLAGE_ERR_INVALID, "too many screen tiles");
+  }
+  s->total_pixels = pix;
+  s->total_tiles = tiles;
+  s->list_total = list;
+  size_t off = 0;
+  s->off_shapes = off;
+  off = align256(off + sizeof(ShapeRec) * (size_t)s->N);
+  s->off_bbox = off;
+  off = align256(off + sizeof(int4) * (size_t)s->N);
+  s->off_edges = off;
+  off = align256(off + sizeof(EdgeRec) * (size_t)s->V);
+  s->off_edges_d = off;
+  off = align256(off + sizeof(EdgeD) * (size_t)s->V);
+  s->off_count = off;
+  off = align256(off + sizeof(int32_t) * (size_t)tiles);
+  s->off_loss = off;
+  off = align256(off + sizeof(double) * 5 * (size_t)tiles);
+  s->off_list = off;
+  off = align256(off + sizeof(int32_t) * (size_t)list);
+  s->off_partial = off;
+  off = align256(off + sizeof(double4) * (size_t)list);
+  s->ws_bytes = off + 256;
+
+  hipError_t e = hipMalloc(&s->d_layouts, sizeof(LayoutRec) * s->B);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipMalloc(layouts)");
+  }
+  e = hipMalloc(&s->d_vert_off, sizeof(int32_t) * (s->N + 1));
+  if (e == hipSuccess) e = hipMemcpy(s->d_layouts, s->layouts.data(), sizeof(LayoutRec) * s->B, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->d_vert_off, s->vert_off.data(), sizeof(int32_t) * (s->N + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    collage_scene_destroy(s);
+    return hip_fail(e, "scene device tables");
+  }
+  *out = s;
+  return COLLAGE_OK;
+}
+
+void collage_scene_destroy(collage_scene *s) {
+  if (!s) return;
+  if (s->d_layouts) (void)hipFree(s->d_layouts);
+  if (s->d_vert_off) (void)hipFree(s->d_vert_off);
+  delete s;
+}
+
+int collage_workspace_size(const collage_scene *s, size_t *bytes) {
+  if (!s || !bytes) return fail(COLLAGE_ERR_INVALID, "scene or bytes is NULL");
+  *bytes = s->ws_bytes;
+  return COLLAGE_OK;
+}
+
+int collage_scene_info(const collage_scene *s, int64_t *num_pixels, int64_t *num_tiles) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (num_pixels) *num_pixels = s->total_pixels;
+  if (num_tiles) *num_tiles = s->total_tiles;
+  return COLLAGE_OK;
+}
+
+int collage_forward(const collage_scene *s, const float *params, float *cov, float *cov_pad, float *loss, void *ws,
+                    size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if ((!params && s->N > 0) || !loss) return fail(COLLAGE_ERR_INVALID, "params or loss is NULL");
+  int rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  a.cov_out = cov;
+  a.cov_pad_out = cov_pad;
+  a.loss_out = loss;
+  a.write_loss = 1;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_tiles(a, false, st);
+  if (e == hipSuccess) e = launch_finalize(a, false, true, false, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_forward launch");
+}
+
+int collage_backward(const collage_scene *s, const float *params, const float *dloss, float *grad, void *ws,
+                     size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!dloss) return fail(COLLAGE_ERR_INVALID, "dloss is NULL");
+  if (s->N > 0 && (!params || !grad)) return fail(COLLAGE_ERR_INVALID, "params or grad is NULL");
+  int rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  if (s->N == 0) return COLLAGE_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  a.dloss = dloss;
+  a.grad_out = grad;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_finalize(a, true, false, false, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward launch");
+}
+
+int collage_forward_backward(const collage_scene *s, const float *params, float *cov, float *cov_pad, float *loss,
+                             float *grad, void *ws, size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!loss || (s->N > 0 && (!params || !grad))) return fail(COLLAGE_ERR_INVALID, "params, loss or grad is NULL");
+  int rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  a.cov_out = cov;
+  a.cov_pad_out = cov_pad;
+  a.loss_out = loss;
+  a.grad_out = grad;
+  a.write_loss = 1;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_finalize(a, true, true, false, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_forward_backward launch");
+}
+
+int collage_step(const collage_scene *s, float *params, const float *grad, float *m, float *v, int32_t *step,
+                 float lr_px, float beta1, float beta2, float eps, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!step || (s->N > 0 && (!params || !grad || !m || !v))) return fail(COLLAGE_ERR_INVALID, "a step buffer is NULL");
+  if (s->N > 0 && !s->rho) return fail(COLLAGE_ERR_INVALID, "the scene has no rho (needed by the update)");
+  int rc = check_adam(lr_px, beta1, beta2, eps);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, nullptr);
+  a.grad_out = const_cast<float *>(grad);
+  a.param_io = params;
+  a.adam_m = m;
+  a.adam_v = v;
+  a.step = step;
+  a.lr_px = lr_px;
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  hipError_t e = launch_adam_only(a, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_step launch");
+}
+
+int collage_iterate(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
+                    float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
+                    size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!loss || !step || (s->N > 0 && (!params || !grad || !m || !v)))
+    return fail(COLLAGE_ERR_INVALID, "an iterate buffer is NULL");
+  if (s->N > 0 && !s->rho) return fail(COLLAGE_ERR_INVALID, "the scene has no rho (needed by the update)");
+  int rc = check_adam(lr_px, beta1, beta2, eps);
+  if (rc) return rc;
+  rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  a.cov_out = cov;
+  a.cov_pad_out = cov_pad;
+  a.loss_out = loss;
+  a.grad_out = grad;
+  a.param_io = params;
+  a.adam_m = m;
+  a.adam_v = v;
+  a.step = step;
+  a.step_inc = step;
+  a.lr_px = lr_px;
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  a.write_loss = 1;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_finalize(a, true, true, true, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_iterate launch");
+}
+
+int collage_render_shapes(const collage_scene *s, const float *params, int32_t first, int32_t count, float *alpha,
+                          float *alpha_pad, void *ws, size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (first < 0 || count < 0 || first + count > s->N)
+    return fail(COLLAGE_ERR_SIZE, "items [%d, %d) outside [0, %d)", first, first + count, s->N);
+  if (count > 65535) return fail(COLLAGE_ERR_SIZE, "at most 65535 items per render call");
+  if (count > 0 && (!params || !alpha)) return fail(COLLAGE_ERR_INVALID, "params or alpha is NULL");
+  int rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  if (count == 0) return COLLAGE_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_render(a, first, count, nullptr, alpha, alpha_pad, s->max_canvas, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_render_shapes launch");
+}
+
+int collage_graph_create(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
+                         float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
+                         size_t ws_bytes, int32_t replays_per_launch, void *stream, collage_graph **out) {
+  if (!out) return fail(COLLAGE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!stream) return fail(COLLAGE_ERR_INVALID, "graph capture needs a non-NULL stream");
+  if (replays_per_launch < 1 || replays_per_launch > 4096)
+    return fail(COLLAGE_ERR_INVALID, "replays_per_launch must be 1..4096");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  int rc = COLLAGE_OK;
+  for (int i = 0; i < replays_per_launch && rc == COLLAGE_OK; ++i)
+    rc = collage_iterate(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  if (rc != COLLAGE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  collage_graph *cg = new (std::nothrow) collage_graph();
+  if (!cg) {
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    return fail(COLLAGE_ERR_INVALID, "out of host memory");
+  }
+  cg->graph = g;
+  cg->exec = ex;
+  *out = cg;
+  return COLLAGE_OK;
+}
+
+int collage_graph_launch(collage_graph *g, int32_t count, void *stream) {
+  if (!g || count < 0) return fail(COLLAGE_ERR_INVALID, "graph is NULL or count < 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < count; ++i) {
+    hipError_t e = hipGraphLaunch(g->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  return COLLAGE_OK;
+}
+
+void collage_graph_destroy(collage_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+}  // extern "C"

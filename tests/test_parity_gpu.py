@@ -1,0 +1,275 @@
+"""GPU (HIP, through the C ABI) vs the FP64 oracle, element by element, on seeded scenes.
+
+Every case prints its name before touching the GPU so that a failing run names it.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle
+from paper_2406_04008_amd import scenes as S
+from paper_2406_04008_amd.collage import CollageLoss, CollageScene
+from tests.parity_util import check_grad, check_image, check_loss, grad_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+SCENES = {
+    "config1": lambda: S.config1(0),
+    "ragged": lambda: S.random_scene(3, [(37, 29), (50, 61), (16, 16), (23, 9)], [4, 9, 1, 0], off_canvas=0.3),
+    "config2": lambda: S.config2(0),
+}
+
+
+@pytest.fixture(scope="module")
+def oracles():
+    cache = {}
+
+    def get(name, level=None):
+        key = (name, level)
+        if key not in cache:
+            sc = SCENES[name]() if name in SCENES else None
+            cache[key] = (sc, Oracle(sc, level=level))
+        return cache[key]
+
+    return get
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("name", list(SCENES))
+def test_forward_parity(name, tile, oracles):
+    sc, o = oracles(name)
+    _say("forward", name, "tile", tile)
+    cs = CollageScene(sc, tile=tile)
+    cov, cov_pad, loss = cs.forward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_image(_np(cov_pad), Sp, "S_pad")
+    check_loss(_np(loss), L)
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("name", list(SCENES))
+def test_backward_parity_autograd(name, tile, oracles):
+    sc, o = oracles(name)
+    _say("backward", name, "tile", tile)
+    cs = CollageScene(sc, tile=tile)
+    p = cs.params_tensor().requires_grad_(True)
+    rng = np.random.default_rng(1)
+    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 5))
+    loss = CollageLoss.apply(p, cs)
+    (loss * torch.tensor(dl, dtype=torch.float32, device=loss.device)).sum().backward()
+    g_ref = o.backward(sc.params, dloss=dl)
+    check_grad(_np(p.grad), g_ref)
+
+
+@pytest.mark.parametrize("cache_slots,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
+@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("name", list(SCENES))
+def test_fused_parity(name, tile, cache_slots, bin_chunk, oracles):
+    sc, o = oracles(name)
+    _say("fused", name, "tile", tile, "cache", cache_slots, "chunk", bin_chunk)
+    cs = CollageScene(sc, tile=tile, cache_slots=cache_slots, bin_chunk=bin_chunk)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_image(_np(cov_pad), Sp, "S_pad")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+
+
+@pytest.mark.parametrize("level", [128, 256, 512, 1024])
+def test_metric_scene_levels(level):
+    """500 Bezier items, the coarse-to-fine levels of the metric scene; 512 is the benchmark launch."""
+    sc = S.config3(0)
+    _say("config3 level", level)
+    o = Oracle(sc, level=level)
+    cs = CollageScene(sc, level=level)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_image(_np(cov_pad), Sp, "S_pad")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+
+
+def test_render_parity(oracles):
+    for name in ("config1", "ragged"):
+        sc, o = oracles(name)
+        _say("render", name)
+        cs = CollageScene(sc)
+        A, Ap = cs.render(cs.params_tensor())
+        Ar, Apr = o.render(sc.params)
+        check_image(_np(A), Ar, "alpha")
+        check_image(_np(Ap), Apr, "alpha_pad")
+
+
+def test_adam_step_matches_torch():
+    sc = S.config1(0)
+    _say("adam")
+    cs = CollageScene(sc)
+    p = cs.params_tensor()
+    _, _, _, g = cs.forward_backward(p)
+    m, v, step = cs.new_state()
+    p_lib = p.clone()
+    cs.step(p_lib, g, m, v, step)
+    cs.step(p_lib, g, m, v, step)
+    # torch.optim.Adam with the same per-parameter learning rates (one group per item and component)
+    k = 1.0
+    lr = np.zeros((sc.num_shapes, 4))
+    lr[:, :2] = sc.lr_px / k
+    lr[:, 2:] = sc.lr_px / (k * sc.rho.astype(np.float64))[:, None]
+    ts = [p[i, c].clone().requires_grad_(True) for i in range(sc.num_shapes) for c in range(4)]
+    opt = torch.optim.Adam([{"params": [t], "lr": float(lr.reshape(-1)[j])} for j, t in enumerate(ts)],
+                           betas=(0.9, 0.999), eps=1e-8)
+    gf = g.reshape(-1)
+    for _ in range(2):
+        for j, t in enumerate(ts):
+            t.grad = gf[j].clone()
+        opt.step()
+    pt = torch.stack([t.detach() for t in ts]).reshape(-1, 4)
+    assert int(step.item()) == 2
+    np.testing.assert_allclose(_np(p_lib), _np(pt), rtol=1e-6, atol=1e-6)
+
+
+def test_iterate_equals_fused_then_step():
+    sc = S.random_scene(4, [(40, 33), (29, 45)], [5, 6])
+    _say("iterate")
+    cs = CollageScene(sc)
+    p0 = cs.params_tensor()
+    p1 = p0.clone()
+    m1, v1, s1 = cs.new_state()
+    m2, v2, s2 = cs.new_state()
+    p2 = p0.clone()
+    for _ in range(3):
+        loss1, g1 = cs.iterate(p1, m1, v1, s1)
+        _, _, loss2, g2 = cs.forward_backward(p2)
+        cs.step(p2, g2, m2, v2, s2)
+        assert torch.equal(loss1, loss2) and torch.equal(g1, g2)
+    assert torch.equal(p1, p2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    assert int(s1.item()) == 3 and int(s2.item()) == 3
+
+
+def test_graph_replay_matches_eager():
+    sc = S.config1(0)
+    _say("graph")
+    cs = CollageScene(sc)
+    p_g = cs.params_tensor()
+    m_g, v_g, s_g = cs.new_state()
+    loss_g = torch.empty(1, 5, device="cuda")
+    grad_g = torch.empty(sc.num_shapes, 4, device="cuda")
+    g = cs.graph(p_g, m_g, v_g, s_g, loss_g, grad_g, replays_per_launch=2)
+    p_e = cs.params_tensor()
+    m_e, v_e, s_e = cs.new_state()
+    for rep in range(4):
+        g.launch(1)
+        g.stream.synchronize()
+        for _ in range(2):
+            loss_e, grad_e = cs.iterate(p_e, m_e, v_e, s_e)
+        torch.cuda.synchronize()
+        assert torch.equal(p_g, p_e), rep
+        assert torch.equal(loss_g, loss_e) and torch.equal(grad_g, grad_e), rep
+        assert int(s_g.item()) == int(s_e.item()) == 2 * (rep + 1)
+
+
+def test_bitwise_deterministic():
+    sc = S.config2(0)
+    _say("determinism")
+    cs = CollageScene(sc)
+    p = cs.params_tensor()
+    a = cs.forward_backward(p)
+    b = cs.forward_backward(p)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_gradient_vs_central_differences_config2():
+    sc = S.config2(0)
+    _say("fd config2")
+    cs = CollageScene(sc)
+    p = cs.params_tensor().requires_grad_(True)
+    CollageLoss.apply(p, cs).sum().backward()
+    o = Oracle(sc)
+    items = [0, 17, 42, 63, 99]
+    fd = o.fd_gradient(sc.params, shapes=items)
+    g = _np(p.grad)
+    full = o.backward(sc.params)
+    floor = 0.01 * np.abs(full).max(0)
+    for c in range(4):
+        err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
+        assert err.max() <= 1e-4, (c, err)
+
+
+def test_edge_cases():
+    _say("edge cases")
+    # items with 1 and 2 vertices, one huge item covering the canvas, one far off canvas
+    outlines = [np.array([[0.0, 0.0]]), np.array([[-3.0, 0.0], [3.0, 0.5]]), S.regular_polygon(12, 4.0),
+                S.star_polygon(5, 6.0, 0.5)]
+    params = np.array([[10.3, 11.7, 0.2, 1.0], [20.1, 9.3, 0.4, 1.0], [15.2, 14.9, 0.3, 9.0],
+                       [-80.0, 10.0, 0.0, 1.0]])
+    sc = S.multi_shape_scene(outlines, params, 33, 27, mask="disk", w_overlap=1, w_contain=1, w_fill=1,
+                             w_pad=1, r_pad=2.0, w_down=1e-3)
+    sc.rho[:2] = 1.0
+    o = Oracle(sc)
+    for tile in (8, 16):
+        cs = CollageScene(sc, tile=tile)
+        cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+        S_, Sp, L = o.forward(sc.params)
+        check_image(_np(cov), S_, "S")
+        check_loss(_np(loss), L)
+        check_grad(_np(grad), o.backward(sc.params))
+    # an empty scene: only the fill term of the container remains
+    empty = S.random_scene(1, [(19, 23)], [0])
+    cs = CollageScene(empty)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    assert float(cov.abs().max()) == 0.0
+    check_loss(_np(loss), Oracle(empty).forward(empty.params)[2])
+    # non-finite parameters: the item is skipped and its gradient is NaN
+    sc2 = S.config1(0)
+    p = sc2.params.copy()
+    p[3, 0] = np.nan
+    cs = CollageScene(sc2)
+    _, _, loss, grad = cs.forward_backward(cs.params_tensor(p))
+    g = _np(grad)
+    assert np.all(np.isnan(g[3])) and np.all(np.isfinite(np.delete(g, 3, 0)))
+    assert np.all(np.isfinite(_np(loss)))
+
+
+def test_batched_layouts_match_separate_scenes():
+    sc = S.config4(0, num_layouts=12)
+    _say("batched vs separate", sc.num_shapes)
+    cs = CollageScene(sc)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    o = Oracle(sc)
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+    # each layout on its own gives bitwise the same per-layout results
+    imgs = cs.layout_images(cov)
+    for b in (0, 5, 11):
+        lay = sc.layouts[b]
+        sub = S.Scene(name="one", verts=sc.verts[sc.vert_off[lay.shape_begin]:sc.vert_off[lay.shape_end]],
+                      vert_off=sc.vert_off[lay.shape_begin:lay.shape_end + 1] - sc.vert_off[lay.shape_begin],
+                      rho=sc.rho[lay.shape_begin:lay.shape_end], params=sc.params[lay.shape_begin:lay.shape_end],
+                      layouts=[S.Layout(lay.width_ref, lay.height_ref, 0, lay.num_shapes, lay.ellipses)],
+                      levels=[1], level_ref=1, tau=sc.tau, r_cut=sc.r_cut, r_pad=sc.r_pad,
+                      w_overlap=sc.w_overlap, w_contain=sc.w_contain, w_fill=sc.w_fill, w_pad=sc.w_pad,
+                      w_down=sc.w_down)
+        cs1 = CollageScene(sub)
+        c1, _, l1, g1 = cs1.forward_backward(cs1.params_tensor())
+        assert torch.equal(c1, imgs[b].reshape(-1))
+        assert torch.equal(l1[0], loss[b])
+        assert torch.equal(g1, grad[lay.shape_begin:lay.shape_end])
