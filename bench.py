@@ -1,0 +1,212 @@
+"""Benchmark of the collage hot path on one MI355X.
+
+Workload: the 512 x 512 level of the coarse-to-fine schedule of the 500-item scene (closed cubic
+Bezier outlines of 4..16 segments flattened at 8 points per segment, a container made of 10 ellipses,
+padding 2 px, downward force weight 1e-3), seed 0.  One step = one optimization epoch: transform,
+coverage, the five loss terms, the adjoint and the Adam update (collage_iterate), with all inputs
+resident in HBM.  The timed region is `steps` consecutive epochs launched on one stream; each records
+a pair of HIP events around its tile kernel (the dominant kernel), which gives the kernel's average
+duration over the timed region.  The same number of epochs is then replayed from one captured
+hipGraph and reported as graph_it_per_s.
+
+Prints one JSON line.  `value` is epochs per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd collage iterations/sec and pixel·edge evals/s at 512², 500 shapes"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 vector lane-operations per second
+# (float32 without packed instructions; an FMA counts as one operation)
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# algorithmic lane-operations per (pixel, edge) of one nearest-edge scan with index tracking:
+# distance 11 (2 sub, mul+fma, mul, clamp, 2 fma, mul+fma, min), crossing 6, argmin tracking 3
+OPS_PER_PAIR = 20
+
+
+def support_pairs(scene, params, level):
+    """Algorithmic (pixel, edge) pairs of one scan: for every item, the pixels whose centres lie in its
+    vertex bounding box widened by r_cut + r_pad (clipped to the canvas), times its edge count."""
+    w, h, k, off = scene.layout_arrays(level)
+    ext = scene.r_cut + max(scene.r_pad, 0.0)
+    V = scene.verts.astype(np.float64)
+    total = 0
+    for b in range(scene.num_layouts):
+        for i in range(int(off[b]), int(off[b + 1])):
+            v0, v1 = int(scene.vert_off[i]), int(scene.vert_off[i + 1])
+            tx, ty, th, s = (float(x) for x in params[i])
+            c, sn = math.cos(th), math.sin(th)
+            x = float(k[b]) * (s * (c * V[v0:v1, 0] - sn * V[v0:v1, 1]) + tx)
+            y = float(k[b]) * (s * (sn * V[v0:v1, 0] + c * V[v0:v1, 1]) + ty)
+            i0 = max(math.ceil(x.min() - ext - 0.5), 0)
+            i1 = min(math.floor(x.max() + ext - 0.5), int(w[b]) - 1)
+            j0 = max(math.ceil(y.min() - ext - 0.5), 0)
+            j1 = min(math.floor(y.max() + ext - 0.5), int(h[b]) - 1)
+            if i1 >= i0 and j1 >= j0:
+                total += (i1 - i0 + 1) * (j1 - j0 + 1) * (v1 - v0)
+    return total
+
+
+def cpu_baseline(scene, level, budget_s=12.0, max_iters=30):
+    """The FP64 oracle (forward, backward, Adam) on the same scene, timed on this host's cores."""
+    from oracle import oracle as orc
+
+    o = orc.Oracle(scene, level=level)
+    p = scene.params.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    lr = o.learning_rates()
+
+    def one(t, p, m, v):
+        o.forward(p)
+        g = o.backward(p)
+        return o.adam(p, g, m, v, t, lr)
+
+    t0 = time.perf_counter()
+    p, m, v = one(1, p, m, v)  # warm-up
+    first = time.perf_counter() - t0
+    n = int(max(2, min(max_iters, budget_s / max(first, 1e-3))))
+    t0 = time.perf_counter()
+    for t in range(2, n + 2):
+        p, m, v = one(t, p, m, v)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "it/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{n} oracle epochs (forward, backward, Adam; FP64) of the same 512x512 / 500-item "
+                      f"scene from the seed-0 layout, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--level", type=int, default=512)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--code-capacity", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    if not (1 <= args.steps <= 4096 and 0 <= args.warmup <= 4096):
+        print("--steps must be 1..4096 and --warmup 0..4096 (one captured graph each)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_04008_amd import scenes
+    from paper_2406_04008_amd.collage import CollageScene, Timer
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    sc = scenes.config3(0)
+    cs = CollageScene(sc, level=args.level, tile=args.tile, code_capacity=args.code_capacity)
+    params = cs.params_tensor()
+    m, v, step = cs.new_state()
+    loss = torch.empty(cs.B, 5, device="cuda")
+    grad = torch.empty(cs.N, 4, device="cuda")
+    stream = torch.cuda.Stream()
+    timer = Timer(args.steps)
+    p0 = params.clone()
+
+    def reset():
+        params.copy_(p0)
+        m.zero_()
+        v.zero_()
+        step.zero_()
+        torch.cuda.synchronize()
+
+    # warm-up epochs, then back to the seed-0 layout: every timed region runs the first `steps` epochs
+    # of the 512 x 512 level from the same layout (the items move, shrink and grow as they are optimized)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            cs.iterate(params, m, v, step, loss=loss, grad=grad)
+    reset()
+    p_start = params.detach().cpu().numpy().copy()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        cs.iterate_timed(params, m, v, step, loss, grad, timer, i, stream=stream)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    region_ms = ev0.elapsed_time(ev1)
+    p_end = params.detach().cpu().numpy().copy()
+    tiles_ms = timer.elapsed_ms()
+    assert np.all(np.isfinite(p_end)), "non-finite parameters after the timed region"
+    # the same epochs from the same start, replayed from one captured hipGraph, for reference
+    g = cs.graph(params, m, v, step, loss, grad, replays_per_launch=args.steps, stream=stream)
+    reset()
+    eg0 = torch.cuda.Event(enable_timing=True)
+    eg1 = torch.cuda.Event(enable_timing=True)
+    eg0.record(stream)
+    g.launch(1)
+    eg1.record(stream)
+    stream.synchronize()
+    graph_ms = eg0.elapsed_time(eg1)
+    graph_same = bool(torch.equal(params, torch.from_numpy(p_end).to(params.device)))
+
+    secs = region_ms / 1e3
+    its = args.steps / secs
+    pairs = 0.5 * (support_pairs(sc, p_start, args.level) + support_pairs(sc, p_end, args.level))
+    tile_ms = float(np.mean(tiles_ms))
+    achieved = OPS_PER_PAIR * pairs / (tile_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": its,
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": region_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "dtype_note": "float32 edge scan; float64 per-(pixel, item) distance, coverage, loss and adjoint",
+        "data": "synthetic",
+        "config": {"workload": "512x512 level of the 128-256-512-1024 schedule; 500 closed cubic-Bezier items "
+                               "(4-16 segments, 8 points each), 10-ellipse container, padding 2 px, "
+                               "downward force 1e-3, seed 0", "tile": args.tile},
+        "pixel_edge_evals_per_s": 2.0 * pairs * its,
+        "pixel_edge_pairs_per_scan": pairs,
+        "wall_s": wall,
+        "graph_it_per_s": args.steps / (graph_ms / 1e3),
+        "graph_matches_eager": graph_same,
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"k_tiles<{args.tile},adjoint> (coverage, loss and adjoint)",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "TOP/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": None,
+            "ops_per_pair": OPS_PER_PAIR,
+            "kernel_ms_mean": tile_ms,
+            "kernel_ms_median": float(np.median(tiles_ms)),
+            "kernel_share_of_step": tile_ms / (region_ms / args.steps),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.level)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,8 +86,9 @@ typedef struct collage_scene_desc {
   float r_pad;                  /* padding offset, level px, >= 0 */
   float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
   int32_t tile;                 /* screen tile edge in px: 8 or 16; 0 = default (16) */
-  int32_t cache_slots;          /* items per tile whose nearest-edge index is kept on chip between
-                                   the coverage and adjoint passes of the fused call; -1 = default */
+  int32_t code_capacity;        /* (tile, item) work units whose nearest-edge codes (2 bytes per pixel)
+                                   are kept between the coverage and adjoint passes; units beyond it
+                                   are rescanned; -1 = default (max(65536, 16 * tiles)) */
   int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
   uint32_t flags;               /* COLLAGE_FLAG_* */
 } collage_scene_desc;
@@ -156,14 +157,31 @@ int collage_render_shapes(const collage_scene *scene, const float *params, int32
                           float *alpha_pad, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Event timer: `count` pairs of HIP events (timing enabled).  collage_iterate_timed records one pair
+ * around its tile kernel (coverage, loss and adjoint).  collage_timer_elapsed waits for the events and
+ * writes the `count` durations in milliseconds.
+ */
+typedef struct collage_timer collage_timer;
+int collage_timer_create(int32_t count, collage_timer **out);
+int collage_timer_elapsed(collage_timer *timer, float *ms);
+void collage_timer_destroy(collage_timer *timer);
+
+/* collage_iterate, recording event pair `index` of `timer` around the tile kernel on `stream`. */
+int collage_iterate_timed(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss,
+                          float *grad, float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2,
+                          float eps, void *workspace, size_t workspace_bytes, collage_timer *timer, int32_t index,
+                          void *stream);
+
+/*
  * hipGraph of `replays_per_launch` consecutive collage_iterate epochs captured on `stream` (which must
- * not be the NULL stream).  collage_graph_launch replays it `count` times on `stream`.
+ * not be the NULL stream).  collage_graph_launch replays it `count` times on `stream`.  `timer` must be
+ * NULL (events recorded inside a captured graph cannot be timed on this platform).
  */
 typedef struct collage_graph collage_graph;
 int collage_graph_create(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss,
                          float *grad, float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2,
-                         float eps, void *workspace, size_t workspace_bytes, int32_t replays_per_launch, void *stream,
-                         collage_graph **out);
+                         float eps, void *workspace, size_t workspace_bytes, int32_t replays_per_launch,
+                         collage_timer *timer, void *stream, collage_graph **out);
 int collage_graph_launch(collage_graph *graph, int32_t count, void *stream);
 void collage_graph_destroy(collage_graph *graph);
 

@@ -35,7 +35,7 @@ class SceneDesc(ctypes.Structure):
         ("tau", ctypes.c_float), ("r_cut", ctypes.c_float), ("r_pad", ctypes.c_float),
         ("w_overlap", ctypes.c_float), ("w_contain", ctypes.c_float), ("w_fill", ctypes.c_float),
         ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float),
-        ("tile", ctypes.c_int32), ("cache_slots", ctypes.c_int32), ("bin_chunk", ctypes.c_int32),
+        ("tile", ctypes.c_int32), ("code_capacity", ctypes.c_int32), ("bin_chunk", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
     ]
 
@@ -57,7 +57,13 @@ SIGNATURES = [
                                              _vp]),
     ("collage_graph_create", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
-                                            ctypes.c_int32, _vp, ctypes.POINTER(_vp)]),
+                                            ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]),
+    ("collage_iterate_timed", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
+                                             _vp, ctypes.c_int32, _vp]),
+    ("collage_timer_create", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp)]),
+    ("collage_timer_elapsed", ctypes.c_int, [_vp, _f32p]),
+    ("collage_timer_destroy", None, [_vp]),
     ("collage_graph_launch", ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     ("collage_graph_destroy", None, [_vp]),
     ("collage_last_error", ctypes.c_char_p, []),

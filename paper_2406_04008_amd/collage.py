@@ -39,7 +39,7 @@ class CollageScene:
     """One level of a batch of layouts, resident on one GPU."""
 
     def __init__(self, scene: Scene, level: Optional[int] = None, device="cuda", tile: int = 0,
-                 cache_slots: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None):
+                 code_capacity: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("CollageScene needs a GPU (the HIP library has no CPU path)")
         self.lib = _lib.load()
@@ -72,7 +72,7 @@ class CollageScene:
         d.mask = self.mask.data_ptr()
         d.tau, d.r_cut, d.r_pad = scene.tau, scene.r_cut, scene.r_pad
         d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down = scene.weights()
-        d.tile, d.cache_slots, d.bin_chunk, d.flags = tile, cache_slots, bin_chunk, flags
+        d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags
         self._desc = d
         h_ = ctypes.c_void_p()
         with torch.cuda.device(dev):
@@ -165,6 +165,17 @@ class CollageScene:
         _lib.check(rc, "collage_iterate")
         return loss, grad
 
+    def iterate_timed(self, params, m, v, step, loss, grad, timer: "Timer", index: int, stream=None, lr_px=None,
+                      betas=(0.9, 0.999), eps=1e-8):
+        """collage_iterate recording `timer` pair `index` around the tile kernel."""
+        lr_px = self.scene.lr_px if lr_px is None else lr_px
+        ws, nb = self._ws()
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        rc = self.lib.collage_iterate_timed(self.handle, _ptr(params), None, None, _ptr(loss), _ptr(grad), _ptr(m),
+                                            _ptr(v), _ptr(step), lr_px, betas[0], betas[1], eps, ws, nb, timer.handle,
+                                            index, st)
+        _lib.check(rc, "collage_iterate_timed")
+
     def render(self, params: torch.Tensor, first: int = 0, count: Optional[int] = None) -> Tuple[torch.Tensor, torch.Tensor]:
         _need(params, (self.N, 4), "params")
         count = self.N - first if count is None else count
@@ -182,10 +193,11 @@ class CollageScene:
         return alpha[:total], alpha_pad[:total]
 
     def graph(self, params, m, v, step, loss, grad, cov=None, cov_pad=None, lr_px=None, betas=(0.9, 0.999),
-              eps=1e-8, replays_per_launch: int = 1, stream: Optional[torch.cuda.Stream] = None) -> "CollageGraph":
+              eps=1e-8, replays_per_launch: int = 1, stream: Optional[torch.cuda.Stream] = None,
+              timer: Optional["Timer"] = None) -> "CollageGraph":
         lr_px = self.scene.lr_px if lr_px is None else lr_px
         return CollageGraph(self, params, m, v, step, loss, grad, cov, cov_pad, lr_px, betas, eps,
-                            replays_per_launch, stream)
+                            replays_per_launch, stream, timer)
 
     def layout_images(self, flat: torch.Tensor):
         out, o = [], 0
@@ -199,7 +211,7 @@ class CollageGraph:
     """A hipGraph of `replays_per_launch` epochs of collage_iterate, captured by the library."""
 
     def __init__(self, cs: CollageScene, params, m, v, step, loss, grad, cov, cov_pad, lr_px, betas, eps,
-                 replays_per_launch, stream):
+                 replays_per_launch, stream, timer=None):
         self.cs = cs
         self.stream = stream if stream is not None else torch.cuda.Stream(cs.device)
         self._keep = (params, m, v, step, loss, grad, cov, cov_pad)
@@ -208,7 +220,8 @@ class CollageGraph:
         torch.cuda.current_stream(cs.device).synchronize()
         rc = cs.lib.collage_graph_create(cs.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss), _ptr(grad),
                                          _ptr(m), _ptr(v), _ptr(step), lr_px, betas[0], betas[1], eps, ws, nb,
-                                         replays_per_launch, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+                                         replays_per_launch, timer.handle if timer is not None else None,
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         _lib.check(rc, "collage_graph_create")
         self.handle = h
         self.replays_per_launch = replays_per_launch
@@ -221,6 +234,28 @@ class CollageGraph:
         h = getattr(self, "handle", None)
         if h is not None and h.value:
             self.cs.lib.collage_graph_destroy(h)
+            self.handle = None
+
+
+class Timer:
+    """HIP event pairs owned by the library (see collage_timer_create)."""
+
+    def __init__(self, count: int):
+        self.lib = _lib.load()
+        self.count = count
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.collage_timer_create(count, ctypes.byref(h)), "collage_timer_create")
+        self.handle = h
+
+    def elapsed_ms(self) -> np.ndarray:
+        out = np.zeros(self.count, np.float32)
+        _lib.check(self.lib.collage_timer_elapsed(self.handle, out.ctypes.data_as(_lib._f32p)), "collage_timer_elapsed")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.collage_timer_destroy(h)
             self.handle = None
 
 

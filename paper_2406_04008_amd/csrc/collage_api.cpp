@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -37,8 +38,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct collage_scene {
   int32_t B = 0, N = 0, V = 0;
   int32_t tile = kDefaultTile;
-  int32_t cache_slots = kDefaultCacheSlots;
+  int32_t code_cap = 0;
   int32_t bin_chunk = kDefaultBinChunk;
+  int32_t persist_grid = 1;
   uint32_t flags = 0;
   std::vector<LayoutRec> layouts;
   std::vector<int32_t> vert_off;
@@ -51,14 +53,20 @@ struct collage_scene {
   LayoutRec *d_layouts = nullptr;
   int32_t *d_vert_off = nullptr;
   // workspace layout
-  size_t off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0, off_list = 0,
-         off_partial = 0;
+  int64_t unit_cap = 0;
+  size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
+         off_list = 0, off_aux = 0, off_tunit = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_gbuf = 0, off_codes = 0;
   size_t ws_bytes = 0;
 };
 
 struct collage_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+};
+
+struct collage_timer {
+  std::vector<hipEvent_t> start, stop;
 };
 
 namespace {
@@ -102,8 +110,7 @@ int validate_desc(const collage_scene_desc *d) {
     if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
   if (d->tile != 0 && d->tile != 8 && d->tile != 16)
     return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8 or 16 (got %d)", d->tile);
-  if (d->cache_slots < -1 || d->cache_slots > kMaxCacheSlots)
-    return fail(COLLAGE_ERR_INVALID, "cache_slots must be -1 or 0..%d", kMaxCacheSlots);
+  if (d->code_capacity < -1) return fail(COLLAGE_ERR_INVALID, "code_capacity must be -1 or >= 0");
   if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)
     return fail(COLLAGE_ERR_INVALID, "bin_chunk must be 0..%d", kMaxBinChunk);
   if (d->flags & ~COLLAGE_FLAG_QUEUE) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
@@ -119,12 +126,15 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.num_shapes = s->N;
   a.total_tiles = (int32_t)s->total_tiles;
   a.tile = s->tile;
-  a.cache_slots = s->cache_slots;
   a.bin_chunk = s->bin_chunk;
+  a.unit_cap = (int32_t)s->unit_cap;
+  a.code_cap = s->code_cap;
+  a.persist_grid = s->persist_grid;
   a.vert_off = s->d_vert_off;
   a.verts = s->verts;
   a.rho = s->rho;
   a.mask = s->mask;
+  a.counters = reinterpret_cast<int32_t *>(w + s->off_counters);
   a.shapes = reinterpret_cast<ShapeRec *>(w + s->off_shapes);
   a.bbox = reinterpret_cast<int4 *>(w + s->off_bbox);
   a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
@@ -132,7 +142,14 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
   a.tile_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
-  a.tile_partial = reinterpret_cast<double4 *>(w + s->off_partial);
+  a.entry_aux = reinterpret_cast<int2 *>(w + s->off_aux);
+  a.tile_unit = reinterpret_cast<int32_t *>(w + s->off_tunit);
+  a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
+  a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
+  a.partial = reinterpret_cast<double4 *>(w + s->off_partial);
+  a.acc = reinterpret_cast<unsigned long long *>(w + s->off_acc);
+  a.gbuf = reinterpret_cast<double2 *>(w + s->off_gbuf);
+  a.codes = reinterpret_cast<uint16_t *>(w + s->off_codes);
   a.tau = s->tau;
   a.inv_tau = 1.0f / s->tau;
   a.r_cut = s->r_cut;
@@ -175,7 +192,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->N = desc->num_shapes;
   s->V = desc->num_verts;
   s->tile = desc->tile == 0 ? kDefaultTile : desc->tile;
-  s->cache_slots = desc->cache_slots < 0 ? kDefaultCacheSlots : desc->cache_slots;
+
   s->bin_chunk = desc->bin_chunk == 0 ? kDefaultBinChunk : desc->bin_chunk;
   s->flags = desc->flags;
   s->verts = desc->verts;
@@ -217,13 +234,25 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->total_pixels = pix;
   s->total_tiles = tiles;
   s->list_total = list;
+  // every (tile, item) pair is one work unit: at most one per list entry
+  s->unit_cap = list;
+  if (s->unit_cap > (int64_t)0x7fffffff) {
+    delete s;
+    return fail(COLLAGE_ERR_INVALID, "too many (tile, item) pairs");
+  }
+  const int64_t quads = (int64_t)(s->tile / 8) * (s->tile / 8);
+  int64_t code_cap = desc->code_capacity;
+  if (code_cap < 0) code_cap = std::max<int64_t>(65536, 16 * tiles);
+  s->code_cap = (int32_t)std::min<int64_t>(code_cap, s->unit_cap);
   size_t off = 0;
+  s->off_counters = off;
+  off = align256(off + sizeof(int32_t) * CNT_WORDS);
   s->off_shapes = off;
   off = align256(off + sizeof(ShapeRec) * (size_t)s->N);
   s->off_bbox = off;
   off = align256(off + sizeof(int4) * (size_t)s->N);
   s->off_edges = off;
-  off = align256(off + sizeof(EdgeRec) * (size_t)s->V);
+  off = align256(off + sizeof(EdgeRec) * ((size_t)s->V + kEdgePad));
   s->off_edges_d = off;
   off = align256(off + sizeof(EdgeD) * (size_t)s->V);
   s->off_count = off;
@@ -232,8 +261,27 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + sizeof(double) * 5 * (size_t)tiles);
   s->off_list = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  s->persist_grid = cus * 4;
+  s->off_aux = off;
+  off = align256(off + sizeof(int2) * (size_t)list);
+  s->off_tunit = off;
+  off = align256(off + sizeof(int32_t) * ((size_t)tiles + 1));
+  s->off_tcost = off;
+  off = align256(off + sizeof(int2) * (size_t)tiles);
+  s->off_tpre = off;
+  off = align256(off + sizeof(long long) * 2 * ((size_t)tiles + 1));
   s->off_partial = off;
   off = align256(off + sizeof(double4) * (size_t)list);
+  s->off_acc = off;
+  off = align256(off + 2 * sizeof(unsigned long long) * (size_t)pix);
+  s->off_gbuf = off;
+  off = align256(off + sizeof(double2) * (size_t)pix);
+  s->off_codes = off;
+  off = align256(off + sizeof(uint16_t) * 64 * (size_t)quads * (size_t)s->code_cap);
   s->ws_bytes = off + 256;
 
   hipError_t e = hipMalloc(&s->d_layouts, sizeof(LayoutRec) * s->B);
@@ -286,7 +334,10 @@ int collage_forward(const collage_scene *s, const float *params, float *cov, flo
   a.loss_out = loss;
   a.write_loss = 1;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_tiles(a, false, st);
+  if (e == hipSuccess) e = launch_bin(a, st);
+  if (e == hipSuccess) e = launch_scan(a, st);
+  if (e == hipSuccess) e = launch_cover(a, st);
+  if (e == hipSuccess) e = launch_pixel(a, false, st);
   if (e == hipSuccess) e = launch_finalize(a, false, true, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_forward launch");
 }
@@ -304,8 +355,13 @@ int collage_backward(const collage_scene *s, const float *params, const float *d
   a.params = params;
   a.dloss = dloss;
   a.grad_out = grad;
+  a.keep_codes = 1;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_bin(a, st);
+  if (e == hipSuccess) e = launch_scan(a, st);
+  if (e == hipSuccess) e = launch_cover(a, st);
+  if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, false, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward launch");
 }
@@ -324,8 +380,13 @@ int collage_forward_backward(const collage_scene *s, const float *params, float 
   a.loss_out = loss;
   a.grad_out = grad;
   a.write_loss = 1;
+  a.keep_codes = 1;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_bin(a, st);
+  if (e == hipSuccess) e = launch_scan(a, st);
+  if (e == hipSuccess) e = launch_cover(a, st);
+  if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, true, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_forward_backward launch");
 }
@@ -352,9 +413,13 @@ int collage_step(const collage_scene *s, float *params, const float *grad, float
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_step launch");
 }
 
-int collage_iterate(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
-                    float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
-                    size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
+                 float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws, size_t ws_bytes,
+                 void *stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
   if (!loss || !step || (s->N > 0 && (!params || !grad || !m || !v)))
     return fail(COLLAGE_ERR_INVALID, "an iterate buffer is NULL");
@@ -380,10 +445,76 @@ int collage_iterate(const collage_scene *s, float *params, float *cov, float *co
   a.beta2 = beta2;
   a.eps = eps;
   a.write_loss = 1;
+  a.keep_codes = 1;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_tiles(a, true, st);
+  if (e == hipSuccess) e = launch_bin(a, st);
+  if (e == hipSuccess) e = launch_scan(a, st);
+  if (e == hipSuccess && ev_start) e = hipEventRecord(ev_start, st);
+  if (e == hipSuccess) e = launch_cover(a, st);
+  if (e == hipSuccess && ev_stop) e = hipEventRecord(ev_stop, st);
+  if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, true, true, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_iterate launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int collage_iterate(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
+                    float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
+                    size_t ws_bytes, void *stream) {
+  return iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
+                      nullptr, nullptr);
+}
+
+int collage_iterate_timed(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
+                          float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
+                          size_t ws_bytes, collage_timer *timer, int32_t index, void *stream) {
+  if (!timer) return fail(COLLAGE_ERR_INVALID, "timer is NULL");
+  if (index < 0 || index >= (int32_t)timer->start.size()) return fail(COLLAGE_ERR_SIZE, "timer index out of range");
+  return iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
+                      timer->start[index], timer->stop[index]);
+}
+
+int collage_timer_create(int32_t count, collage_timer **out) {
+  if (!out) return fail(COLLAGE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || count > 65536) return fail(COLLAGE_ERR_INVALID, "count must be 1..65536");
+  collage_timer *t = new (std::nothrow) collage_timer();
+  if (!t) return fail(COLLAGE_ERR_INVALID, "out of host memory");
+  t->start.assign(count, nullptr);
+  t->stop.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    hipError_t e = hipEventCreate(&t->start[i]);
+    if (e == hipSuccess) e = hipEventCreate(&t->stop[i]);
+    if (e != hipSuccess) {
+      collage_timer_destroy(t);
+      return hip_fail(e, "hipEventCreate");
+    }
+  }
+  *out = t;
+  return COLLAGE_OK;
+}
+
+int collage_timer_elapsed(collage_timer *t, float *ms) {
+  if (!t || !ms) return fail(COLLAGE_ERR_INVALID, "timer or ms is NULL");
+  for (size_t i = 0; i < t->start.size(); ++i) {
+    hipError_t e = hipEventSynchronize(t->stop[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], t->start[i], t->stop[i]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+  }
+  return COLLAGE_OK;
+}
+
+void collage_timer_destroy(collage_timer *t) {
+  if (!t) return;
+  for (auto e : t->start)
+    if (e) (void)hipEventDestroy(e);
+  for (auto e : t->stop)
+    if (e) (void)hipEventDestroy(e);
+  delete t;
 }
 
 int collage_render_shapes(const collage_scene *s, const float *params, int32_t first, int32_t count, float *alpha,
@@ -400,24 +531,27 @@ int collage_render_shapes(const collage_scene *s, const float *params, int32_t f
   KArgs a = base_args(s, ws);
   a.params = params;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_render(a, first, count, nullptr, alpha, alpha_pad, s->max_canvas, st);
+  if (e == hipSuccess) e = launch_render(a, first, count, alpha, alpha_pad, s->max_canvas, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_render_shapes launch");
 }
 
 int collage_graph_create(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                          float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
-                         size_t ws_bytes, int32_t replays_per_launch, void *stream, collage_graph **out) {
+                         size_t ws_bytes, int32_t replays_per_launch, collage_timer *timer, void *stream,
+                         collage_graph **out) {
   if (!out) return fail(COLLAGE_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (!stream) return fail(COLLAGE_ERR_INVALID, "graph capture needs a non-NULL stream");
   if (replays_per_launch < 1 || replays_per_launch > 4096)
     return fail(COLLAGE_ERR_INVALID, "replays_per_launch must be 1..4096");
+  if (timer) return fail(COLLAGE_ERR_UNSUPPORTED, "event timers cannot be captured in a graph");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   int rc = COLLAGE_OK;
   for (int i = 0; i < replays_per_launch && rc == COLLAGE_OK; ++i)
-    rc = collage_iterate(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream);
+    rc = iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
+                      nullptr, nullptr);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(st, &g);
   if (rc != COLLAGE_OK) {

@@ -50,7 +50,15 @@ struct alignas(16) EdgeRec {
 struct alignas(16) EdgeD {
   double ax, ay;
   double ex, ey;
+  double inv_ee;        // 1 / |b - a|^2 (0 for a degenerate edge)
+  double kra_x, kra_y;  // k R(theta) v_a: the unscaled end point a (its derivative with respect to s)
+  double kre_x, kre_y;  // k R(theta) (v_b - v_a)
+  double pad;
 };
+
+// Work counters at the start of the workspace (zeroed by the transform kernel of every call).
+enum Counter { CNT_UNITS = 0, CNT_WORDS = 8 };
+constexpr int kPersistWaves = 4;  // waves per workgroup of the persistent kernels
 
 // Kernel arguments (one struct, passed by value).
 struct KArgs {
@@ -58,9 +66,11 @@ struct KArgs {
   int32_t num_layouts;
   int32_t num_shapes;
   int32_t total_tiles;
-  int32_t tile;          // tile edge in px
-  int32_t cache_slots;   // on-chip nearest-edge cache depth (fused call)
+  int32_t tile;          // tile edge in px (8 or 16); a tile has (tile / 8)^2 quadrants of 8 x 8 px
   int32_t bin_chunk;     // items binned per pass
+  int32_t unit_cap;      // upper bound of the number of units (list entries)
+  int32_t code_cap;      // units whose nearest-edge codes are kept between the coverage and adjoint passes
+  int32_t persist_grid;  // workgroups of the persistent kernels
   const int32_t *vert_off;
   const float *verts;
   const float *rho;
@@ -71,18 +81,27 @@ struct KArgs {
   int4 *bbox;            // inclusive pixel box x0, y0, x1, y1 (empty: x1 < x0)
   EdgeRec *edges;
   EdgeD *edges_d;
-  // per-tile outputs
+  // binning outputs
+  int32_t *counters;
   int32_t *tile_count;
   int32_t *tile_list;
-  double4 *tile_partial; // per (tile, slot): sums of the per-pixel adjoint terms (n_x, n_y, theta, scale)
-  double *tile_loss;     // per tile: the 5 loss-term sums
-  uint32_t *status;
-  int32_t *step_inc;     // incremented once by the transform kernel when not null
+  int2 *entry_aux;       // per list entry (tile, slot): (quadrant mask, coverage cost)
+  int32_t *tile_unit;    // [tiles + 1] first unit of every tile (prefix of the tile counts)
+  int2 *tile_cost;       // [tiles] summed (coverage, adjoint) costs of the tile's units
+  long long *tile_pre;   // [2][tiles + 1] exclusive prefix sums of the tile costs (coverage, adjoint)
+  uint16_t *codes;       // [code_cap * 64] nearest edge (15 bits) | inside << 15
+  // accumulators
+  unsigned long long *acc;  // [pixels][2] fixed-point S and S_pad (2^-40 units)
+  double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
+  double4 *partial;         // [list entries][quadrants] adjoint sums (n_x, n_y, theta, scale terms)
+  double *tile_loss;        // per tile: the 5 loss-term sums
+  int32_t *step_inc;        // incremented once by the transform kernel when not null
   // images
   float *cov_out;
   float *cov_pad_out;
   const float *dloss;    // [B,5] or null (= 1)
   int32_t write_loss;    // tile loss partials are written (forward and fused calls)
+  int32_t keep_codes;    // the coverage pass stores nearest-edge codes (adjoint calls)
   // constants
   float tau, inv_tau, r_cut, r_pad;
   float w[5];
@@ -94,28 +113,26 @@ struct KArgs {
   float *adam_v;
   const int32_t *step;
   float lr_px, beta1, beta2, eps;
-  // work queue (batched form)
-  int32_t *queue_counter;
-  const int32_t *queue_order;
-  int32_t use_queue;
-  int32_t queue_grid;
 };
-
-
 
 // Launchers (collage_kernels.hip).  Each returns hipGetLastError() of its launches.
 hipError_t launch_transform(const KArgs &a, hipStream_t st);
-hipError_t launch_tiles(const KArgs &a, bool adjoint, hipStream_t st);
+hipError_t launch_bin(const KArgs &a, hipStream_t st);
+hipError_t launch_scan(const KArgs &a, hipStream_t st);
+hipError_t launch_cover(const KArgs &a, hipStream_t st);
+hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
+hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st);
 hipError_t launch_adam_only(const KArgs &a, hipStream_t st);
-hipError_t launch_render(const KArgs &a, int first, int count, const int64_t *out_off_dev, float *alpha,
-                         float *alpha_pad, int max_pixels, hipStream_t st);
+hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, float *alpha_pad, int max_pixels,
+                         hipStream_t st);
 
 constexpr int kDefaultTile = 16;
-constexpr int kDefaultCacheSlots = 48;
-constexpr int kMaxCacheSlots = 64;
-constexpr int kDefaultBinChunk = 2048;
-constexpr int kMaxBinChunk = 2048;
+constexpr int kDefaultBinChunk = 1024;
+constexpr int kMaxBinChunk = 1024;
+constexpr int kEdgePad = 4;  // edge records past the last item that the scan may fetch
 constexpr int kMaxVertsPerItem = 32767;
+constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point scale of the coverage accumulators
+constexpr double kFixInv = 1.0 / 1099511627776.0;
 
 }  // namespace collage

@@ -1,23 +1,28 @@
 // HIP kernels (gfx950, wave64) of the image-space collage hot path.
 //
-// Per call the work is split into three launches with grids fixed by the scene:
+// One call is a short chain of launches with grids fixed by the scene:
 //   k_transform  one wave per item: eq. 2 applied to the outline (in double precision), float edge
 //                records for the scan and double edge records for the per-pixel evaluation, both
 //                relative to the item's origin, the pixel box of the item's coverage support and the
-//                outline orientation.
-//   k_tiles      one workgroup per screen tile: bins the layout's items whose support box meets the
-//                tile (ordered by item index, kept in LDS); for every pixel and binned item, scans the
-//                item's edges in float32 (edge records read through the scalar cache, shared by the
-//                whole wave) for the nearest edge and the even-odd parity, then evaluates the signed
-//                distance to that one edge, the coverage and (adjoint calls) the gradient terms in
-//                double precision; accumulates S and S_pad, the loss terms and dLoss/dS per pixel, and
-//                reduces the adjoint of every pixel per item into one partial per (tile, item) -- no
-//                atomics.  The nearest-edge index found by the coverage pass is kept in LDS for the
-//                adjoint pass (items beyond the LDS depth are rescanned).
+//                outline orientation.  Also clears the work counters.
+//   k_bin        one workgroup per screen tile: the layout's items whose support box meets the tile,
+//                in item order (LDS list copied to the workspace); every (tile, item) becomes one
+//                work unit with a mask of the tile's 8 x 8 quadrants the item touches.  Clears the
+//                tile's coverage accumulators.
+//   k_cover      persistent waves pull work units from a global counter (so heavy and light regions
+//                balance across the whole chip); per unit and pixel: float32 scan of the item's edges
+//                (records read through the scalar cache, shared by the wave) for the nearest edge and
+//                the even-odd parity, then the signed distance to that edge and the coverage in double
+//                precision, added to the pixel's S and S_pad as 2^-40 fixed point with 64-bit integer
+//                atomics (exact, so the result does not depend on the order of the units).  Adjoint
+//                calls keep a 2-byte nearest-edge code per (unit, pixel).
+//   k_pixel      one thread per pixel: S, S_pad, the five loss terms (summed per tile in a fixed order)
+//                and dLoss/dS, dLoss/dS_pad.
+//   k_adjoint    persistent waves again: per unit, the gradient terms of its pixels (double) reduced to
+//                one partial per (tile, item).
 //   k_finalize   one wave per item sums its tiles' partials in a fixed order (gradient, then the
-//                optional Adam update); one workgroup per layout sums its tiles' loss partials in a
-//                fixed order.
-// Results are deterministic (no atomics, fixed reduction orders).
+//                optional Adam update); one workgroup per layout sums its tiles' loss partials.
+// Results are deterministic.
 #include "collage_internal.h"
 
 #include <math.h>
@@ -41,7 +46,18 @@ __device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
   return make_int4(q[0], q[1], q[2], q[3]);
 }
 
+__device__ __forceinline__ int2 load_pair(cptr<int2> p, int64_t i) {
+  cptr<int> q = (cptr<int>)(p + i);
+  return make_int2(q[0], q[1]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -105,6 +121,7 @@ __device__ __forceinline__ void place_vertex(double c, double sn, double s, doub
 
 __global__ __launch_bounds__(256) void k_transform(KArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x < CNT_WORDS) a.counters[threadIdx.x] = 0;
   if (a.step_inc != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.step_inc[0] = a.step_inc[0] + 1;
   const int sid = blockIdx.x * 4 + wave;
   if (sid >= a.num_shapes) return;
@@ -144,6 +161,15 @@ __global__ __launch_bounds__(256) void k_transform(KArgs a) {
     rd.ay = ay;
     rd.ex = ex;
     rd.ey = ey;
+    rd.inv_ee = inv;
+    // d v' / d s = k R(theta) v for both end points (exact also when s = 0)
+    {
+      const float2 va = V[m], vb = V[m + 1 == n ? 0 : m + 1];
+      rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
+      rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
+      rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
+      rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
+    }
     a.edges_d[v0 + m] = rd;
     mnx = fmin(mnx, ax);
     mxx = fmax(mxx, ax);
@@ -190,29 +216,61 @@ __global__ __launch_bounds__(256) void k_transform(KArgs a) {
 // ------------------------------------------------------------------------------------------------
 // The float32 edge scan (the hot inner loop): nearest edge and crossing parity.
 // ------------------------------------------------------------------------------------------------
+// Two consecutive edge records (16 floats), loaded with one scalar-cache load into SGPRs.
+typedef float f32x16 __attribute__((ext_vector_type(16), aligned(4)));
+typedef const __attribute__((address_space(4))) f32x16 *cptr16;
+
+struct Edge2 {
+  f32x16 v;
+};
+
+__device__ __forceinline__ Edge2 load_edge2(cptr<float> F, int e) {
+  Edge2 r;
+  r.v = *(cptr16)(F + 8 * e);
+  return r;
+}
+
+// One edge of the scan: squared distance (tracked minimum and its index) and the crossing test.
+// r0..r7 = ax, ay, exs, eys, ex, ey, by, slope.
+__device__ __forceinline__ void scan_one(float ax, float ay, float exs, float eys, float ex, float ey, float by,
+                                         float slope, int e, float rx, float ry, float &best, int &idx, bool &par) {
+  const float wx = rx - ax, wy = ry - ay;
+  const float s = fmaf(wx, exs, wy * eys);
+  const float u = __builtin_amdgcn_fmed3f(s, 0.0f, 1.0f);
+  const float qx = fmaf(-u, ex, wx), qy = fmaf(-u, ey, wy);
+  const float d2 = fmaf(qx, qx, qy * qy);
+  if (d2 < best) {
+    best = d2;
+    idx = e;
+  }
+  const bool c1 = ay > ry, c2 = by > ry;
+  const bool xt = wx < wy * slope;
+  par ^= ((c1 != c2) && xt);
+}
+
 // Nearest edge (lowest index among equal float distances) of one item, and the even-odd parity of
 // the crossings of the ray from the pixel towards +x (half-open rule on the vertex ordinates).
+// Edge records are fetched two pairs ahead of their use so that the scalar-load latency overlaps the
+// arithmetic; the fetch may run up to four records past the item's last edge (the edge array is
+// padded by four records).
 __device__ __forceinline__ void edge_scan(cptr<EdgeRec> E, int cnt, float rx, float ry, int &bi, bool &par) {
+  cptr<float> F = (cptr<float>)E;
   float best = INFINITY;
   int idx = 0;
   bool pr = false;
-#pragma unroll 2
-  for (int e = 0; e < cnt; ++e) {
-    const float ax = E[e].ax, ay = E[e].ay, exs = E[e].exs, eys = E[e].eys;
-    const float ex = E[e].ex, ey = E[e].ey, by = E[e].by, slope = E[e].slope;
-    const float wx = rx - ax, wy = ry - ay;
-    const float s = fmaf(wx, exs, wy * eys);
-    const float u = __builtin_amdgcn_fmed3f(s, 0.0f, 1.0f);
-    const float qx = fmaf(-u, ex, wx), qy = fmaf(-u, ey, wy);
-    const float d2 = fmaf(qx, qx, qy * qy);
-    if (d2 < best) {
-      best = d2;
-      idx = e;
-    }
-    const bool c1 = ay > ry, c2 = by > ry;
-    const bool xt = wx < wy * slope;
-    pr ^= ((c1 != c2) && xt);
+  Edge2 cur = load_edge2(F, 0);
+  Edge2 nxt = load_edge2(F, 2);
+  int e = 0;
+  for (; e + 2 <= cnt; e += 2) {
+    const Edge2 nn = load_edge2(F, e + 4);
+    scan_one(cur.v[0], cur.v[1], cur.v[2], cur.v[3], cur.v[4], cur.v[5], cur.v[6], cur.v[7], e, rx, ry, best, idx, pr);
+    scan_one(cur.v[8], cur.v[9], cur.v[10], cur.v[11], cur.v[12], cur.v[13], cur.v[14], cur.v[15], e + 1, rx, ry, best,
+             idx, pr);
+    cur = nxt;
+    nxt = nn;
   }
+  if (e < cnt)
+    scan_one(cur.v[0], cur.v[1], cur.v[2], cur.v[3], cur.v[4], cur.v[5], cur.v[6], cur.v[7], e, rx, ry, best, idx, pr);
   bi = idx;
   par = pr;
 }
@@ -223,17 +281,21 @@ struct PairD {
   double sd, d, u, qx, qy;
 };
 
-__device__ __forceinline__ PairD pair_eval(const EdgeD &e, double rx, double ry, bool par) {
+__device__ __forceinline__ void pair_d2(const EdgeD &e, double rx, double ry, double &d2, double &u, double &qx,
+                                        double &qy) {
   const double wx = rx - e.ax, wy = ry - e.ay;
-  const double ee = e.ex * e.ex + e.ey * e.ey;
-  double u = 0.0;
-  if (ee > 0.0) u = fmin(fmax((wx * e.ex + wy * e.ey) / ee, 0.0), 1.0);
+  u = fmin(fmax((wx * e.ex + wy * e.ey) * e.inv_ee, 0.0), 1.0);
+  qx = wx - u * e.ex;
+  qy = wy - u * e.ey;
+  d2 = qx * qx + qy * qy;
+}
+
+__device__ __forceinline__ PairD pair_eval(const EdgeD &e, double rx, double ry, bool par) {
   PairD r;
-  r.qx = wx - u * e.ex;
-  r.qy = wy - u * e.ey;
-  r.d = sqrt(r.qx * r.qx + r.qy * r.qy);
+  double d2;
+  pair_d2(e, rx, ry, d2, r.u, r.qx, r.qy);
+  r.d = sqrt(d2);
   r.sd = par ? r.d : -r.d;
-  r.u = u;
   return r;
 }
 
@@ -242,38 +304,41 @@ __device__ __forceinline__ PairD pair_eval(const EdgeD &e, double rx, double ry,
 // (near the boundary between a vertex's fan and an edge's perpendicular strip), where the choice does
 // not change the distance much but does tilt the gradient direction.  So the nearest edge is decided
 // again in double among the scan's choice and its two neighbours (lowest index on exact ties).
-__device__ __forceinline__ PairD nearest_refined(const EdgeD *E, int ec, int bi, double rx, double ry, bool par,
-                                                 int &best) {
+__device__ __forceinline__ int nearest_refined(const EdgeD *E, int ec, int bi, double rx, double ry) {
   const int lo = bi == 0 ? ec - 1 : bi - 1, hi = bi + 1 == ec ? 0 : bi + 1;
-  int cand[3] = {lo, bi, hi};
+  int c0 = lo, c1 = bi, c2 = hi;
   // visit in increasing index so that strict '<' keeps the lowest index on ties
-  if (cand[0] > cand[1]) {
-    const int t = cand[0];
-    cand[0] = cand[1];
-    cand[1] = t;
+  if (c0 > c1) {
+    const int t = c0;
+    c0 = c1;
+    c1 = t;
   }
-  if (cand[1] > cand[2]) {
-    const int t = cand[1];
-    cand[1] = cand[2];
-    cand[2] = t;
+  if (c1 > c2) {
+    const int t = c1;
+    c1 = c2;
+    c2 = t;
   }
-  if (cand[0] > cand[1]) {
-    const int t = cand[0];
-    cand[0] = cand[1];
-    cand[1] = t;
+  if (c0 > c1) {
+    const int t = c0;
+    c0 = c1;
+    c1 = t;
   }
-  PairD r = pair_eval(E[cand[0]], rx, ry, par);
-  best = cand[0];
-#pragma unroll
-  for (int j = 1; j < 3; ++j) {
-    if (cand[j] == cand[j - 1]) continue;
-    const PairD c = pair_eval(E[cand[j]], rx, ry, par);
-    if (c.d < r.d) {
-      r = c;
-      best = cand[j];
+  double d2, u, qx, qy;
+  pair_d2(E[c0], rx, ry, d2, u, qx, qy);
+  int best = c0;
+  double bd = d2;
+  if (c1 != c0) {
+    pair_d2(E[c1], rx, ry, d2, u, qx, qy);
+    if (d2 < bd) {
+      bd = d2;
+      best = c1;
     }
   }
-  return r;
+  if (c2 != c1) {
+    pair_d2(E[c2], rx, ry, d2, u, qx, qy);
+    if (d2 < bd) best = c2;
+  }
+  return best;
 }
 
 // Coverage of one item at one pixel from its signed distance: alpha, alpha_pad (0 past the cut-off).
@@ -287,8 +352,8 @@ __device__ __forceinline__ void coverage(const KArgs &a, double sd, double &al, 
   dalp *= inv_tau;
 }
 
-// Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the per-item factors
-// (-k for t, 1/s for s) applied by the finalize kernel.  omega = G dalpha/dsd + G_pad dalpha_pad/dsd.
+// Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
+// translation terms applied by the finalize kernel.  omega = G dalpha/dsd + G_pad dalpha_pad/dsd.
 __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
                                                  bool par, float orient, double G, double Gp) {
   double al, dal, alp, dalp;
@@ -301,7 +366,7 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
     // nearest point inside the edge: grad sd is the unit edge normal, oriented (inside ? +1 : -1)
     // times the side of the edge the pixel is on; within 1e-4 px of the edge the float parity is
     // not reliable, but the product of the two is the outline orientation
-    const double il = 1.0 / sqrt(e.ex * e.ex + e.ey * e.ey);
+    const double il = sqrt(e.inv_ee);
     double sg = (double)orient;
     if (q.d >= 1e-4) {
       const double side = q.qy * e.ex - q.qx * e.ey;
@@ -317,7 +382,8 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
   t.x = om * nx;
   t.y = om * ny;
   t.z = om * (nx * ry - ny * rx);
-  t.w = om * (q.sd - (nx * rx + ny * ry));
+  // d sd / d s = -n . (k R (v_a + u (v_b - v_a))): the nearest point of the unscaled outline
+  t.w = -om * (nx * (e.kra_x + q.u * e.kre_x) + ny * (e.kra_y + q.u * e.kre_y));
   return t;
 }
 
@@ -356,88 +422,308 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
   return count;
 }
 
+// Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  Each
+// has a cost (coverage: quadrants x (edges + 16); adjoint: 64 x quadrants).  The persistent wave w of
+// W waves processes the units whose cost interval [p, p + c) ends in (B_w, B_{w+1}], where
+// B_w = ceil(w * total / W) and p is the unit's cost prefix: it finds the tile holding B_w by binary
+// search over the tile prefix sums and walks from there.  Every wave gets the same amount of work to
+// within one unit, and no counter is shared between waves.
+struct Walk {
+  int tile, slot, count;   // current unit = slot `slot` of tile `tile` (which has `count` units)
+  int layout, W, H, x0, y0;
+  int64_t pix_off, list_base;
+  long long p, end;        // cost prefix of the current unit; the wave stops at units ending past `end`
+  bool adj;
+};
+
+__device__ __forceinline__ void walk_tile(const KArgs &a, Walk &w, int T) {
+  cptr<LayoutRec> LS = konst(a.layouts);
+  w.layout = layout_of_tile(LS, a.num_layouts, w.tile);
+  w.W = LS[w.layout].W;
+  w.H = LS[w.layout].H;
+  const int ntx = LS[w.layout].ntx;
+  const int nb = LS[w.layout].shape_end - LS[w.layout].shape_begin;
+  const int lt = w.tile - LS[w.layout].tile_off;
+  const int tyi = lt / ntx;
+  w.x0 = (lt - tyi * ntx) * T;
+  w.y0 = tyi * T;
+  w.pix_off = LS[w.layout].pix_off;
+  w.list_base = LS[w.layout].list_off + (int64_t)lt * nb;
+  w.count = konst(a.tile_count)[w.tile];
+}
+
+__device__ __forceinline__ long long unit_cost(const Walk &w, int2 aux) {
+  return w.adj ? 64ll * __popc(aux.x) : (long long)aux.y;
+}
+
+// Moves to the next unit that exists (skipping empty tiles); returns false past the last tile.
+__device__ __forceinline__ bool walk_settle(const KArgs &a, Walk &w, int T) {
+  while (w.slot >= w.count) {
+    if (++w.tile >= a.total_tiles) return false;
+    w.slot = 0;
+    walk_tile(a, w, T);
+  }
+  return true;
+}
+
+// First unit of persistent wave gw: returns false when the wave has no work.
+__device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T) {
+  const long long *pre = a.tile_pre + (adj ? a.total_tiles + 1 : 0);
+  cptr<long long> P = konst(pre);
+  const long long tot = P[a.total_tiles];
+  w.adj = adj;
+  if (tot <= 0) return false;
+  const long long b0 = ((long long)gw * tot + nwaves - 1) / nwaves;
+  w.end = ((long long)(gw + 1) * tot + nwaves - 1) / nwaves;
+  if (b0 >= tot) return false;
+  int lo = 0, hi = a.total_tiles - 1;  // last tile with pre <= b0
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (P[mid] <= b0)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  w.tile = lo;
+  w.slot = 0;
+  w.p = P[lo];
+  walk_tile(a, w, T);
+  // skip the units that end at or before b0 (they belong to earlier waves)
+  for (;;) {
+    if (!walk_settle(a, w, T)) return false;
+    const long long c = unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot));
+    if (w.p + c > b0) break;
+    w.p += c;
+    ++w.slot;
+  }
+  // wave 0 also takes any zero-cost units in front of its first unit (there are none: every unit
+  // covers at least one quadrant); the current unit is this wave's iff it ends by w.end
+  return w.p + unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot)) <= w.end;
+}
+
+// Advances to the next unit of the wave; returns false when the wave is done.
+__device__ __forceinline__ bool walk_next(const KArgs &a, Walk &w, int T) {
+  w.p += unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot));
+  ++w.slot;
+  if (!walk_settle(a, w, T)) return false;
+  return w.p + unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot)) <= w.end;
+}
+
+// The unit the walk is on.
+struct Unit {
+  int slot, mask, item, W, H, x0, y0, u;
+  int64_t pix_off, entry;
+};
+
+__device__ __forceinline__ Unit walk_unit(const KArgs &a, const Walk &w) {
+  Unit r;
+  r.slot = w.slot;
+  r.entry = w.list_base + w.slot;
+  r.mask = load_pair(konst(a.entry_aux), r.entry).x;
+  r.item = konst(a.tile_list)[r.entry];
+  r.W = w.W;
+  r.H = w.H;
+  r.x0 = w.x0;
+  r.y0 = w.y0;
+  r.pix_off = w.pix_off;
+  return r;
+}
+
+// The wave index is wave-uniform; readfirstlane tells the compiler so, which keeps the work walk in SGPRs
+// and its loads on the scalar cache.
+__device__ __forceinline__ int global_wave() { return uniform((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6))); }
+
 // ------------------------------------------------------------------------------------------------
-// k_tiles: one workgroup per T x T screen tile, one thread per pixel, one wave per 8 x 8 quadrant.
-// ADJ = false: coverage and loss.  ADJ = true: also the adjoint (gradient partials).
+// k_bin: per tile, the ordered item list and one work unit per (tile, item).
 // ------------------------------------------------------------------------------------------------
-template <int T, bool ADJ>
-__global__ __launch_bounds__(T *T) void k_tiles(KArgs a) {
-  constexpr int NT = T * T;
-  constexpr int NW = NT / 64;
-  constexpr int QPR = T / 8;
-  constexpr int CS = ADJ ? kMaxCacheSlots : 1;
+template <int T>
+__global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
+  constexpr int NT = T * T, NW = NT / 64, QPR = T / 8, Q = QPR * QPR;
   __shared__ int s_list[kMaxBinChunk];
   __shared__ int s_wcnt[NW];
-  __shared__ unsigned short s_cache[CS][NT];
-  __shared__ double4 s_red[NW][64];
-  __shared__ double s_loss[NW][5];
-
-  const int tile = blockIdx.x;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tile = blockIdx.x, tid = threadIdx.x;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_tile(LS, a.num_layouts, tile);
   const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
-  const int sb = LS[b].shape_begin, se = LS[b].shape_end;
-  const int nb = se - sb;
-  const int64_t pix_off = LS[b].pix_off, list_off = LS[b].list_off;
-  const int lt = tile - LS[b].tile_off;
-  const int tyi = lt / ntx, txi = lt - tyi * ntx;
+  const int sb = LS[b].shape_begin, se = LS[b].shape_end, nb = se - sb;
+  const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
   const int x0 = txi * T, y0 = tyi * T;
-  const int wbx0 = x0 + 8 * (w % QPR), wby0 = y0 + 8 * (w / QPR);
-  const int wbx1 = wbx0 + 7, wby1 = wby0 + 7;
-  const int pxi = wbx0 + (l & 7), pyi = wby0 + (l >> 3);
-  const bool valid = pxi < W && pyi < H;
-  const float px = pxi + 0.5f, py = pyi + 0.5f;
-  const double pxd = pxi + 0.5, pyd = pyi + 0.5;
-  const int64_t pix = pix_off + (int64_t)pyi * W + pxi;
-  const int64_t list_base = list_off + (int64_t)lt * nb;
-  const int chunk = a.bin_chunk;
-  const int nchunks = (nb + chunk - 1) / chunk;
-  const int cache_slots = ADJ ? a.cache_slots : 0;
-  cptr<int4> BB = konst(a.bbox);
-  cptr<ShapeRec> SR = konst(a.shapes);
-  cptr<EdgeRec> ED = konst(a.edges);
-
-  // ---- binning + coverage --------------------------------------------------------------------
-  double S = 0.0, Sp = 0.0;
-  int slots = 0, last_cnt = 0;
-  for (int cb = sb; cb < se; cb += chunk) {
-    const int ce = min(cb + chunk, se);
-    const int cnt =
-        bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots);
-    last_cnt = cnt;
-    for (int q = 0; q < cnt; ++q) {
-      const int sid = uniform(s_list[q]);
-      const int4 bb = load_box(BB, sid);
-      if (bb.x > wbx1 || bb.z < wbx0 || bb.y > wby1 || bb.w < wby0) continue;
-      const int eo = SR[sid].edge_off, ec = SR[sid].edge_cnt;
-      int bi;
-      bool par;
-      edge_scan(ED + eo, ec, px - SR[sid].cxf, py - SR[sid].cyf, bi, par);
-      if (ec > 0) {
-        int be;
-        const PairD pr = nearest_refined(a.edges_d + eo, ec, bi, pxd - SR[sid].cx, pyd - SR[sid].cy, par, be);
-        double al, dal, alp, dalp;
-        coverage(a, pr.sd, al, dal, alp, dalp);
-        S += al;
-        Sp += alp;
+  const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
+  {
+    const int pxi = x0 + tid % T, pyi = y0 + tid / T;
+    if (pxi < W && pyi < H) {
+      const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
+      a.acc[2 * pix] = 0ull;
+      a.acc[2 * pix + 1] = 0ull;
+    }
+  }
+  int slots = 0;
+  long long my_cost = 0, my_quads = 0;
+  for (int cb = sb; cb < se; cb += a.bin_chunk) {
+    const int ce = min(cb + a.bin_chunk, se);
+    const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots);
+    for (int q = tid; q < cnt; q += NT) {
+      const int4 bb = a.bbox[s_list[q]];
+      int mask = 0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int qx0 = x0 + 8 * (k % QPR), qy0 = y0 + 8 * (k / QPR);
+        if (!(bb.x > qx0 + 7 || bb.z < qx0 || bb.y > qy0 + 7 || bb.w < qy0)) mask |= 1 << k;
       }
-      if (ADJ) {
-        const int slot = slots + q;
-        if (slot < cache_slots) s_cache[slot < CS ? slot : 0][tid] = (unsigned short)(bi | (par ? 0x8000 : 0));
-      }
+      const int nq = __popc(mask);
+      const int cost = nq * (a.shapes[s_list[q]].edge_cnt + 16);
+      a.entry_aux[list_base + slots + q] = make_int2(mask, cost);
+      my_cost += cost;
+      my_quads += nq;
     }
     slots += cnt;
     __syncthreads();
   }
-  if (tid == 0) a.tile_count[tile] = slots;
+  // tile totals of the unit costs (for the work partition of the persistent kernels)
+  my_cost = wave_sum_ll(my_cost);
+  my_quads = wave_sum_ll(my_quads);
+  __shared__ long long s_red[NW][2];
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6][0] = my_cost;
+    s_red[tid >> 6][1] = my_quads;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    long long c = 0, q = 0;
+    for (int j = 0; j < NW; ++j) {
+      c += s_red[j][0];
+      q += s_red[j][1];
+    }
+    a.tile_count[tile] = slots;
+    a.tile_cost[tile] = make_int2((int)c, (int)(64 * q));
+  }
+}
 
-  // ---- per-pixel loss terms and dLoss/dS -----------------------------------------------------
-  const double M = valid ? (double)a.mask[pix] : 0.0;
-  const double yinv = (double)H - pyd;
+// ------------------------------------------------------------------------------------------------
+// k_scan: one workgroup.  Unit numbering (prefix of the tile counts), prefix sums of the unit costs
+// and the first unit of every persistent wave.  Every thread owns a contiguous segment: one pass to
+// sum it, one block scan of the 1024 sums, one pass to write.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long block_exclusive_scan(long long v, long long *s_w, long long &total) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(x, o, 64);
+    if (l >= o) x += y;
+  }
+  if (l == 63) s_w[w] = x;
+  __syncthreads();
+  long long off = 0, tot = 0;
+  for (int j = 0; j < 16; ++j) {
+    if (j < w) off += s_w[j];
+    tot += s_w[j];
+  }
+  __syncthreads();
+  total = tot;
+  return off + x - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan(KArgs a) {
+  __shared__ long long s_w[16];
+  const int tid = threadIdx.x;
+  const int nt = a.total_tiles;
+  const int per = (nt + 1023) / 1024, t0 = min(tid * per, nt), t1 = min(t0 + per, nt);
+  long long cnt = 0, cc = 0, ca = 0;
+  for (int t = t0; t < t1; ++t) {
+    cnt += a.tile_count[t];
+    const int2 c = a.tile_cost[t];
+    cc += c.x;
+    ca += c.y;
+  }
+  long long nunits, tot_c, tot_a;
+  long long u = block_exclusive_scan(cnt, s_w, nunits);
+  long long pc = block_exclusive_scan(cc, s_w, tot_c);
+  long long pa = block_exclusive_scan(ca, s_w, tot_a);
+  long long *prc = a.tile_pre, *pra = a.tile_pre + (nt + 1);
+  for (int t = t0; t < t1; ++t) {
+    a.tile_unit[t] = (int)u;
+    prc[t] = pc;
+    pra[t] = pa;
+    const int2 c = a.tile_cost[t];
+    u += a.tile_count[t];
+    pc += c.x;
+    pa += c.y;
+  }
+  if (tid == 0) {
+    a.tile_unit[nt] = (int)nunits;
+    prc[nt] = tot_c;
+    pra[nt] = tot_a;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// k_cover: coverage of every (unit, pixel) into the fixed-point accumulators.
+// ------------------------------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_cover(KArgs a) {
+  constexpr int QPR = T / 8, Q = QPR * QPR;
+  const int lane = threadIdx.x & 63;
+  cptr<ShapeRec> SR = konst(a.shapes);
+  cptr<EdgeRec> ED = konst(a.edges);
+  const int gw = global_wave();
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  Walk wk;
+  for (bool ok = walk_begin(a, wk, gw, nwaves, false, T); ok; ok = walk_next(a, wk, T)) {
+    const Unit un = walk_unit(a, wk);
+    const int u = uniform(konst(a.tile_unit)[wk.tile]) + wk.slot;
+    const int eo = SR[un.item].edge_off, ec = SR[un.item].edge_cnt;
+    const float cxf = SR[un.item].cxf, cyf = SR[un.item].cyf;
+    const double cx = SR[un.item].cx, cy = SR[un.item].cy;
+    const bool keep = a.keep_codes && u < a.code_cap;
+    for (int k = 0; k < Q; ++k) {
+      if (!((un.mask >> k) & 1)) continue;
+      const int pxi = un.x0 + 8 * (k % QPR) + (lane & 7), pyi = un.y0 + 8 * (k / QPR) + (lane >> 3);
+      int bi = 0;
+      bool par = false;
+      edge_scan(ED + eo, ec, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+      if (ec > 0) {
+        const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
+        bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+        if (pxi < un.W && pyi < un.H) {
+          const PairD pr = pair_eval(a.edges_d[eo + bi], rx, ry, par);
+          double al, dal, alp, dalp;
+          coverage(a, pr.sd, al, dal, alp, dalp);
+          const int64_t pix = un.pix_off + (int64_t)pyi * un.W + pxi;
+          if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
+          if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
+        }
+      }
+      if (keep) a.codes[((int64_t)u * Q + k) * 64 + lane] = (uint16_t)(bi | (par ? 0x8000 : 0));
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// k_pixel: S, S_pad, loss terms (per tile) and dLoss/dS, dLoss/dS_pad per pixel.
+// ------------------------------------------------------------------------------------------------
+template <int T, bool GRAD>
+__global__ __launch_bounds__(T *T) void k_pixel(KArgs a) {
+  constexpr int NT = T * T, NW = NT / 64;
+  __shared__ double s_loss[NW][5];
+  const int tile = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  cptr<LayoutRec> LS = konst(a.layouts);
+  const int b = layout_of_tile(LS, a.num_layouts, tile);
+  const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
+  const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
+  const int pxi = txi * T + tid % T, pyi = tyi * T + tid / T;
+  const bool valid = pxi < W && pyi < H;
+  const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
+  double S = 0.0, Sp = 0.0, M = 0.0;
+  if (valid) {
+    S = (double)a.acc[2 * pix] * kFixInv;
+    Sp = (double)a.acc[2 * pix + 1] * kFixInv;
+    M = (double)a.mask[pix];
+    if (a.cov_out) a.cov_out[pix] = (float)S;
+    if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
+  }
+  const double yinv = (double)H - (pyi + 0.5);
   const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
-  if (valid && a.cov_out) a.cov_out[pix] = (float)S;
-  if (valid && a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
   if (a.write_loss) {
     double term[5];
     term[0] = valid ? (double)a.w[0] * (ov * ov) : 0.0;
@@ -457,82 +743,72 @@ __global__ __launch_bounds__(T *T) void k_tiles(KArgs a) {
       a.tile_loss[(int64_t)tile * 5 + tid] = v;
     }
   }
-  if (!ADJ) return;
-
-  double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
-  if (a.dloss) {
-    c_ov *= (double)a.dloss[5 * b + 0];
-    c_c *= (double)a.dloss[5 * b + 1];
-    c_f *= (double)a.dloss[5 * b + 2];
-    c_p *= (double)a.dloss[5 * b + 3];
-    c_d *= (double)a.dloss[5 * b + 4];
+  if (GRAD && valid) {
+    double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
+    if (a.dloss) {
+      c_ov *= (double)a.dloss[5 * b + 0];
+      c_c *= (double)a.dloss[5 * b + 1];
+      c_f *= (double)a.dloss[5 * b + 2];
+      c_p *= (double)a.dloss[5 * b + 3];
+      c_d *= (double)a.dloss[5 * b + 4];
+    }
+    const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
+    const double Gp = 2.0 * c_p * pv;
+    a.gbuf[pix] = make_double2(G, Gp);
   }
-  double G = 0.0, Gp = 0.0;
-  if (valid) {
-    G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
-    Gp = 2.0 * c_p * pv;
-  }
+}
 
-  // ---- adjoint: per (tile, item) partial gradient ----------------------------------------------
-  int slot0 = 0;
-  for (int cb = sb; cb < se; cb += chunk) {
-    const int ce = min(cb + chunk, se);
-    int cnt = last_cnt;
-    if (nchunks > 1) cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, nullptr);
-    for (int g0 = 0; g0 < cnt; g0 += 64) {
-      const int gn = min(64, cnt - g0);
-      for (int q = g0; q < g0 + gn; ++q) {
-        const int sid = uniform(s_list[q]);
-        const int4 bb = load_box(BB, sid);
-        double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (!(bb.x > wbx1 || bb.z < wbx0 || bb.y > wby1 || bb.w < wby0)) {
-          const int eo = SR[sid].edge_off, ec = SR[sid].edge_cnt;
-          const int slot = slot0 + q;
-          int bi;
-          bool par;
-          if (slot < cache_slots) {
-            const unsigned code = s_cache[slot < CS ? slot : 0][tid];
-            bi = (int)(code & 0x7fffu);
-            par = (code & 0x8000u) != 0u;
-          } else {
-            edge_scan(ED + eo, ec, px - SR[sid].cxf, py - SR[sid].cyf, bi, par);
-          }
-          double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
-          if (ec > 0) {
-            const double rx = pxd - SR[sid].cx, ry = pyd - SR[sid].cy;
-            int be;
-            const PairD pr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry, par, be);
-            t = adjoint_terms(a, a.edges_d[eo + be], pr, rx, ry, par, SR[sid].orient, G, Gp);
-          }
-          acc.x = wave_sum(t.x);
-          acc.y = wave_sum(t.y);
-          acc.z = wave_sum(t.z);
-          acc.w = wave_sum(t.w);
-        }
-        if (NW == 1) {
-          if (l == 0) a.tile_partial[list_base + slot0 + q] = acc;
-        } else {
-          if (l == 0) s_red[w][q - g0] = acc;
-        }
+// ------------------------------------------------------------------------------------------------
+// k_adjoint: per unit, the gradient terms of its pixels reduced to one partial per (tile, item).
+// ------------------------------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
+  constexpr int QPR = T / 8, Q = QPR * QPR;
+  const int lane = threadIdx.x & 63;
+  cptr<ShapeRec> SR = konst(a.shapes);
+  cptr<EdgeRec> ED = konst(a.edges);
+  const int gw = global_wave();
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  Walk wk;
+  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T); ok; ok = walk_next(a, wk, T)) {
+    const Unit un = walk_unit(a, wk);
+    const int u = uniform(konst(a.tile_unit)[wk.tile]) + wk.slot;
+    const int eo = SR[un.item].edge_off, ec = SR[un.item].edge_cnt;
+    const float cxf = SR[un.item].cxf, cyf = SR[un.item].cyf, orient = SR[un.item].orient;
+    const double cx = SR[un.item].cx, cy = SR[un.item].cy;
+    const bool cached = u < a.code_cap;
+    double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int k = 0; k < Q; ++k) {
+      if (!((un.mask >> k) & 1)) continue;
+      const int pxi = un.x0 + 8 * (k % QPR) + (lane & 7), pyi = un.y0 + 8 * (k / QPR) + (lane >> 3);
+      const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
+      int bi;
+      bool par;
+      if (cached) {
+        const unsigned code = a.codes[((int64_t)u * Q + k) * 64 + lane];
+        bi = (int)(code & 0x7fffu);
+        par = (code & 0x8000u) != 0u;
+      } else {
+        edge_scan(ED + eo, ec, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+        if (ec > 0) bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
       }
-      if (NW > 1) {
-        __syncthreads();
-        if (tid < gn) {
-          double4 s = s_red[0][tid];
-          for (int j = 1; j < NW; ++j) {
-            const double4 v = s_red[j][tid];
-            s.x += v.x;
-            s.y += v.y;
-            s.z += v.z;
-            s.w += v.w;
-          }
-          a.tile_partial[list_base + slot0 + g0 + tid] = s;
-        }
-        __syncthreads();
+      if (ec > 0 && pxi < un.W && pyi < un.H) {
+        const int64_t pix = un.pix_off + (int64_t)pyi * un.W + pxi;
+        const double2 g = a.gbuf[pix];
+        const EdgeD e = a.edges_d[eo + bi];
+        const PairD pr = pair_eval(e, rx, ry, par);
+        const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y);
+        acc.x += t.x;
+        acc.y += t.y;
+        acc.z += t.z;
+        acc.w += t.w;
       }
     }
-    slot0 += cnt;
-    if (nchunks > 1) __syncthreads();
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    acc.z = wave_sum(acc.z);
+    acc.w = wave_sum(acc.w);
+    if (lane == 0) a.partial[un.entry] = acc;
   }
 }
 
@@ -573,7 +849,7 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
   cptr<ShapeRec> SR = konst(a.shapes);
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = SR[sid].layout;
-  const float k = SR[sid].k, s = SR[sid].s;
+  const float k = SR[sid].k;
   const int4 bb = load_box(konst(a.bbox), sid);
   const int ntx = LS[b].ntx, nb = LS[b].shape_end - LS[b].shape_begin;
   const int tile_off = LS[b].tile_off;
@@ -601,7 +877,7 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
           hi = mid - 1;
       }
       if (slot >= 0) {
-        const double4 v = a.tile_partial[list_off + (int64_t)lt * nb + slot];
+        const double4 v = a.partial[list_off + (int64_t)lt * nb + slot];
         acc.x += v.x;
         acc.y += v.y;
         acc.z += v.z;
@@ -614,8 +890,7 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
   acc.z = wave_sum(acc.z);
   acc.w = wave_sum(acc.w);
   if (lane == 0) {
-    float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * acc.y), (float)acc.z,
-                           (float)(acc.w / (double)s));
+    float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * acc.y), (float)acc.z, (float)acc.w);
     if (SR[sid].bad != 0) g = make_float4(NAN, NAN, NAN, NAN);
     if (a.grad_out) reinterpret_cast<float4 *>(a.grad_out)[sid] = g;
     if (do_adam) adam_update(a, sid, g, k);
@@ -693,8 +968,9 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
     int bi;
     bool par;
     edge_scan(konst(a.edges) + eo, ec, pxi + 0.5f - SR[q].cxf, pyi + 0.5f - SR[q].cyf, bi, par);
-    int be;
-    const PairD pr = nearest_refined(a.edges_d + eo, ec, bi, pxi + 0.5 - SR[q].cx, pyi + 0.5 - SR[q].cy, par, be);
+    const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
+    bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+    const PairD pr = pair_eval(a.edges_d[eo + bi], rx, ry, par);
     double dal, dalp;
     coverage(a, pr.sd, al, dal, alp, dalp);
   }
@@ -706,29 +982,55 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
 // Launchers
 // ------------------------------------------------------------------------------------------------
 hipError_t launch_transform(const KArgs &a, hipStream_t st) {
-  const int blocks = (a.num_shapes + 3) / 4;
-  if (blocks > 0) {
-    hipLaunchKernelGGL(k_transform, dim3(blocks), dim3(256), 0, st, a);
-  } else if (a.step_inc) {
-    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, a.step_inc);
+  const int blocks = a.num_shapes > 0 ? (a.num_shapes + 3) / 4 : 1;
+  hipLaunchKernelGGL(k_transform, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const KArgs &a, hipStream_t st) {
+  if (a.total_tiles <= 0) return hipSuccess;
+  if (a.tile == 8)
+    hipLaunchKernelGGL(k_bin<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_bin<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const KArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cover(const KArgs &a, hipStream_t st) {
+  if (a.tile == 8)
+    hipLaunchKernelGGL(k_cover<8>, dim3(a.persist_grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_cover<16>, dim3(a.persist_grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
+  if (a.total_tiles <= 0) return hipSuccess;
+  const dim3 g(a.total_tiles);
+  if (a.tile == 8) {
+    if (grad)
+      hipLaunchKernelGGL((k_pixel<8, true>), g, dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pixel<8, false>), g, dim3(64), 0, st, a);
+  } else {
+    if (grad)
+      hipLaunchKernelGGL((k_pixel<16, true>), g, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pixel<16, false>), g, dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_tiles(const KArgs &a, bool adjoint, hipStream_t st) {
-  if (a.total_tiles <= 0) return hipSuccess;
-  const dim3 grid(a.total_tiles);
-  if (a.tile == 8) {
-    if (adjoint)
-      hipLaunchKernelGGL((k_tiles<8, true>), grid, dim3(64), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_tiles<8, false>), grid, dim3(64), 0, st, a);
-  } else {
-    if (adjoint)
-      hipLaunchKernelGGL((k_tiles<16, true>), grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_tiles<16, false>), grid, dim3(256), 0, st, a);
-  }
+hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
+  if (a.tile == 8)
+    hipLaunchKernelGGL(k_adjoint<8>, dim3(a.persist_grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adjoint<16>, dim3(a.persist_grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -749,8 +1051,8 @@ hipError_t launch_adam_only(const KArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_render(const KArgs &a, int first, int count, const int64_t *, float *alpha, float *alpha_pad,
-                         int max_pixels, hipStream_t st) {
+hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, float *alpha_pad, int max_pixels,
+                         hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_render, dim3((max_pixels + 255) / 256, count), dim3(256), 0, st, a, first, alpha, alpha_pad);
   return hipGetLastError();

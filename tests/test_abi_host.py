@@ -45,7 +45,7 @@ def _desc(B=1, N=1, V=4, w=(16,), h=(16,), k=(1.0,), shapes=(0, 1), voff=(0, 4))
     d.mask = 0x2000
     d.tau, d.r_cut, d.r_pad = 0.5, 8.0, 0.0
     d.w_overlap = d.w_contain = d.w_fill = 1.0
-    d.cache_slots = -1
+    d.code_capacity = -1
     return d, keep
 
 
@@ -57,8 +57,8 @@ def _desc(B=1, N=1, V=4, w=(16,), h=(16,), k=(1.0,), shapes=(0, 1), voff=(0, 4))
     (lambda d: setattr(d, "w_fill", float("inf")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "tile", 12), _lib.ERR_UNSUPPORTED),
     (lambda d: setattr(d, "flags", 0x80), _lib.ERR_UNSUPPORTED),
-    (lambda d: setattr(d, "cache_slots", 65), _lib.ERR_INVALID),
-    (lambda d: setattr(d, "bin_chunk", 4096), _lib.ERR_INVALID),
+    (lambda d: setattr(d, "code_capacity", -2), _lib.ERR_INVALID),
+    (lambda d: setattr(d, "bin_chunk", 1025), _lib.ERR_INVALID),
     (lambda d: setattr(d, "num_shapes", 2), _lib.ERR_SIZE),
     (lambda d: setattr(d, "num_verts", 5), _lib.ERR_SIZE),
     (lambda d: setattr(d, "mask", None), _lib.ERR_INVALID),

@@ -75,13 +75,13 @@ def test_backward_parity_autograd(name, tile, oracles):
     check_grad(_np(p.grad), g_ref)
 
 
-@pytest.mark.parametrize("cache_slots,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
+@pytest.mark.parametrize("code_capacity,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
 @pytest.mark.parametrize("tile", [16, 8])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_fused_parity(name, tile, cache_slots, bin_chunk, oracles):
+def test_fused_parity(name, tile, code_capacity, bin_chunk, oracles):
     sc, o = oracles(name)
-    _say("fused", name, "tile", tile, "cache", cache_slots, "chunk", bin_chunk)
-    cs = CollageScene(sc, tile=tile, cache_slots=cache_slots, bin_chunk=bin_chunk)
+    _say("fused", name, "tile", tile, "cache", code_capacity, "chunk", bin_chunk)
+    cs = CollageScene(sc, tile=tile, code_capacity=code_capacity, bin_chunk=bin_chunk)
     cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
     S_, Sp, L = o.forward(sc.params)
     check_image(_np(cov), S_, "S")
