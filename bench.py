@@ -57,7 +57,7 @@ def support_pairs(scene, params, level):
     return total
 
 
-def cpu_baseline(scene, level, budget_s=12.0, max_iters=30):
+def cpu_baseline(scene, level, budget_s=12.0, max_iters=2000):
     """The FP64 oracle (forward, backward, Adam) on the same scene, timed on this host's cores."""
     from oracle import oracle as orc
 
@@ -122,6 +122,8 @@ def main():
     p0 = params.clone()
 
     def reset():
+        # the epochs run on `stream`: drain it before the default stream rewrites their state
+        torch.cuda.synchronize()
         params.copy_(p0)
         m.zero_()
         v.zero_()
@@ -190,7 +192,7 @@ def main():
         "graph_matches_eager": graph_same,
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_tiles<{args.tile},adjoint> (coverage, loss and adjoint)",
+            "kernel": f"k_cover<{args.tile}> (edge scan, coverage, pixel accumulation)",
             "achieved": achieved / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s",
