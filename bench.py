@@ -85,15 +85,84 @@ def cpu_baseline(scene, level, budget_s=12.0, max_iters=2000):
                       f"scene from the seed-0 layout, {dt:.1f} s"}
 
 
+def coarse_to_fine(sc):
+    """The whole schedule of the metric scene (128 -> 256 -> 512 -> 1024, 300 epochs each), one captured
+    hipGraph per level, launch configurations autotuned per level."""
+    import torch
+
+    from paper_2406_04008_amd import autotune
+    from paper_2406_04008_amd.schedule import CoarseToFine
+
+    cfgs = autotune.tune_levels(sc)
+    sched = CoarseToFine(sc, configs=cfgs)
+    sched.run(keep_level_params=False)  # warm-up (instantiated graphs, caches)
+    res = sched.run(keep_level_params=False)
+    assert np.all(np.isfinite(res.params)), "non-finite parameters after the schedule"
+    return {"epochs": res.epochs, "gpu_s": res.gpu_ms / 1e3, "it_per_s": res.epochs / (res.gpu_ms / 1e3),
+            "levels": [{"level": l.level, "tile": l.tile, "ms_per_epoch": l.gpu_ms / l.steps,
+                        "final_loss": [float(x) for x in l.loss.sum(0)]} for l in res.levels]}
+
+
+def batched_vs_loop(steps):
+    """64 independent layouts (sides 128..512, 20..400 items) at full resolution: one batched scene (every
+    kernel launched once per epoch over all layouts) against a loop over 64 one-layout scenes on the same
+    stream, same epochs from the same start.  Per-layout results are bitwise identical in the two forms."""
+    import torch
+
+    from paper_2406_04008_amd import autotune, scenes
+    from paper_2406_04008_amd.collage import CollageScene
+
+    sc = scenes.config4(0)
+    level = sc.level_ref
+    cfg, _ = autotune.tune(sc, level=level, epochs=5, repeats=1)
+    stream = torch.cuda.Stream()
+
+    def run(css, reps):
+        state = []
+        for c in css:
+            p = c.params_tensor()
+            m, v, st = c.new_state()
+            state.append((c, p, m, v, st, torch.empty(c.B, 5, device="cuda"), torch.empty(c.N, 4, device="cuda")))
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(reps):
+                for c, p, m, v, st, loss, grad in state:
+                    c.iterate(p, m, v, st, loss=loss, grad=grad)
+            e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1), torch.cat([s_[1] for s_ in state]).cpu().numpy()
+
+    batched = [CollageScene(sc, level=level, **cfg.scene_kwargs())]
+    loop = [CollageScene(sc.layout_subset(b), level=level, **cfg.scene_kwargs()) for b in range(sc.num_layouts)]
+    run(batched, 2)
+    run(loop, 2)
+    tb, pb = run(batched, steps)
+    tl, pl = run(loop, steps)
+    pairs = support_pairs(sc, sc.params, level)
+    return {"layouts": sc.num_layouts, "items": sc.num_shapes, "pixels": int(batched[0].num_pixels),
+            "pixel_edge_pairs_per_scan": pairs, "steps": steps, "tile": cfg.tile,
+            "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk,
+            "batched_it_per_s": steps / (tb / 1e3), "loop_it_per_s": steps / (tl / 1e3),
+            "batched_pixel_edge_evals_per_s": 2.0 * pairs * steps / (tb / 1e3),
+            "loop_pixel_edge_evals_per_s": 2.0 * pairs * steps / (tl / 1e3),
+            "speedup": tl / tb, "batched_matches_loop": bool(np.array_equal(pb, pl))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--level", type=int, default=512)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="0: autotuned (tile, code capacity, bin chunk)")
     ap.add_argument("--code-capacity", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the coarse-to-fine schedule and the batched-vs-loop comparison")
+    ap.add_argument("--batched-steps", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
@@ -105,14 +174,18 @@ def main():
 
     import torch
 
-    from paper_2406_04008_amd import scenes
+    from paper_2406_04008_amd import autotune, scenes
     from paper_2406_04008_amd.collage import CollageScene, Timer
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     sc = scenes.config3(0)
-    cs = CollageScene(sc, level=args.level, tile=args.tile, code_capacity=args.code_capacity)
+    if args.tile == 0:
+        cfg, tune_times = autotune.tune(sc, level=args.level)
+    else:
+        cfg, tune_times = autotune.LaunchConfig(args.tile, args.code_capacity, 0), {}
+    cs = CollageScene(sc, level=args.level, **cfg.scene_kwargs())
     params = cs.params_tensor()
     m, v, step = cs.new_state()
     loss = torch.empty(cs.B, 5, device="cuda")
@@ -184,7 +257,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "512x512 level of the 128-256-512-1024 schedule; 500 closed cubic-Bezier items "
                                "(4-16 segments, 8 points each), 10-ellipse container, padding 2 px, "
-                               "downward force 1e-3, seed 0", "tile": args.tile},
+                               "downward force 1e-3, seed 0", "tile": cfg.tile,
+                   "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk},
         "pixel_edge_evals_per_s": 2.0 * pairs * its,
         "pixel_edge_pairs_per_scan": pairs,
         "wall_s": wall,
@@ -192,7 +266,7 @@ def main():
         "graph_matches_eager": graph_same,
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_cover<{args.tile}> (edge scan, coverage, pixel accumulation)",
+            "kernel": f"k_cover<{cfg.tile}> (edge scan, coverage, pixel accumulation)",
             "achieved": achieved / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s",
@@ -204,7 +278,11 @@ def main():
             "kernel_share_of_step": tile_ms / (region_ms / args.steps),
         },
         "cpu_baseline": None,
+        "autotune_ms_per_epoch": tune_times,
     }
+    if not args.no_extras:
+        out["coarse_to_fine"] = coarse_to_fine(sc)
+        out["batched"] = batched_vs_loop(args.batched_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.level)
     print(json.dumps(out), flush=True)

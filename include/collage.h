@@ -55,9 +55,6 @@ extern "C" {
 #define COLLAGE_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
 #define COLLAGE_ERR_UNSUPPORTED (-5) /* unknown flag or tile size */
 
-/* Scene flags. */
-#define COLLAGE_FLAG_NONE 0u
-#define COLLAGE_FLAG_QUEUE 1u /* batched form: tiles are taken from a device work queue, heaviest first */
 
 typedef struct collage_scene collage_scene; /* opaque host handle */
 
@@ -85,12 +82,13 @@ typedef struct collage_scene_desc {
   float r_cut;                  /* coverage cut-off, level px, >= 0 */
   float r_pad;                  /* padding offset, level px, >= 0 */
   float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
-  int32_t tile;                 /* screen tile edge in px: 8 or 16; 0 = default (16) */
+  int32_t tile;                 /* screen tile edge in px: 8, 16 or 32; 0 = default (16) */
   int32_t code_capacity;        /* (tile, item) work units whose nearest-edge codes (2 bytes per pixel)
                                    are kept between the coverage and adjoint passes; units beyond it
-                                   are rescanned; -1 = default (max(65536, 16 * tiles)) */
+                                   are rescanned; -1 = default (max(65536, 16 * tiles),
+                                   a quarter of that for 32-px tiles) */
   int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
-  uint32_t flags;               /* COLLAGE_FLAG_* */
+  uint32_t flags;               /* reserved: must be 0 */
 } collage_scene_desc;
 
 /* Validates `desc`, copies its host arrays and allocates the scene's small device tables.
@@ -173,15 +171,28 @@ int collage_iterate_timed(const collage_scene *scene, float *params, float *cov,
                           void *stream);
 
 /*
- * hipGraph of `replays_per_launch` consecutive collage_iterate epochs captured on `stream` (which must
- * not be the NULL stream).  collage_graph_launch replays it `count` times on `stream`.  `timer` must be
- * NULL (events recorded inside a captured graph cannot be timed on this platform).
+ * Start of a level of the coarse-to-fine schedule (Sec. 3.3; the optimizer state is not carried
+ * across levels, since the loss changes scale with the pixel count): zeroes m[N,4], v[N,4] and the
+ * device step counter with a kernel on `stream`.  Returns COLLAGE_ERR_INVALID for NULL buffers.
+ */
+int collage_adam_reset(const collage_scene *scene, float *m, float *v, int32_t *step, void *stream);
+
+/* graph_flags of collage_graph_create */
+#define COLLAGE_GRAPH_RESET_ADAM 1u /* the graph begins with collage_adam_reset */
+
+/*
+ * hipGraph of `replays_per_launch` (1..4096) consecutive collage_iterate epochs captured on `stream`
+ * (which must not be the NULL stream), preceded by the Adam reset when graph_flags has
+ * COLLAGE_GRAPH_RESET_ADAM: one launch of such a graph runs a whole level of the coarse-to-fine
+ * schedule.  The graph keeps the buffer addresses it was captured with; the caller keeps them alive and
+ * unmoved while the graph exists.  collage_graph_launch replays it `count` times on `stream`.
+ * Unknown graph flags give COLLAGE_ERR_UNSUPPORTED; argument errors are those of collage_iterate.
  */
 typedef struct collage_graph collage_graph;
 int collage_graph_create(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss,
                          float *grad, float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2,
                          float eps, void *workspace, size_t workspace_bytes, int32_t replays_per_launch,
-                         collage_timer *timer, void *stream, collage_graph **out);
+                         uint32_t graph_flags, void *stream, collage_graph **out);
 int collage_graph_launch(collage_graph *graph, int32_t count, void *stream);
 void collage_graph_destroy(collage_graph *graph);
 

@@ -13,13 +13,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcollage.so")
 
 OK = 0
+GRAPH_RESET_ADAM = 1
 ERR_INVALID = -1
 ERR_SIZE = -2
 ERR_WORKSPACE = -3
 ERR_HIP = -4
 ERR_UNSUPPORTED = -5
 FLAG_NONE = 0
-FLAG_QUEUE = 1
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -57,7 +57,8 @@ SIGNATURES = [
                                              _vp]),
     ("collage_graph_create", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
-                                            ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]),
+                                            ctypes.c_int32, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]),
+    ("collage_adam_reset", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("collage_iterate_timed", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
                                              ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
                                              _vp, ctypes.c_int32, _vp]),

@@ -143,6 +143,14 @@ class CollageScene:
         step = torch.zeros(1, dtype=torch.int32, device=self.device)
         return m, v, step
 
+    def reset_state(self, m, v, step):
+        """Zeroes the Adam state in a kernel on the current stream (collage_adam_reset)."""
+        _need(m, (self.N, 4), "m")
+        _need(v, (self.N, 4), "v")
+        _need(step, (1,), "step", torch.int32)
+        _lib.check(self.lib.collage_adam_reset(self.handle, _ptr(m), _ptr(v), _ptr(step), _stream(self.device)),
+                   "collage_adam_reset")
+
     def step(self, params, grad, m, v, step, lr_px=None, betas=(0.9, 0.999), eps=1e-8):
         lr_px = self.scene.lr_px if lr_px is None else lr_px
         for t, n in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
@@ -194,10 +202,11 @@ class CollageScene:
 
     def graph(self, params, m, v, step, loss, grad, cov=None, cov_pad=None, lr_px=None, betas=(0.9, 0.999),
               eps=1e-8, replays_per_launch: int = 1, stream: Optional[torch.cuda.Stream] = None,
-              timer: Optional["Timer"] = None) -> "CollageGraph":
+              reset_adam: bool = False) -> "CollageGraph":
+        """A captured hipGraph of `replays_per_launch` epochs (optionally preceded by the Adam reset)."""
         lr_px = self.scene.lr_px if lr_px is None else lr_px
         return CollageGraph(self, params, m, v, step, loss, grad, cov, cov_pad, lr_px, betas, eps,
-                            replays_per_launch, stream, timer)
+                            replays_per_launch, stream, reset_adam)
 
     def layout_images(self, flat: torch.Tensor):
         out, o = [], 0
@@ -211,7 +220,7 @@ class CollageGraph:
     """A hipGraph of `replays_per_launch` epochs of collage_iterate, captured by the library."""
 
     def __init__(self, cs: CollageScene, params, m, v, step, loss, grad, cov, cov_pad, lr_px, betas, eps,
-                 replays_per_launch, stream, timer=None):
+                 replays_per_launch, stream, reset_adam=False):
         self.cs = cs
         self.stream = stream if stream is not None else torch.cuda.Stream(cs.device)
         self._keep = (params, m, v, step, loss, grad, cov, cov_pad)
@@ -220,7 +229,7 @@ class CollageGraph:
         torch.cuda.current_stream(cs.device).synchronize()
         rc = cs.lib.collage_graph_create(cs.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss), _ptr(grad),
                                          _ptr(m), _ptr(v), _ptr(step), lr_px, betas[0], betas[1], eps, ws, nb,
-                                         replays_per_launch, timer.handle if timer is not None else None,
+                                         replays_per_launch, _lib.GRAPH_RESET_ADAM if reset_adam else 0,
                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         _lib.check(rc, "collage_graph_create")
         self.handle = h

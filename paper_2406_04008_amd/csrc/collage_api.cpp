@@ -108,12 +108,12 @@ int validate_desc(const collage_scene_desc *d) {
   const float ws[5] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down};
   for (float x : ws)
     if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
-  if (d->tile != 0 && d->tile != 8 && d->tile != 16)
-    return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8 or 16 (got %d)", d->tile);
+  if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32)
+    return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8, 16 or 32 (got %d)", d->tile);
   if (d->code_capacity < -1) return fail(COLLAGE_ERR_INVALID, "code_capacity must be -1 or >= 0");
   if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)
     return fail(COLLAGE_ERR_INVALID, "bin_chunk must be 0..%d", kMaxBinChunk);
-  if (d->flags & ~COLLAGE_FLAG_QUEUE) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  if (d->flags != 0) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
   return COLLAGE_OK;
 }
 
@@ -242,7 +242,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   }
   const int64_t quads = (int64_t)(s->tile / 8) * (s->tile / 8);
   int64_t code_cap = desc->code_capacity;
-  if (code_cap < 0) code_cap = std::max<int64_t>(65536, 16 * tiles);
+  if (code_cap < 0) {
+    code_cap = std::max<int64_t>(65536, 16 * tiles);
+    if (quads > 4) code_cap = code_cap * 4 / quads;  // same bytes as 16-px tiles
+  }
   s->code_cap = (int32_t)std::min<int64_t>(code_cap, s->unit_cap);
   size_t off = 0;
   s->off_counters = off;
@@ -537,18 +540,25 @@ int collage_render_shapes(const collage_scene *s, const float *params, int32_t f
 
 int collage_graph_create(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                          float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
-                         size_t ws_bytes, int32_t replays_per_launch, collage_timer *timer, void *stream,
+                         size_t ws_bytes, int32_t replays_per_launch, uint32_t graph_flags, void *stream,
                          collage_graph **out) {
   if (!out) return fail(COLLAGE_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (!stream) return fail(COLLAGE_ERR_INVALID, "graph capture needs a non-NULL stream");
   if (replays_per_launch < 1 || replays_per_launch > 4096)
     return fail(COLLAGE_ERR_INVALID, "replays_per_launch must be 1..4096");
-  if (timer) return fail(COLLAGE_ERR_UNSUPPORTED, "event timers cannot be captured in a graph");
+  if (graph_flags & ~(uint32_t)COLLAGE_GRAPH_RESET_ADAM) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown graph flag");
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if ((graph_flags & COLLAGE_GRAPH_RESET_ADAM) && (!step || (s->N > 0 && (!m || !v))))
+    return fail(COLLAGE_ERR_INVALID, "m, v or step is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   int rc = COLLAGE_OK;
+  if (graph_flags & COLLAGE_GRAPH_RESET_ADAM) {
+    e = launch_adam_reset(m, v, step, s->N, st);
+    if (e != hipSuccess) rc = hip_fail(e, "adam reset launch");
+  }
   for (int i = 0; i < replays_per_launch && rc == COLLAGE_OK; ++i)
     rc = iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
                       nullptr, nullptr);
@@ -575,6 +585,13 @@ int collage_graph_create(const collage_scene *s, float *params, float *cov, floa
   cg->exec = ex;
   *out = cg;
   return COLLAGE_OK;
+}
+
+int collage_adam_reset(const collage_scene *s, float *m, float *v, int32_t *step, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!step || (s->N > 0 && (!m || !v))) return fail(COLLAGE_ERR_INVALID, "m, v or step is NULL");
+  hipError_t e = launch_adam_reset(m, v, step, s->N, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "adam reset launch");
 }
 
 int collage_graph_launch(collage_graph *g, int32_t count, void *stream) {

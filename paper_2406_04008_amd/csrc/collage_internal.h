@@ -123,6 +123,7 @@ hipError_t launch_cover(const KArgs &a, hipStream_t st);
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st);
+hipError_t launch_adam_reset(float *m, float *v, int32_t *step, int num_shapes, hipStream_t st);
 hipError_t launch_adam_only(const KArgs &a, hipStream_t st);
 hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, float *alpha_pad, int max_pixels,
                          hipStream_t st);

@@ -934,6 +934,17 @@ __global__ void k_step_inc(int32_t *step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) step[0] = step[0] + 1;
 }
 
+// Zeroes the Adam moments and the step counter (a kernel rather than a memset, so that it can sit in a
+// captured graph).
+__global__ __launch_bounds__(256) void k_adam_reset(float *m, float *v, int32_t *step, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    m[i] = 0.0f;
+    v[i] = 0.0f;
+  }
+  if (i == 0) step[0] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_adam(KArgs a) {
   const int sid = blockIdx.x * 256 + threadIdx.x;
   if (sid >= a.num_shapes) return;
@@ -987,12 +998,26 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Every tile-size dependent kernel is instantiated for T = 8, 16 and 32; the scene fixes T.
+#define COLLAGE_TILE_DISPATCH(T_, STMT)                                                               \
+  switch (a.tile) {                                                                                  \
+    case 8: {                                                                                        \
+      constexpr int T_ = 8;                                                                          \
+      STMT;                                                                                          \
+    } break;                                                                                         \
+    case 32: {                                                                                       \
+      constexpr int T_ = 32;                                                                         \
+      STMT;                                                                                          \
+    } break;                                                                                         \
+    default: {                                                                                       \
+      constexpr int T_ = 16;                                                                         \
+      STMT;                                                                                          \
+    } break;                                                                                         \
+  }
+
 hipError_t launch_bin(const KArgs &a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
-  if (a.tile == 8)
-    hipLaunchKernelGGL(k_bin<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_bin<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles), dim3(T * T), 0, st, a));
   return hipGetLastError();
 }
 
@@ -1002,35 +1027,23 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_cover(const KArgs &a, hipStream_t st) {
-  if (a.tile == 8)
-    hipLaunchKernelGGL(k_cover<8>, dim3(a.persist_grid), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_cover<16>, dim3(a.persist_grid), dim3(256), 0, st, a);
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
   return hipGetLastError();
 }
 
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
   const dim3 g(a.total_tiles);
-  if (a.tile == 8) {
-    if (grad)
-      hipLaunchKernelGGL((k_pixel<8, true>), g, dim3(64), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_pixel<8, false>), g, dim3(64), 0, st, a);
+  if (grad) {
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_pixel<T, true>), g, dim3(T * T), 0, st, a));
   } else {
-    if (grad)
-      hipLaunchKernelGGL((k_pixel<16, true>), g, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_pixel<16, false>), g, dim3(256), 0, st, a);
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_pixel<T, false>), g, dim3(T * T), 0, st, a));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
-  if (a.tile == 8)
-    hipLaunchKernelGGL(k_adjoint<8>, dim3(a.persist_grid), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adjoint<16>, dim3(a.persist_grid), dim3(256), 0, st, a);
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_adjoint<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
   return hipGetLastError();
 }
 
@@ -1038,16 +1051,20 @@ hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_a
   const int gb = do_grad ? (a.num_shapes + 3) / 4 : 0;
   const int lb = do_loss ? a.num_layouts : 0;
   if (gb + lb == 0) return hipSuccess;
-  if (a.tile == 8)
-    hipLaunchKernelGGL(k_finalize<8>, dim3(gb + lb), dim3(256), 0, st, a, gb, do_adam ? 1 : 0, do_loss ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_finalize<16>, dim3(gb + lb), dim3(256), 0, st, a, gb, do_adam ? 1 : 0, do_loss ? 1 : 0);
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, do_adam ? 1 : 0,
+                                              do_loss ? 1 : 0));
   return hipGetLastError();
 }
 
 hipError_t launch_adam_only(const KArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, const_cast<int32_t *>(a.step));
   if (a.num_shapes > 0) hipLaunchKernelGGL(k_adam, dim3((a.num_shapes + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_reset(float *m, float *v, int32_t *step, int num_shapes, hipStream_t st) {
+  const int n = 4 * num_shapes;
+  hipLaunchKernelGGL(k_adam_reset, dim3(n > 0 ? (n + 255) / 256 : 1), dim3(256), 0, st, m, v, step, n);
   return hipGetLastError();
 }
 

@@ -125,6 +125,16 @@ class Scene:
             h.update(np.array([L.width_ref, L.height_ref, L.shape_begin, L.shape_end], np.int64).tobytes())
         return h.hexdigest()[:16]
 
+    def layout_subset(self, b: int) -> "Scene":
+        """Layout `b` alone, as a one-layout scene with the same constants and levels."""
+        lay = self.layouts[b]
+        v0, v1 = int(self.vert_off[lay.shape_begin]), int(self.vert_off[lay.shape_end])
+        return dataclasses.replace(
+            self, name=f"{self.name}[{b}]", verts=self.verts[v0:v1],
+            vert_off=(self.vert_off[lay.shape_begin:lay.shape_end + 1] - v0).astype(np.int32),
+            rho=self.rho[lay.shape_begin:lay.shape_end], params=self.params[lay.shape_begin:lay.shape_end],
+            layouts=[Layout(lay.width_ref, lay.height_ref, 0, lay.num_shapes, lay.ellipses, lay.rects, lay.full)])
+
     def with_params(self, params: np.ndarray) -> "Scene":
         return dataclasses.replace(self, params=np.ascontiguousarray(params, np.float32))
 
@@ -344,7 +354,8 @@ def config3(seed: int = 0, num_shapes: int = 500) -> Scene:
 
 def config4(seed: int = 0, num_layouts: int = 64) -> Scene:
     """Batched: layouts of side {128, 256, 384, 512}, 20..400 items each (50/50 star / Bezier),
-    each with its own 6-ellipse container (semi-axes U(30, 90) * side / 256)."""
+    each with its own 6-ellipse container (semi-axes U(30, 90) * side / 256).  Coarse-to-fine levels
+    1 -> 2 -> 4 with reference level 4: canvases at a quarter, half and full side."""
     rng = np.random.default_rng(seed)
     outlines, params, layouts = [], [], []
     begin = 0
@@ -363,7 +374,7 @@ def config4(seed: int = 0, num_layouts: int = 64) -> Scene:
         params.append(place_in_mask(rng, container_mask(lay, side, side, 1.0), n))
         layouts.append(lay)
         begin += n
-    return assemble("config4", outlines, np.concatenate(params, 0), layouts, [1], 1, tau=0.5, r_cut=8.0,
+    return assemble("config4", outlines, np.concatenate(params, 0), layouts, [1, 2, 4], 4, tau=0.5, r_cut=8.0,
                     r_pad=2.0, w_overlap=1.0, w_contain=1.0, w_fill=1.0, w_pad=1.0, w_down=1e-3,
                     steps_per_level=300, seed=seed)
 

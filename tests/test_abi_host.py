@@ -98,3 +98,10 @@ def test_null_scene_calls_fail_cleanly():
     assert lib.collage_forward(None, None, None, None, None, None, 0, None) == _lib.ERR_INVALID
     assert lib.collage_backward(None, None, None, None, None, 0, None) == _lib.ERR_INVALID
     assert lib.collage_graph_launch(None, 1, None) == _lib.ERR_INVALID
+    assert lib.collage_adam_reset(None, None, None, None, None) == _lib.ERR_INVALID
+    out_g = ctypes.c_void_p()
+    # graph capture is refused on the NULL stream and for unknown flags before any HIP call
+    assert lib.collage_graph_create(None, None, None, None, None, None, None, None, None, 0.5, 0.9, 0.999, 1e-8,
+                                    None, 0, 1, 0, None, ctypes.byref(out_g)) == _lib.ERR_INVALID
+    assert lib.collage_graph_create(None, None, None, None, None, None, None, None, None, 0.5, 0.9, 0.999, 1e-8,
+                                    None, 0, 1, 2, ctypes.c_void_p(1), ctypes.byref(out_g)) == _lib.ERR_UNSUPPORTED

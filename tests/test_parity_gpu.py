@@ -47,7 +47,7 @@ def oracles():
     return get
 
 
-@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("tile", [16, 8, 32])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_forward_parity(name, tile, oracles):
     sc, o = oracles(name)
@@ -60,7 +60,7 @@ def test_forward_parity(name, tile, oracles):
     check_loss(_np(loss), L)
 
 
-@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("tile", [16, 8, 32])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_backward_parity_autograd(name, tile, oracles):
     sc, o = oracles(name)
@@ -76,7 +76,7 @@ def test_backward_parity_autograd(name, tile, oracles):
 
 
 @pytest.mark.parametrize("code_capacity,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
-@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("tile", [16, 8, 32])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_fused_parity(name, tile, code_capacity, bin_chunk, oracles):
     sc, o = oracles(name)
@@ -90,13 +90,15 @@ def test_fused_parity(name, tile, code_capacity, bin_chunk, oracles):
     check_grad(_np(grad), o.backward(sc.params))
 
 
-@pytest.mark.parametrize("level", [128, 256, 512, 1024])
-def test_metric_scene_levels(level):
-    """500 Bezier items, the coarse-to-fine levels of the metric scene; 512 is the benchmark launch."""
+@pytest.mark.parametrize("level,tile,code_capacity", [(128, 16, -1), (256, 16, -1), (512, 16, -1), (512, 8, -1),
+                                                      (512, 32, -1), (512, 8, 0), (1024, 16, -1)])
+def test_metric_scene_levels(level, tile, code_capacity):
+    """500 Bezier items, the coarse-to-fine levels of the metric scene; 512 is the benchmark launch, in
+    every tile size the autotuner may pick."""
     sc = S.config3(0)
-    _say("config3 level", level)
+    _say("config3 level", level, "tile", tile, "cache", code_capacity)
     o = Oracle(sc, level=level)
-    cs = CollageScene(sc, level=level)
+    cs = CollageScene(sc, level=level, tile=tile, code_capacity=code_capacity)
     cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
     S_, Sp, L = o.forward(sc.params)
     check_image(_np(cov), S_, "S")
@@ -261,13 +263,7 @@ def test_batched_layouts_match_separate_scenes():
     imgs = cs.layout_images(cov)
     for b in (0, 5, 11):
         lay = sc.layouts[b]
-        sub = S.Scene(name="one", verts=sc.verts[sc.vert_off[lay.shape_begin]:sc.vert_off[lay.shape_end]],
-                      vert_off=sc.vert_off[lay.shape_begin:lay.shape_end + 1] - sc.vert_off[lay.shape_begin],
-                      rho=sc.rho[lay.shape_begin:lay.shape_end], params=sc.params[lay.shape_begin:lay.shape_end],
-                      layouts=[S.Layout(lay.width_ref, lay.height_ref, 0, lay.num_shapes, lay.ellipses)],
-                      levels=[1], level_ref=1, tau=sc.tau, r_cut=sc.r_cut, r_pad=sc.r_pad,
-                      w_overlap=sc.w_overlap, w_contain=sc.w_contain, w_fill=sc.w_fill, w_pad=sc.w_pad,
-                      w_down=sc.w_down)
+        sub = sc.layout_subset(b)
         cs1 = CollageScene(sub)
         c1, _, l1, g1 = cs1.forward_backward(cs1.params_tensor())
         assert torch.equal(c1, imgs[b].reshape(-1))
