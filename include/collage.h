@@ -3,12 +3,12 @@
  *
  * The operations are those of "Image-Space Collage and Packing with Differentiable Rendering"
  * (arXiv 2406.04008):
- *   - the collage problem of Sec. 2 ("Collage Problem"): items G_i with a translation t_i, a rotation
+ *   - the collage problem of Sec. 3 ("Collage Problem"): items G_i with a translation t_i, a rotation
  *     r_i and a scale s_i each, arranged in a container C;
- *   - the per-epoch pipeline of Sec. 3 (Fig. 2): transform every item (eq. 2), rasterize the items
+ *   - the per-epoch pipeline of Sec. 4 (Fig. 2): transform every item (eq. 2), rasterize the items
  *     differentiably into a w x h image, evaluate image-space losses against the container image
- *     (eq. 3, Sec. 3.2), back-propagate to (t, r, s) and update them (eq. 4);
- *   - the coarse-to-fine resolution schedule of Sec. 3.3, driven by the caller level by level.
+ *     (eq. 3, Sec. 4.2), back-propagate to (t, r, s) and update them (eq. 4);
+ *   - the coarse-to-fine resolution schedule of Sec. 4.3, driven by the caller level by level.
  *
  * Conventions shared by every entry point
  *   - Pixel (i, j), i the column and j the row, has centre (i + 1/2, j + 1/2) in level pixels; y points
@@ -103,7 +103,7 @@ int collage_workspace_size(const collage_scene *scene, size_t *bytes);
 int collage_scene_info(const collage_scene *scene, int64_t *num_pixels, int64_t *num_tiles);
 
 /*
- * Forward pass (Sec. 3, eqs. 2-3): coverage sums and the weighted loss terms.
+ * Forward pass (Sec. 4, eqs. 2-3): coverage sums and the weighted loss terms.
  *   params  [N,4]        item parameters
  *   cov     [pixels]     S, written (may be NULL)
  *   cov_pad [pixels]     S_pad, written (may be NULL)
@@ -171,7 +171,7 @@ int collage_iterate_timed(const collage_scene *scene, float *params, float *cov,
                           void *stream);
 
 /*
- * Start of a level of the coarse-to-fine schedule (Sec. 3.3; the optimizer state is not carried
+ * Start of a level of the coarse-to-fine schedule (Sec. 4.3; the optimizer state is not carried
  * across levels, since the loss changes scale with the pixel count): zeroes m[N,4], v[N,4] and the
  * device step counter with a kernel on `stream`.  Returns COLLAGE_ERR_INVALID for NULL buffers.
  */

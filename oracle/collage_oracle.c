@@ -7,22 +7,22 @@
  * What it computes, for every layout b of a batch and every pixel centre p = (i + 1/2, j + 1/2)
  * (level pixels, y down), following the paper:
  *
- *   - Rigid transform of each item (Sec. 3, eq. 2 with a uniform scale as in Sec. 4 "Data
+ *   - Rigid transform of each item (Sec. 4, eq. 2 with a uniform scale as in Sec. 5 "Data
  *     Visualization"):  v' = k * (R(theta) * (s * v) + t), k = level scale, rotation about the item's
  *     area centroid (the local origin).
- *   - Soft rasterization (Sec. 2 "Differentiable Rendering": an anti-aliased, continuous scene
+ *   - Soft rasterization (Sec. 3 "Differentiable Rendering": an anti-aliased, continuous scene
  *     function).  Reading used here: per item a coverage alpha = sigmoid(sd / tau), where sd is the
  *     Euclidean signed distance to the closed outline (positive inside by the even-odd rule), with a
  *     hard zero once sd < -r_cut; a padded coverage alpha_pad = sigmoid((sd + r_pad) / tau) with the
  *     same cut-off on sd + r_pad.  S = sum_i alpha_i, S_pad = sum_i alpha_pad_i.
- *   - Image-space losses (Sec. 3.2, eqs. for containment and non-overlap, in their differentiable
- *     reading) plus padding and the downward force of Sec. 4 ("Force Attraction"):
+ *   - Image-space losses (Sec. 4.2, eqs. for containment and non-overlap, in their differentiable
+ *     reading) plus padding and the downward force of Sec. 5 ("Force Attraction"):
  *        L_ov   = sum_p relu(S - 1)^2           L_cont = sum_p S (1 - M)
  *        L_fill = sum_p M relu(1 - S)^2         L_pad  = sum_p relu(S_pad - 1)^2
  *        L_down = sum_p S (H - y_p)
  *     reported weighted: loss[b][term] = w_term * L_term.
  *   - The gradient of sum_b sum_term dloss[b][term] * loss[b][term] with respect to every item's
- *     (t_x, t_y, theta, s) (Sec. 3, eq. 4 needs dL/dt, dL/dr, dL/ds), by the chain rule through the
+ *     (t_x, t_y, theta, s) (Sec. 4, eq. 4 needs dL/dt, dL/dr, dL/ds), by the chain rule through the
  *     two end points of each pixel's nearest edge and then through eq. 2.
  *   - Adam on those gradients (the update of eq. 4 with Adam's moment estimates).
  *

@@ -5,11 +5,11 @@ container masks sampled at pixel centres, and initial per-item transforms.  It c
 method's arithmetic (no coverage, no losses, no gradients, no optimizer), so both the GPU path and the
 FP64 oracle can consume the same scenes without sharing any of the computation they are compared on.
 
-Item representation follows the paper's "Vector Representation" paragraph (Sec. 2): each item is a
+Item representation follows the paper's "Vector Representation" paragraph (Sec. 3): each item is a
 closed outline; cubic Bezier outlines are flattened once, in the item's local frame, at 8 parameter
 values per segment (flattening commutes with the rigid transform of eq. 2, since Bezier curves are
 affine invariant).  The local frame is centred on the outline's area centroid, which is the rotation
-and scaling centre of eq. 2.  The container image of Sec. 3 (interior black, exterior white) is given
+and scaling centre of eq. 2.  The container image of Sec. 4 (interior black, exterior white) is given
 as its complement M = 1 inside, 0 outside, sampled at pixel centres (i + 1/2, j + 1/2), y down.
 
 All randomness comes from ``numpy.random.default_rng(seed)`` (PCG64) with a fixed draw order, so a

@@ -1,4 +1,4 @@
-"""Coarse-to-fine optimization schedule (Sec. 3.3 and the hierarchical rows of Table 1).
+"""Coarse-to-fine optimization schedule (Sec. 4.3 and the hierarchical rows of Table 1).
 
 The layout is optimized at a sequence of increasing resolutions.  Parameters are held in canonical
 (reference-level) pixels, so a level switch hands them over unchanged; what changes per level is the

@@ -225,7 +225,7 @@ def test_edge_cases():
                              w_pad=1, r_pad=2.0, w_down=1e-3)
     sc.rho[:2] = 1.0
     o = Oracle(sc)
-    for tile in (8, 16):
+    for tile in (8, 16, 32):
         cs = CollageScene(sc, tile=tile)
         cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
         S_, Sp, L = o.forward(sc.params)
@@ -247,6 +247,41 @@ def test_edge_cases():
     g = _np(grad)
     assert np.all(np.isnan(g[3])) and np.all(np.isfinite(np.delete(g, 3, 0)))
     assert np.all(np.isfinite(_np(loss)))
+
+
+def test_degenerate_scales():
+    # s = 0 collapses an item to its centre (sd = minus the distance to that point); s < 0 is a point
+    # reflection of the outline; both are valid inputs of eq. 2
+    sc = S.config1(0)
+    p = sc.params.copy()
+    p[1, 3] = 0.0
+    p[4, 3] = -0.8
+    _say("degenerate scales")
+    o = Oracle(sc)
+    S_, Sp, L = o.forward(p)
+    g_ref = o.backward(p)
+    for tile in (8, 16, 32):
+        cs = CollageScene(sc, tile=tile)
+        cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor(p))
+        check_image(_np(cov), S_, "S")
+        check_loss(_np(loss), L)
+        check_grad(_np(grad), g_ref)
+
+
+def test_more_items_than_one_bin_chunk():
+    # 1100 items in one layout: the binning kernel takes the layout in two LDS chunks (1024 + 76)
+    sc = S.random_scene(21, [(96, 80)], [1100], radius=(1.5, 4.0), off_canvas=0.1)
+    _say("1100 items", sc.num_shapes)
+    o = Oracle(sc)
+    S_, Sp, L = o.forward(sc.params)
+    g_ref = o.backward(sc.params)
+    for tile in (8, 16):
+        cs = CollageScene(sc, tile=tile)
+        cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+        check_image(_np(cov), S_, "S")
+        check_image(_np(cov_pad), Sp, "S_pad")
+        check_loss(_np(loss), L)
+        check_grad(_np(grad), g_ref)
 
 
 def test_batched_layouts_match_separate_scenes():

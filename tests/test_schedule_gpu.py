@@ -1,5 +1,5 @@
 """Coarse-to-fine schedule: one captured hipGraph per level, Adam restarted at each level, parameters
-handed over in canonical pixels (Sec. 3.3)."""
+handed over in canonical pixels (Sec. 4.3)."""
 import dataclasses
 import sys
 
