@@ -83,10 +83,11 @@ typedef struct collage_scene_desc {
   float r_pad;                  /* padding offset, level px, >= 0 */
   float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
   int32_t tile;                 /* screen tile edge in px: 8, 16 or 32; 0 = default (16) */
-  int32_t code_capacity;        /* (tile, item) work units whose nearest-edge codes (2 bytes per pixel)
-                                   are kept between the coverage and adjoint passes; units beyond it
-                                   are rescanned; -1 = default (max(65536, 16 * tiles),
-                                   a quarter of that for 32-px tiles) */
+  int32_t code_capacity;        /* 64-pixel chunks of (tile, item) work whose nearest-edge codes (2 bytes
+                                   per pixel) are kept between the coverage and adjoint passes; the
+                                   adjoint rescans the edges of later chunks.  -1 = default (four
+                                   items per pixel on average, at least 65536 chunks); 0 = always
+                                   rescan */
   int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
   uint32_t flags;               /* reserved: must be 0 */
 } collage_scene_desc;

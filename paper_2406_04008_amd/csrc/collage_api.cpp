@@ -38,7 +38,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct collage_scene {
   int32_t B = 0, N = 0, V = 0;
   int32_t tile = kDefaultTile;
-  int32_t code_cap = 0;
+  int64_t code_cap = 0;
+  int64_t chunk_cap = 0;
   int32_t bin_chunk = kDefaultBinChunk;
   int32_t persist_grid = 1;
   uint32_t flags = 0;
@@ -55,7 +56,7 @@ struct collage_scene {
   // workspace layout
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_aux = 0, off_tunit = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_list = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0;
   size_t ws_bytes = 0;
 };
@@ -128,6 +129,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.tile = s->tile;
   a.bin_chunk = s->bin_chunk;
   a.unit_cap = (int32_t)s->unit_cap;
+  a.chunk_cap = s->chunk_cap;
   a.code_cap = s->code_cap;
   a.persist_grid = s->persist_grid;
   a.vert_off = s->d_vert_off;
@@ -142,8 +144,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
   a.tile_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
-  a.entry_aux = reinterpret_cast<int2 *>(w + s->off_aux);
-  a.tile_unit = reinterpret_cast<int32_t *>(w + s->off_tunit);
+  a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
   a.partial = reinterpret_cast<double4 *>(w + s->off_partial);
@@ -240,13 +241,13 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     delete s;
     return fail(COLLAGE_ERR_INVALID, "too many (tile, item) pairs");
   }
-  const int64_t quads = (int64_t)(s->tile / 8) * (s->tile / 8);
+  // nearest-edge codes: one per lane of every 64-pixel chunk of the pass; a unit has at most
+  // tile^2 / 64 chunks.  Default: four items per pixel on average (units beyond it are rescanned).
+  const int64_t max_chunks = list * (int64_t)((s->tile * s->tile + 63) / 64);
+  s->chunk_cap = max_chunks;
   int64_t code_cap = desc->code_capacity;
-  if (code_cap < 0) {
-    code_cap = std::max<int64_t>(65536, 16 * tiles);
-    if (quads > 4) code_cap = code_cap * 4 / quads;  // same bytes as 16-px tiles
-  }
-  s->code_cap = (int32_t)std::min<int64_t>(code_cap, s->unit_cap);
+  if (code_cap < 0) code_cap = std::max<int64_t>(65536, 4 * ((pix + 63) / 64));
+  s->code_cap = std::min<int64_t>(code_cap, max_chunks);
   size_t off = 0;
   s->off_counters = off;
   off = align256(off + sizeof(int32_t) * CNT_WORDS);
@@ -270,21 +271,19 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     cus = 256;
   s->persist_grid = cus * 4;
   s->off_aux = off;
-  off = align256(off + sizeof(int2) * (size_t)list);
-  s->off_tunit = off;
-  off = align256(off + sizeof(int32_t) * ((size_t)tiles + 1));
+  off = align256(off + sizeof(int4) * (size_t)list);
   s->off_tcost = off;
   off = align256(off + sizeof(int2) * (size_t)tiles);
   s->off_tpre = off;
   off = align256(off + sizeof(long long) * 2 * ((size_t)tiles + 1));
   s->off_partial = off;
-  off = align256(off + sizeof(double4) * (size_t)list);
+  off = align256(off + sizeof(double4) * (size_t)s->chunk_cap);
   s->off_acc = off;
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)pix);
   s->off_gbuf = off;
   off = align256(off + sizeof(double2) * (size_t)pix);
   s->off_codes = off;
-  off = align256(off + sizeof(uint16_t) * 64 * (size_t)quads * (size_t)s->code_cap);
+  off = align256(off + sizeof(uint16_t) * 64 * (size_t)s->code_cap);
   s->ws_bytes = off + 256;
 
   hipError_t e = hipMalloc(&s->d_layouts, sizeof(LayoutRec) * s->B);

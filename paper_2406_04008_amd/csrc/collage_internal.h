@@ -66,10 +66,12 @@ struct KArgs {
   int32_t num_layouts;
   int32_t num_shapes;
   int32_t total_tiles;
-  int32_t tile;          // tile edge in px (8 or 16); a tile has (tile / 8)^2 quadrants of 8 x 8 px
+  int32_t tile;          // tile edge in px (8, 16 or 32)
   int32_t bin_chunk;     // items binned per pass
   int32_t unit_cap;      // upper bound of the number of units (list entries)
-  int32_t code_cap;      // units whose nearest-edge codes are kept between the coverage and adjoint passes
+  int64_t chunk_cap;     // upper bound of the number of 64-pixel chunks of a pass
+  int64_t code_cap;      // 64-pixel chunks whose nearest-edge codes are kept between the coverage and
+                         // adjoint passes (the first code_cap chunks of the pass)
   int32_t persist_grid;  // workgroups of the persistent kernels
   const int32_t *vert_off;
   const float *verts;
@@ -85,15 +87,16 @@ struct KArgs {
   int32_t *counters;
   int32_t *tile_count;
   int32_t *tile_list;
-  int2 *entry_aux;       // per list entry (tile, slot): (quadrant mask, coverage cost)
-  int32_t *tile_unit;    // [tiles + 1] first unit of every tile (prefix of the tile counts)
-  int2 *tile_cost;       // [tiles] summed (coverage, adjoint) costs of the tile's units
-  long long *tile_pre;   // [2][tiles + 1] exclusive prefix sums of the tile costs (coverage, adjoint)
-  uint16_t *codes;       // [code_cap * 64] nearest edge (15 bits) | inside << 15
+  int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
+                         // chunks of the tile's earlier units, 0)
+  int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units
+  long long *tile_pre;   // [2][tiles + 1] exclusive prefix sums of the tile costs and of the tile chunks
+  uint16_t *codes;       // [code_cap * 64] per chunk and lane: nearest edge (15 bits) | inside << 15
   // accumulators
   unsigned long long *acc;  // [pixels][2] fixed-point S and S_pad (2^-40 units)
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
-  double4 *partial;         // [list entries][quadrants] adjoint sums (n_x, n_y, theta, scale terms)
+  double4 *partial;         // [chunks of the pass] adjoint sums (n_x, n_y, theta, scale terms) of the
+                            // piece of a unit that starts at the chunk, 0 for other chunks
   double *tile_loss;        // per tile: the 5 loss-term sums
   int32_t *step_inc;        // incremented once by the transform kernel when not null
   // images
@@ -131,7 +134,9 @@ hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, flo
 constexpr int kDefaultTile = 16;
 constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
-constexpr int kEdgePad = 4;  // edge records past the last item that the scan may fetch
+constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
+constexpr int kStageEdges = 256;   // edge records a wave stages in LDS at a time (8 KiB)
+constexpr int kEpilogueCost = 16;  // per-pixel work after the scan, in edge evaluations (work partition)
 constexpr int kMaxVertsPerItem = 32767;
 constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point scale of the coverage accumulators
 constexpr double kFixInv = 1.0 / 1099511627776.0;

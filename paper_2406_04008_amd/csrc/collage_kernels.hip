@@ -46,11 +46,6 @@ __device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
   return make_int4(q[0], q[1], q[2], q[3]);
 }
 
-__device__ __forceinline__ int2 load_pair(cptr<int2> p, int64_t i) {
-  cptr<int> q = (cptr<int>)(p + i);
-  return make_int2(q[0], q[1]);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -186,9 +181,11 @@ __global__ __launch_bounds__(256) void k_transform(KArgs a) {
     const double ext = (double)a.r_cut + fmax((double)a.r_pad, 0.0);
     int4 box = make_int4(1, 1, 0, 0);  // empty
     if (n > 0 && finite) {
-      // pixel centres i + 1/2 in [cx + mnx - ext, cx + mxx + ext], widened by one pixel
-      double fx0 = floor(cx + mnx - ext - 0.5) - 1.0, fx1 = ceil(cx + mxx + ext - 0.5) + 1.0;
-      double fy0 = floor(cy + mny - ext - 0.5) - 1.0, fy1 = ceil(cy + mxy + ext - 0.5) + 1.0;
+      // pixel centres i + 1/2 in [cx + mnx - ext, cx + mxx + ext] (widened by 1e-6 px against
+      // rounding): a pixel farther than ext from the vertex box is farther than ext from the outline,
+      // where both alpha and alpha_pad are cut to zero
+      double fx0 = ceil(cx + mnx - ext - 0.5 - 1e-6), fx1 = floor(cx + mxx + ext - 0.5 + 1e-6);
+      double fy0 = ceil(cy + mny - ext - 0.5 - 1e-6), fy1 = floor(cy + mxy + ext - 0.5 + 1e-6);
       fx0 = fmax(fx0, 0.0);
       fy0 = fmax(fy0, 0.0);
       fx1 = fmin(fx1, (double)(W - 1));
@@ -399,7 +396,8 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
     bool hit = false;
     if (sid < ce) {
       const int4 bb = a.bbox[sid];
-      hit = !(bb.x > x1 || bb.z < x0 || bb.y > y1 || bb.w < y0);
+      // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
+      hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x1 || bb.z < x0 || bb.y > y1 || bb.w < y0);
     }
     const unsigned long long m = __ballot(hit);
     const int before = __popcll(m & ((1ull << l) - 1ull));
@@ -422,61 +420,85 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
   return count;
 }
 
-// Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  Each
-// has a cost (coverage: quadrants x (edges + 16); adjoint: 64 x quadrants).  The persistent wave w of
-// W waves processes the units whose cost interval [p, p + c) ends in (B_w, B_{w+1}], where
-// B_w = ceil(w * total / W) and p is the unit's cost prefix: it finds the tile holding B_w by binary
-// search over the tile prefix sums and walks from there.  Every wave gets the same amount of work to
-// within one unit, and no counter is shared between waves.
+// Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  A unit
+// covers the rectangle where the item's support box meets the tile, packed row by row into chunks of
+// 64 pixels (one pixel per lane).  A chunk costs (edges + kEpilogueCost) in the coverage pass and 1 in
+// the adjoint pass.  Chunks are numbered through the whole pass in unit order (the same numbering in
+// both passes: it indexes the nearest-edge codes kept between them and the adjoint partials).
+//
+// The persistent wave w of W processes the chunks whose cost interval [p, p + c) ends in
+// (B_w, B_{w+1}], where B_w = ceil(w * total / W) and p is the chunk's cost prefix.  It finds the tile
+// holding B_w by binary search over the tile prefix sums and walks from there; a unit may be split
+// between consecutive waves.  Every wave gets the same work to within one chunk, and no counter is
+// shared between waves.
 struct Walk {
   int tile, slot, count;   // current unit = slot `slot` of tile `tile` (which has `count` units)
-  int layout, W, H, x0, y0;
+  int W, x0, y0;           // canvas width and origin of the tile
   int64_t pix_off, list_base;
-  long long p, end;        // cost prefix of the current unit; the wave stops at units ending past `end`
+  long long p, end;        // cost prefix of the current unit (in this pass); end of the wave's range
+  long long q0;            // first chunk of the tile
+  int4 aux;                // (chunks, cost per chunk, chunks of the tile's earlier units, 0) of the unit
+  int jlo, jhi;            // the wave's chunks [jlo, jhi) of the current unit
   bool adj;
 };
 
+__device__ __forceinline__ int4 load_aux(const KArgs &a, int64_t i) {
+  cptr<int> r = (cptr<int>)(konst(a.entry_aux) + i);
+  return make_int4(r[0], r[1], r[2], r[3]);
+}
+
 __device__ __forceinline__ void walk_tile(const KArgs &a, Walk &w, int T) {
   cptr<LayoutRec> LS = konst(a.layouts);
-  w.layout = layout_of_tile(LS, a.num_layouts, w.tile);
-  w.W = LS[w.layout].W;
-  w.H = LS[w.layout].H;
-  const int ntx = LS[w.layout].ntx;
-  const int nb = LS[w.layout].shape_end - LS[w.layout].shape_begin;
-  const int lt = w.tile - LS[w.layout].tile_off;
+  const int b = layout_of_tile(LS, a.num_layouts, w.tile);
+  w.W = LS[b].W;
+  const int ntx = LS[b].ntx;
+  const int nb = LS[b].shape_end - LS[b].shape_begin;
+  const int lt = w.tile - LS[b].tile_off;
   const int tyi = lt / ntx;
   w.x0 = (lt - tyi * ntx) * T;
   w.y0 = tyi * T;
-  w.pix_off = LS[w.layout].pix_off;
-  w.list_base = LS[w.layout].list_off + (int64_t)lt * nb;
+  w.pix_off = LS[b].pix_off;
+  w.list_base = LS[b].list_off + (int64_t)lt * nb;
   w.count = konst(a.tile_count)[w.tile];
+  w.q0 = konst(a.tile_pre)[(a.total_tiles + 1) + w.tile];
 }
 
-__device__ __forceinline__ long long unit_cost(const Walk &w, int2 aux) {
-  return w.adj ? 64ll * __popc(aux.x) : (long long)aux.y;
-}
+__device__ __forceinline__ int chunk_cost(const Walk &w) { return w.adj ? 1 : w.aux.y; }
 
-// Moves to the next unit that exists (skipping empty tiles); returns false past the last tile.
+// Moves to the next unit that exists and has work (skipping empty tiles and, should one occur, a unit
+// without pixels) and loads its record; returns false past the last tile.
 __device__ __forceinline__ bool walk_settle(const KArgs &a, Walk &w, int T) {
-  while (w.slot >= w.count) {
-    if (++w.tile >= a.total_tiles) return false;
-    w.slot = 0;
-    walk_tile(a, w, T);
+  for (;;) {
+    while (w.slot >= w.count) {
+      if (++w.tile >= a.total_tiles) return false;
+      w.slot = 0;
+      walk_tile(a, w, T);
+    }
+    w.aux = load_aux(a, w.list_base + w.slot);
+    if (w.aux.x > 0) return true;
+    ++w.slot;
   }
-  return true;
 }
 
-// First unit of persistent wave gw: returns false when the wave has no work.
+// The wave's chunks of the current unit: those ending in (b0, end] (b0 <= p for every unit after the
+// first).
+__device__ __forceinline__ void walk_range(Walk &w, long long b0) {
+  const long long c = chunk_cost(w);
+  w.jlo = b0 > w.p ? (int)((b0 - w.p) / c) : 0;
+  const long long hi = (w.end - w.p) / c;
+  w.jhi = hi < (long long)w.aux.x ? (int)hi : w.aux.x;
+}
+
+// First piece of persistent wave gw: returns false when the wave has no work.
 __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T) {
-  const long long *pre = a.tile_pre + (adj ? a.total_tiles + 1 : 0);
-  cptr<long long> P = konst(pre);
+  cptr<long long> P = konst(a.tile_pre + (adj ? a.total_tiles + 1 : 0));
   const long long tot = P[a.total_tiles];
   w.adj = adj;
   if (tot <= 0) return false;
   const long long b0 = ((long long)gw * tot + nwaves - 1) / nwaves;
   w.end = ((long long)(gw + 1) * tot + nwaves - 1) / nwaves;
-  if (b0 >= tot) return false;
-  int lo = 0, hi = a.total_tiles - 1;  // last tile with pre <= b0
+  if (b0 >= tot || w.end <= b0) return false;
+  int lo = 0, hi = a.total_tiles - 1;  // last tile with prefix <= b0
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (P[mid] <= b0)
@@ -488,44 +510,43 @@ __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int 
   w.slot = 0;
   w.p = P[lo];
   walk_tile(a, w, T);
-  // skip the units that end at or before b0 (they belong to earlier waves)
+  // skip the units that end at or before b0 (they belong to earlier waves); every unit has a
+  // positive cost, since it covers at least one pixel
   for (;;) {
     if (!walk_settle(a, w, T)) return false;
-    const long long c = unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot));
+    const long long c = (long long)w.aux.x * chunk_cost(w);
     if (w.p + c > b0) break;
     w.p += c;
     ++w.slot;
   }
-  // wave 0 also takes any zero-cost units in front of its first unit (there are none: every unit
-  // covers at least one quadrant); the current unit is this wave's iff it ends by w.end
-  return w.p + unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot)) <= w.end;
+  walk_range(w, b0);
+  return w.jhi > w.jlo;
 }
 
-// Advances to the next unit of the wave; returns false when the wave is done.
+// Advances to the wave's next piece; returns false when the wave is done.
 __device__ __forceinline__ bool walk_next(const KArgs &a, Walk &w, int T) {
-  w.p += unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot));
+  if (w.jhi < w.aux.x) return false;  // the rest of this unit belongs to the next wave
+  w.p += (long long)w.aux.x * chunk_cost(w);
   ++w.slot;
   if (!walk_settle(a, w, T)) return false;
-  return w.p + unit_cost(w, load_pair(konst(a.entry_aux), w.list_base + w.slot)) <= w.end;
+  walk_range(w, w.p);
+  return w.jhi > 0;
 }
 
-// The unit the walk is on.
-struct Unit {
-  int slot, mask, item, W, H, x0, y0, u;
-  int64_t pix_off, entry;
+// First chunk (in the pass numbering) of the current unit.
+__device__ __forceinline__ long long walk_chunk0(const Walk &w) { return w.q0 + w.aux.z; }
+
+// The rectangle of a unit: the item's support box clipped to the tile (never empty for a listed item).
+struct Rect {
+  int x0, y0, w, n;
 };
 
-__device__ __forceinline__ Unit walk_unit(const KArgs &a, const Walk &w) {
-  Unit r;
-  r.slot = w.slot;
-  r.entry = w.list_base + w.slot;
-  r.mask = load_pair(konst(a.entry_aux), r.entry).x;
-  r.item = konst(a.tile_list)[r.entry];
-  r.W = w.W;
-  r.H = w.H;
-  r.x0 = w.x0;
-  r.y0 = w.y0;
-  r.pix_off = w.pix_off;
+__device__ __forceinline__ Rect unit_rect(int4 bb, int tx0, int ty0, int T) {
+  Rect r;
+  r.x0 = max(bb.x, tx0);
+  r.y0 = max(bb.y, ty0);
+  r.w = min(bb.z, tx0 + T - 1) - r.x0 + 1;
+  r.n = r.w * (min(bb.w, ty0 + T - 1) - r.y0 + 1);
   return r;
 }
 
@@ -538,7 +559,7 @@ __device__ __forceinline__ int global_wave() { return uniform((int)(blockIdx.x *
 // ------------------------------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
-  constexpr int NT = T * T, NW = NT / 64, QPR = T / 8, Q = QPR * QPR;
+  constexpr int NT = T * T, NW = NT / 64;
   __shared__ int s_list[kMaxBinChunk];
   __shared__ int s_wcnt[NW];
   const int tile = blockIdx.x, tid = threadIdx.x;
@@ -558,26 +579,37 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
     }
   }
   int slots = 0;
-  long long my_cost = 0, my_quads = 0;
+  long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
   for (int cb = sb; cb < se; cb += a.bin_chunk) {
     const int ce = min(cb + a.bin_chunk, se);
     const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots);
     for (int q = tid; q < cnt; q += NT) {
-      const int4 bb = a.bbox[s_list[q]];
-      int mask = 0;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const int qx0 = x0 + 8 * (k % QPR), qy0 = y0 + 8 * (k / QPR);
-        if (!(bb.x > qx0 + 7 || bb.z < qx0 || bb.y > qy0 + 7 || bb.w < qy0)) mask |= 1 << k;
-      }
-      const int nq = __popc(mask);
-      const int cost = nq * (a.shapes[s_list[q]].edge_cnt + 16);
-      a.entry_aux[list_base + slots + q] = make_int2(mask, cost);
-      my_cost += cost;
-      my_quads += nq;
+      const int sid = s_list[q];
+      const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
+      const int chunks = (r.n + 63) >> 6;
+      const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost;
+      a.entry_aux[list_base + slots + q] = make_int4(chunks, cpc, 0, 0);
+      my_cost += (long long)chunks * cpc;
+      my_quads += chunks;
     }
     slots += cnt;
     __syncthreads();
+  }
+  // chunks of the tile's earlier units, per unit (first wave, 64 units at a time)
+  if (tid < 64) {
+    int run = 0;
+    for (int base = 0; base < slots; base += 64) {
+      const int j = base + tid;
+      const int c = j < slots ? a.entry_aux[list_base + j].x : 0;
+      int x = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (tid >= o) x += y;
+      }
+      if (j < slots) a.entry_aux[list_base + j].z = run + x - c;
+      run += __shfl(x, 63, 64);
+    }
   }
   // tile totals of the unit costs (for the work partition of the persistent kernels)
   my_cost = wave_sum_ll(my_cost);
@@ -595,13 +627,13 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
       q += s_red[j][1];
     }
     a.tile_count[tile] = slots;
-    a.tile_cost[tile] = make_int2((int)c, (int)(64 * q));
+    a.tile_cost[tile] = make_int2((int)c, (int)q);
   }
 }
 
 // ------------------------------------------------------------------------------------------------
-// k_scan: one workgroup.  Unit numbering (prefix of the tile counts), prefix sums of the unit costs
-// and the first unit of every persistent wave.  Every thread owns a contiguous segment: one pass to
+// k_scan: one workgroup.  Prefix sums over the tiles of the coverage cost and of the chunk count (the
+// work partition of the persistent kernels).  Every thread owns a contiguous segment: one pass to
 // sum it, one block scan of the 1024 sums, one pass to write.
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ long long block_exclusive_scan(long long v, long long *s_w, long long &total) {
@@ -629,32 +661,125 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
   const int tid = threadIdx.x;
   const int nt = a.total_tiles;
   const int per = (nt + 1023) / 1024, t0 = min(tid * per, nt), t1 = min(t0 + per, nt);
-  long long cnt = 0, cc = 0, ca = 0;
+  long long cc = 0, cq = 0;
   for (int t = t0; t < t1; ++t) {
-    cnt += a.tile_count[t];
     const int2 c = a.tile_cost[t];
     cc += c.x;
-    ca += c.y;
+    cq += c.y;
   }
-  long long nunits, tot_c, tot_a;
-  long long u = block_exclusive_scan(cnt, s_w, nunits);
+  long long tot_c, tot_q;
   long long pc = block_exclusive_scan(cc, s_w, tot_c);
-  long long pa = block_exclusive_scan(ca, s_w, tot_a);
-  long long *prc = a.tile_pre, *pra = a.tile_pre + (nt + 1);
+  long long pq = block_exclusive_scan(cq, s_w, tot_q);
+  long long *prc = a.tile_pre, *prq = a.tile_pre + (nt + 1);
   for (int t = t0; t < t1; ++t) {
-    a.tile_unit[t] = (int)u;
     prc[t] = pc;
-    pra[t] = pa;
+    prq[t] = pq;
     const int2 c = a.tile_cost[t];
-    u += a.tile_count[t];
     pc += c.x;
-    pa += c.y;
+    pq += c.y;
   }
   if (tid == 0) {
-    a.tile_unit[nt] = (int)nunits;
     prc[nt] = tot_c;
-    pra[nt] = tot_a;
+    prq[nt] = tot_q;
   }
+}
+
+// ------------------------------------------------------------------------------------------------
+// The scan from LDS.  A wave stages the edge records of its current item in its own LDS slice with
+// coalesced vector loads (items with more than kStageEdges edges go through in segments), then every
+// lane reads each record with a broadcast LDS load.  LDS loads of a wave complete in order, so the next
+// records can be in flight while the current ones are used, which the scalar cache could not sustain
+// (most of its edge fetches missed).  The parity of the crossings and the ordinate test that the
+// next edge shares with this one (b_y of edge e is a_y of edge e + 1, the same float) are kept as
+// wave-wide lane masks in scalar registers.
+// ------------------------------------------------------------------------------------------------
+constexpr int kStageSlots = 2 * kStageEdges + 8;  // float4 slots per wave (+8: the scan reads ahead)
+
+__device__ __forceinline__ void stage_edges(const EdgeRec *E, int ne, float4 *dst, int lane) {
+  const float4 *src = reinterpret_cast<const float4 *>(E);
+  for (int i = lane; i < 2 * ne; i += 64) dst[i] = src[i];
+  __builtin_amdgcn_wave_barrier();
+}
+
+struct ScanState {
+  float best;               // smallest squared distance so far
+  int idx;                  // its edge (lowest index among equal distances)
+  unsigned long long par;   // lanes with an odd number of crossings so far
+  unsigned long long up;    // lanes whose ordinate test holds for the current vertex
+};
+
+__device__ __forceinline__ void scan_start(ScanState &st, const float4 *S, float ry) {
+  st.best = INFINITY;
+  st.idx = 0;
+  st.par = 0ull;
+  st.up = __ballot(S[0].y > ry);  // a_y of the item's first edge
+}
+
+// r0 = (a_x, a_y, e_x / |e|^2, e_y / |e|^2), r1 = (e_x, e_y, b_y, e_x / e_y).
+__device__ __forceinline__ void scan_edge(const float4 r0, const float4 r1, int e, float rx, float ry, ScanState &st) {
+  const float wx = rx - r0.x, wy = ry - r0.y;
+  const float t = fmaf(wx, r0.z, wy * r0.w);
+  const float u = __builtin_amdgcn_fmed3f(t, 0.0f, 1.0f);
+  const float qx = fmaf(-u, r1.x, wx), qy = fmaf(-u, r1.y, wy);
+  const float d2 = fmaf(qx, qx, qy * qy);
+  st.idx = d2 < st.best ? e : st.idx;  // strict: the lowest index wins ties
+  st.best = fminf(st.best, d2);
+  const unsigned long long up_b = __ballot(r1.z > ry);
+  const unsigned long long left = __ballot(wx < wy * r1.w);
+  st.par ^= (st.up ^ up_b) & left;
+  st.up = up_b;
+}
+
+// Edges [0, ne) of the staged slice S, numbered from ebase.  Each step loads four records' worth of
+// LDS slots at once and evaluates them as they arrive (LDS loads complete in order); the other waves
+// of the SIMD cover the remaining latency.  Reads up to eight slots past 2 ne.
+__device__ __forceinline__ void scan_lds(const float4 *S, int ne, int ebase, float rx, float ry, ScanState &st) {
+  int e = 0;
+  for (; e + 4 <= ne; e += 4) {
+    const float4 *R = S + 2 * e;
+    const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
+    scan_edge(r0, r1, ebase + e, rx, ry, st);
+    scan_edge(r2, r3, ebase + e + 1, rx, ry, st);
+    scan_edge(r4, r5, ebase + e + 2, rx, ry, st);
+    scan_edge(r6, r7, ebase + e + 3, rx, ry, st);
+  }
+  if (e < ne) {
+    const float4 *R = S + 2 * e;
+    const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
+    scan_edge(r0, r1, ebase + e, rx, ry, st);
+    if (e + 1 < ne) scan_edge(r2, r3, ebase + e + 1, rx, ry, st);
+    if (e + 2 < ne) scan_edge(r4, r5, ebase + e + 2, rx, ry, st);
+  }
+}
+
+// Nearest edge and inside flag of the lane's pixel over all ec edges of the item at E.  When the item
+// has at most kStageEdges edges they must already be staged in S; otherwise they are staged here.
+__device__ __forceinline__ void scan_item(const EdgeRec *E, int ec, bool staged, float4 *S, int lane, float rx,
+                                          float ry, int &bi, bool &par) {
+  ScanState st;
+  if (staged) {
+    scan_start(st, S, ry);
+    scan_lds(S, ec, 0, rx, ry, st);
+  } else {
+    for (int e0 = 0; e0 < ec; e0 += kStageEdges) {
+      const int ne = min(kStageEdges, ec - e0);
+      stage_edges(E + e0, ne, S, lane);
+      if (e0 == 0) scan_start(st, S, ry);
+      scan_lds(S, ne, e0, rx, ry, st);
+    }
+  }
+  bi = st.idx;
+  par = ((st.par >> lane) & 1ull) != 0ull;
+}
+
+// Pixel of `lane` in chunk j of a unit rectangle (in = false past the rectangle's last pixel; the
+// lane then computes on the rectangle's first pixel and its results are discarded).
+__device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int &px, int &py, bool &in) {
+  const int i = j * 64 + lane;
+  in = i < r.n;
+  const int ly = in ? i / r.w : 0;
+  px = r.x0 + (in ? i - ly * r.w : 0);
+  py = r.y0 + ly;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -662,39 +787,42 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
 // ------------------------------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(256) void k_cover(KArgs a) {
-  constexpr int QPR = T / 8, Q = QPR * QPR;
+  __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
+  float4 *S = s_stage[threadIdx.x >> 6];
   cptr<ShapeRec> SR = konst(a.shapes);
-  cptr<EdgeRec> ED = konst(a.edges);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   for (bool ok = walk_begin(a, wk, gw, nwaves, false, T); ok; ok = walk_next(a, wk, T)) {
-    const Unit un = walk_unit(a, wk);
-    const int u = uniform(konst(a.tile_unit)[wk.tile]) + wk.slot;
-    const int eo = SR[un.item].edge_off, ec = SR[un.item].edge_cnt;
-    const float cxf = SR[un.item].cxf, cyf = SR[un.item].cyf;
-    const double cx = SR[un.item].cx, cy = SR[un.item].cy;
-    const bool keep = a.keep_codes && u < a.code_cap;
-    for (int k = 0; k < Q; ++k) {
-      if (!((un.mask >> k) & 1)) continue;
-      const int pxi = un.x0 + 8 * (k % QPR) + (lane & 7), pyi = un.y0 + 8 * (k / QPR) + (lane >> 3);
+    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
+    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    const long long q = walk_chunk0(wk);
+    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
+    const float cxf = SR[item].cxf, cyf = SR[item].cyf;
+    const double cx = SR[item].cx, cy = SR[item].cy;
+    const bool staged = ec <= kStageEdges;
+    if (staged) stage_edges(a.edges + eo, ec, S, lane);
+    for (int j = wk.jlo; j < wk.jhi; ++j) {
+      int pxi, pyi;
+      bool in;
+      chunk_pixel(r, j, lane, pxi, pyi, in);
       int bi = 0;
       bool par = false;
-      edge_scan(ED + eo, ec, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+      scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
       if (ec > 0) {
         const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
         bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
-        if (pxi < un.W && pyi < un.H) {
+        if (in) {
           const PairD pr = pair_eval(a.edges_d[eo + bi], rx, ry, par);
           double al, dal, alp, dalp;
           coverage(a, pr.sd, al, dal, alp, dalp);
-          const int64_t pix = un.pix_off + (int64_t)pyi * un.W + pxi;
+          const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
           if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
           if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
         }
       }
-      if (keep) a.codes[((int64_t)u * Q + k) * 64 + lane] = (uint16_t)(bi | (par ? 0x8000 : 0));
+      if (a.keep_codes && q + j < a.code_cap) a.codes[(q + j) * 64 + lane] = (uint16_t)(bi | (par ? 0x8000 : 0));
     }
   }
 }
@@ -763,37 +891,40 @@ __global__ __launch_bounds__(T *T) void k_pixel(KArgs a) {
 // ------------------------------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
-  constexpr int QPR = T / 8, Q = QPR * QPR;
+  __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
+  float4 *S = s_stage[threadIdx.x >> 6];
   cptr<ShapeRec> SR = konst(a.shapes);
-  cptr<EdgeRec> ED = konst(a.edges);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   for (bool ok = walk_begin(a, wk, gw, nwaves, true, T); ok; ok = walk_next(a, wk, T)) {
-    const Unit un = walk_unit(a, wk);
-    const int u = uniform(konst(a.tile_unit)[wk.tile]) + wk.slot;
-    const int eo = SR[un.item].edge_off, ec = SR[un.item].edge_cnt;
-    const float cxf = SR[un.item].cxf, cyf = SR[un.item].cyf, orient = SR[un.item].orient;
-    const double cx = SR[un.item].cx, cy = SR[un.item].cy;
-    const bool cached = u < a.code_cap;
+    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
+    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    const long long q = walk_chunk0(wk);
+    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
+    const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
+    const double cx = SR[item].cx, cy = SR[item].cy;
+    const bool staged = ec <= kStageEdges;
+    if (staged && q + wk.jhi > a.code_cap) stage_edges(a.edges + eo, ec, S, lane);
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int k = 0; k < Q; ++k) {
-      if (!((un.mask >> k) & 1)) continue;
-      const int pxi = un.x0 + 8 * (k % QPR) + (lane & 7), pyi = un.y0 + 8 * (k / QPR) + (lane >> 3);
+    for (int j = wk.jlo; j < wk.jhi; ++j) {
+      int pxi, pyi;
+      bool in;
+      chunk_pixel(r, j, lane, pxi, pyi, in);
       const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
-      int bi;
-      bool par;
-      if (cached) {
-        const unsigned code = a.codes[((int64_t)u * Q + k) * 64 + lane];
+      int bi = 0;
+      bool par = false;
+      if (q + j < a.code_cap) {
+        const unsigned code = a.codes[(q + j) * 64 + lane];
         bi = (int)(code & 0x7fffu);
         par = (code & 0x8000u) != 0u;
       } else {
-        edge_scan(ED + eo, ec, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+        scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
         if (ec > 0) bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
       }
-      if (ec > 0 && pxi < un.W && pyi < un.H) {
-        const int64_t pix = un.pix_off + (int64_t)pyi * un.W + pxi;
+      if (ec > 0 && in) {
+        const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
         const double2 g = a.gbuf[pix];
         const EdgeD e = a.edges_d[eo + bi];
         const PairD pr = pair_eval(e, rx, ry, par);
@@ -808,7 +939,9 @@ __global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
     acc.y = wave_sum(acc.y);
     acc.z = wave_sum(acc.z);
     acc.w = wave_sum(acc.w);
-    if (lane == 0) a.partial[un.entry] = acc;
+    // the piece's sum sits at its first chunk; the piece's other chunks hold zeros
+    if (lane == 0) a.partial[q + wk.jlo] = acc;
+    for (int j = wk.jlo + 1 + lane; j < wk.jhi; j += 64) a.partial[q + j] = make_double4(0.0, 0.0, 0.0, 0.0);
   }
 }
 
@@ -877,11 +1010,15 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
           hi = mid - 1;
       }
       if (slot >= 0) {
-        const double4 v = a.partial[list_off + (int64_t)lt * nb + slot];
-        acc.x += v.x;
-        acc.y += v.y;
-        acc.z += v.z;
-        acc.w += v.w;
+        const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot];
+        const double4 *pp = a.partial + a.tile_pre[(a.total_tiles + 1) + tile_off + lt] + ax.z;
+        for (int c = 0; c < ax.x; ++c) {
+          const double4 v = pp[c];
+          acc.x += v.x;
+          acc.y += v.y;
+          acc.z += v.z;
+          acc.w += v.w;
+        }
       }
     }
   }
