@@ -5,11 +5,12 @@ Bezier outlines of 4..16 segments flattened at 8 points per segment, a container
 padding 2 px, downward force weight 1e-3), seed 0.  One step = one optimization epoch: transform,
 coverage, the five loss terms, the adjoint and the Adam update (collage_iterate), with all inputs
 resident in HBM.  The timed region is `steps` consecutive epochs launched on one stream; each records
-a pair of HIP events around its tile kernel (the dominant kernel), which gives the kernel's average
+a pair of HIP events around its coverage kernel (the dominant kernel), which gives the kernel's average
 duration over the timed region.  The same number of epochs is then replayed from one captured
 hipGraph and reported as graph_it_per_s.
 
-Prints one JSON line.  `value` is epochs per second.
+The timed region is one collage_iterate_n call of `steps` epochs (inside it, each epoch's update kernel
+also transforms the items for the next epoch).  Prints one JSON line.  `value` is epochs per second.
 """
 from __future__ import annotations
 
@@ -207,16 +208,16 @@ def main():
     # warm-up epochs, then back to the seed-0 layout: every timed region runs the first `steps` epochs
     # of the 512 x 512 level from the same layout (the items move, shrink and grow as they are optimized)
     with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            cs.iterate(params, m, v, step, loss=loss, grad=grad)
+        if args.warmup:
+            cs.iterate_n(params, m, v, step, args.warmup, loss=loss, grad=grad, stream=stream)
     reset()
     p_start = params.detach().cpu().numpy().copy()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    for i in range(args.steps):
-        cs.iterate_timed(params, m, v, step, loss, grad, timer, i, stream=stream)
+    with torch.cuda.stream(stream):
+        cs.iterate_n(params, m, v, step, args.steps, loss=loss, grad=grad, timer=timer, stream=stream)
     ev1.record(stream)
     stream.synchronize()
     torch.cuda.synchronize()

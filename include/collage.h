@@ -156,20 +156,25 @@ int collage_render_shapes(const collage_scene *scene, const float *params, int32
                           float *alpha_pad, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Event timer: `count` pairs of HIP events (timing enabled).  collage_iterate_timed records one pair
- * around its tile kernel (coverage, loss and adjoint).  collage_timer_elapsed waits for the events and
- * writes the `count` durations in milliseconds.
+ * Event timer: `count` pairs of HIP events (timing enabled).  collage_iterate_n records one pair per
+ * epoch around the coverage kernel.  collage_timer_elapsed waits for the events and writes the `count`
+ * durations in milliseconds.
  */
 typedef struct collage_timer collage_timer;
 int collage_timer_create(int32_t count, collage_timer **out);
 int collage_timer_elapsed(collage_timer *timer, float *ms);
 void collage_timer_destroy(collage_timer *timer);
 
-/* collage_iterate, recording event pair `index` of `timer` around the tile kernel on `stream`. */
-int collage_iterate_timed(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss,
-                          float *grad, float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2,
-                          float eps, void *workspace, size_t workspace_bytes, collage_timer *timer, int32_t index,
-                          void *stream);
+/*
+ * `epochs` (1..65536) consecutive collage_iterate epochs in one call, on `stream`.  Equivalent to that
+ * many collage_iterate calls; loss, grad and the optional images are those of the last epoch.  Within
+ * the call, the update of each epoch also transforms the items for the next one (one launch fewer per
+ * epoch).  With a non-NULL `timer` (at least `epochs` pairs), pair e is recorded around epoch e's
+ * coverage kernel.  Errors: those of collage_iterate; COLLAGE_ERR_SIZE if the timer is too small.
+ */
+int collage_iterate_n(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
+                      float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,
+                      void *workspace, size_t workspace_bytes, int32_t epochs, collage_timer *timer, void *stream);
 
 /*
  * Start of a level of the coarse-to-fine schedule (Sec. 4.3; the optimizer state is not carried

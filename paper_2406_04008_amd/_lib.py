@@ -59,9 +59,9 @@ SIGNATURES = [
                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
                                             ctypes.c_int32, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]),
     ("collage_adam_reset", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
-    ("collage_iterate_timed", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
-                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
-                                             _vp, ctypes.c_int32, _vp]),
+    ("collage_iterate_n", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t,
+                                         ctypes.c_int32, _vp, _vp]),
     ("collage_timer_create", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp)]),
     ("collage_timer_elapsed", ctypes.c_int, [_vp, _f32p]),
     ("collage_timer_destroy", None, [_vp]),

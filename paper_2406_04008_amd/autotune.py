@@ -4,7 +4,7 @@ The knobs of the scene (tile edge T in {8, 16, 32}, the code capacity that decid
 reads the coverage pass's nearest-edge codes or rescans, and the bin chunk, i.e. how many items one
 pass of the binning kernel holds in LDS) change only the speed: every configuration computes the
 same quantities to the same tolerance against the oracle.  The tuner times whole epochs
-(collage_iterate) of every candidate from the same parameters on the GPU it will run on, and keeps
+(collage_iterate_n) of every candidate from the same parameters on the GPU it will run on, and keeps
 the fastest.  Results are cached per (scene signature, level, device name) in memory and, if a path
 is given, in a JSON file.
 """
@@ -63,8 +63,7 @@ def time_config(scene: Scene, level: Optional[int], cfg: LaunchConfig, epochs: i
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            for _ in range(epochs):
-                cs.iterate(p, m, v, st, loss=loss, grad=grad)
+            cs.iterate_n(p, m, v, st, epochs, loss=loss, grad=grad, stream=stream)
             e1.record(stream)
             stream.synchronize()
             if r > 0:  # the first round warms up

@@ -173,16 +173,20 @@ class CollageScene:
         _lib.check(rc, "collage_iterate")
         return loss, grad
 
-    def iterate_timed(self, params, m, v, step, loss, grad, timer: "Timer", index: int, stream=None, lr_px=None,
-                      betas=(0.9, 0.999), eps=1e-8):
-        """collage_iterate recording `timer` pair `index` around the tile kernel."""
+    def iterate_n(self, params, m, v, step, epochs: int, loss=None, grad=None, timer: Optional["Timer"] = None,
+                  stream=None, lr_px=None, betas=(0.9, 0.999), eps=1e-8):
+        """`epochs` epochs in one call (collage_iterate_n); with `timer`, one event pair per epoch around the
+        coverage kernel.  Returns (loss, grad) of the last epoch."""
         lr_px = self.scene.lr_px if lr_px is None else lr_px
+        loss = torch.empty(self.B, 5, device=self.device) if loss is None else loss
+        grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
         ws, nb = self._ws()
         st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
-        rc = self.lib.collage_iterate_timed(self.handle, _ptr(params), None, None, _ptr(loss), _ptr(grad), _ptr(m),
-                                            _ptr(v), _ptr(step), lr_px, betas[0], betas[1], eps, ws, nb, timer.handle,
-                                            index, st)
-        _lib.check(rc, "collage_iterate_timed")
+        rc = self.lib.collage_iterate_n(self.handle, _ptr(params), None, None, _ptr(loss), _ptr(grad), _ptr(m),
+                                        _ptr(v), _ptr(step), lr_px, betas[0], betas[1], eps, ws, nb, epochs,
+                                        timer.handle if timer is not None else None, st)
+        _lib.check(rc, "collage_iterate_n")
+        return loss, grad
 
     def render(self, params: torch.Tensor, first: int = 0, count: Optional[int] = None) -> Tuple[torch.Tensor, torch.Tensor]:
         _need(params, (self.N, 4), "params")

@@ -48,7 +48,7 @@ struct collage_scene {
   const float *verts = nullptr, *rho = nullptr, *mask = nullptr;
   float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
   float w[5] = {1, 1, 1, 0, 0};
-  int64_t total_pixels = 0, total_tiles = 0, list_total = 0;
+  int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_pblk = 0;
   int32_t max_canvas = 0;
   // device tables owned by the scene
   LayoutRec *d_layouts = nullptr;
@@ -56,7 +56,7 @@ struct collage_scene {
   // workspace layout
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_list = 0, off_islot = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0;
   size_t ws_bytes = 0;
 };
@@ -126,6 +126,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.num_layouts = s->B;
   a.num_shapes = s->N;
   a.total_tiles = (int32_t)s->total_tiles;
+  a.total_pblk = (int32_t)s->total_pblk;
   a.tile = s->tile;
   a.bin_chunk = s->bin_chunk;
   a.unit_cap = (int32_t)s->unit_cap;
@@ -142,8 +143,9 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
   a.edges_d = reinterpret_cast<EdgeD *>(w + s->off_edges_d);
   a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
-  a.tile_loss = reinterpret_cast<double *>(w + s->off_loss);
+  a.block_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
+  a.item_slot = reinterpret_cast<int32_t *>(w + s->off_islot);
   a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
@@ -209,7 +211,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->w[4] = desc->w_down;
   s->vert_off.assign(desc->vert_offset, desc->vert_offset + s->N + 1);
   s->layouts.resize(s->B);
-  int64_t pix = 0, tiles = 0, list = 0;
+  int64_t pix = 0, tiles = 0, list = 0, pblk = 0;
   for (int b = 0; b < s->B; ++b) {
     LayoutRec &L = s->layouts[b];
     std::memset(&L, 0, sizeof(L));
@@ -223,17 +225,20 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     L.pix_off = pix;
     L.list_off = list;
     L.k = desc->layout_scale[b];
+    L.pblk_off = (int32_t)pblk;
+    pblk += ((int64_t)L.W * L.H + kPixelBlock - 1) / kPixelBlock;
     pix += (int64_t)L.W * L.H;
     tiles += (int64_t)L.ntx * L.nty;
     list += (int64_t)L.ntx * L.nty * (L.shape_end - L.shape_begin);
     if (L.W * L.H > s->max_canvas) s->max_canvas = L.W * L.H;
   }
-  if (tiles > (int64_t)0x7fffffff) {
+  if (tiles > (int64_t)0x7fffffff || pblk > (int64_t)0x7fffffff) {
     delete s;
     return fail(COLLAGE_ERR_INVALID, "too many screen tiles");
   }
   s->total_pixels = pix;
   s->total_tiles = tiles;
+  s->total_pblk = pblk;
   s->list_total = list;
   // every (tile, item) pair is one work unit: at most one per list entry
   s->unit_cap = list;
@@ -262,8 +267,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->off_count = off;
   off = align256(off + sizeof(int32_t) * (size_t)tiles);
   s->off_loss = off;
-  off = align256(off + sizeof(double) * 5 * (size_t)tiles);
+  off = align256(off + sizeof(double) * 5 * (size_t)pblk);
   s->off_list = off;
+  off = align256(off + sizeof(int32_t) * (size_t)list);
+  s->off_islot = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -419,13 +426,18 @@ int collage_step(const collage_scene *s, float *params, const float *grad, float
 
 namespace {
 
+// n consecutive epochs (forward, loss, backward, Adam).  Only the first epoch launches the transform
+// kernel: the update kernel of every other epoch transforms the items with their new parameters.
+// With a timer, pair e of `timer` is recorded around epoch e's coverage kernel.
 int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
                  float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws, size_t ws_bytes,
-                 void *stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 void *stream, int32_t n, collage_timer *timer) {
   if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
   if (!loss || !step || (s->N > 0 && (!params || !grad || !m || !v)))
     return fail(COLLAGE_ERR_INVALID, "an iterate buffer is NULL");
   if (s->N > 0 && !s->rho) return fail(COLLAGE_ERR_INVALID, "the scene has no rho (needed by the update)");
+  if (n < 1 || n > 65536) return fail(COLLAGE_ERR_INVALID, "epochs must be 1..65536 (got %d)", n);
+  if (timer && (int64_t)timer->start.size() < n) return fail(COLLAGE_ERR_SIZE, "the timer has fewer pairs than epochs");
   int rc = check_adam(lr_px, beta1, beta2, eps);
   if (rc) return rc;
   rc = check_ws(s, ws, ws_bytes);
@@ -449,14 +461,16 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
   a.write_loss = 1;
   a.keep_codes = 1;
   hipError_t e = launch_transform(a, st);
-  if (e == hipSuccess) e = launch_bin(a, st);
-  if (e == hipSuccess) e = launch_scan(a, st);
-  if (e == hipSuccess && ev_start) e = hipEventRecord(ev_start, st);
-  if (e == hipSuccess) e = launch_cover(a, st);
-  if (e == hipSuccess && ev_stop) e = hipEventRecord(ev_stop, st);
-  if (e == hipSuccess) e = launch_pixel(a, true, st);
-  if (e == hipSuccess) e = launch_adjoint(a, st);
-  if (e == hipSuccess) e = launch_finalize(a, true, true, true, st);
+  for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+    e = launch_bin(a, st);
+    if (e == hipSuccess) e = launch_scan(a, st);
+    if (e == hipSuccess && timer) e = hipEventRecord(timer->start[i], st);
+    if (e == hipSuccess) e = launch_cover(a, st);
+    if (e == hipSuccess && timer) e = hipEventRecord(timer->stop[i], st);
+    if (e == hipSuccess) e = launch_pixel(a, true, st);
+    if (e == hipSuccess) e = launch_adjoint(a, st);
+    if (e == hipSuccess) e = launch_finalize(a, true, true, true, st, i + 1 < n);
+  }
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_iterate launch");
 }
 
@@ -468,16 +482,14 @@ int collage_iterate(const collage_scene *s, float *params, float *cov, float *co
                     float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
                     size_t ws_bytes, void *stream) {
   return iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
-                      nullptr, nullptr);
+                      1, nullptr);
 }
 
-int collage_iterate_timed(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
-                          float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
-                          size_t ws_bytes, collage_timer *timer, int32_t index, void *stream) {
-  if (!timer) return fail(COLLAGE_ERR_INVALID, "timer is NULL");
-  if (index < 0 || index >= (int32_t)timer->start.size()) return fail(COLLAGE_ERR_SIZE, "timer index out of range");
+int collage_iterate_n(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad,
+                      float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws,
+                      size_t ws_bytes, int32_t epochs, collage_timer *timer, void *stream) {
   return iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
-                      timer->start[index], timer->stop[index]);
+                      epochs, timer);
 }
 
 int collage_timer_create(int32_t count, collage_timer **out) {
@@ -558,9 +570,9 @@ int collage_graph_create(const collage_scene *s, float *params, float *cov, floa
     e = launch_adam_reset(m, v, step, s->N, st);
     if (e != hipSuccess) rc = hip_fail(e, "adam reset launch");
   }
-  for (int i = 0; i < replays_per_launch && rc == COLLAGE_OK; ++i)
+  if (rc == COLLAGE_OK)
     rc = iterate_impl(s, params, cov, cov_pad, loss, grad, m, v, step, lr_px, beta1, beta2, eps, ws, ws_bytes, stream,
-                      nullptr, nullptr);
+                      replays_per_launch, nullptr);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(st, &g);
   if (rc != COLLAGE_OK) {

@@ -13,7 +13,7 @@ struct alignas(16) LayoutRec {
   int32_t tile_off;     // first global tile index
   int32_t shape_begin;  // item range [shape_begin, shape_end)
   int32_t shape_end;
-  int32_t pad0;
+  int32_t pblk_off;     // first pixel block (kPixelBlock pixels) of the layout
   int64_t pix_off;      // first pixel in packed images
   int64_t list_off;     // first entry of this layout's per-tile item lists (capacity: items of the layout per tile)
   float k;              // level scale
@@ -66,6 +66,7 @@ struct KArgs {
   int32_t num_layouts;
   int32_t num_shapes;
   int32_t total_tiles;
+  int32_t total_pblk;    // pixel blocks over all layouts
   int32_t tile;          // tile edge in px (8, 16 or 32)
   int32_t bin_chunk;     // items binned per pass
   int32_t unit_cap;      // upper bound of the number of units (list entries)
@@ -87,6 +88,7 @@ struct KArgs {
   int32_t *counters;
   int32_t *tile_count;
   int32_t *tile_list;
+  int32_t *item_slot;    // per layout [items][tiles]: the item's slot in the tile's list (set where listed)
   int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
                          // chunks of the tile's earlier units, 0)
   int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units
@@ -97,8 +99,8 @@ struct KArgs {
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
   double4 *partial;         // [chunks of the pass] adjoint sums (n_x, n_y, theta, scale terms) of the
                             // piece of a unit that starts at the chunk, 0 for other chunks
-  double *tile_loss;        // per tile: the 5 loss-term sums
-  int32_t *step_inc;        // incremented once by the transform kernel when not null
+  double *block_loss;       // per pixel block: the 5 loss-term sums
+  int32_t *step_inc;        // incremented once per epoch by the scan kernel when not null
   // images
   float *cov_out;
   float *cov_pad_out;
@@ -125,7 +127,10 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st);
 hipError_t launch_cover(const KArgs &a, hipStream_t st);
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
-hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st);
+// do_transform: after the update, transform every item with its new parameters (the next epoch of the
+// same call then needs no transform launch)
+hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
+                           bool do_transform = false);
 hipError_t launch_adam_reset(float *m, float *v, int32_t *step, int num_shapes, hipStream_t st);
 hipError_t launch_adam_only(const KArgs &a, hipStream_t st);
 hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, float *alpha_pad, int max_pixels,
@@ -136,6 +141,7 @@ constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 256;   // edge records a wave stages in LDS at a time (8 KiB)
+constexpr int kPixelBlock = 1024;  // pixels per workgroup of the per-pixel kernel (4 per thread)
 constexpr int kEpilogueCost = 16;  // per-pixel work after the scan, in edge evaluations (work partition)
 constexpr int kMaxVertsPerItem = 32767;
 constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point scale of the coverage accumulators

@@ -114,17 +114,12 @@ __device__ __forceinline__ void place_vertex(double c, double sn, double s, doub
   y = k * (sn * sx + c * sy);
 }
 
-__global__ __launch_bounds__(256) void k_transform(KArgs a) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (blockIdx.x == 0 && threadIdx.x < CNT_WORDS) a.counters[threadIdx.x] = 0;
-  if (a.step_inc != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.step_inc[0] = a.step_inc[0] + 1;
-  const int sid = blockIdx.x * 4 + wave;
-  if (sid >= a.num_shapes) return;
+// One wave transforms item sid with parameters p (the same in every lane).
+__device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_shape(LS, a.num_layouts, sid);
   const double k = (double)LS[b].k;
   const int W = LS[b].W, H = LS[b].H;
-  const float4 p = reinterpret_cast<const float4 *>(a.params)[sid];
   const int v0 = a.vert_off[sid];
   const int n = a.vert_off[sid + 1] - v0;
   const bool finite = isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w);
@@ -208,6 +203,14 @@ __global__ __launch_bounds__(256) void k_transform(KArgs a) {
     sr.pad = 0;
     a.shapes[sid] = sr;
   }
+}
+
+__global__ __launch_bounds__(256) void k_transform(KArgs a) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x < CNT_WORDS) a.counters[threadIdx.x] = 0;
+  const int sid = blockIdx.x * 4 + wave;
+  if (sid >= a.num_shapes) return;
+  transform_item(a, sid, lane, reinterpret_cast<const float4 *>(a.params)[sid]);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -568,6 +571,7 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
   const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
   const int sb = LS[b].shape_begin, se = LS[b].shape_end, nb = se - sb;
   const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
+  const int ntiles = ntx * LS[b].nty;
   const int x0 = txi * T, y0 = tyi * T;
   const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
   {
@@ -585,6 +589,7 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
     const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots);
     for (int q = tid; q < cnt; q += NT) {
       const int sid = s_list[q];
+      a.item_slot[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = slots + q;
       const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
       const int chunks = (r.n + 63) >> 6;
       const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost;
@@ -681,6 +686,7 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
   if (tid == 0) {
     prc[nt] = tot_c;
     prq[nt] = tot_q;
+    if (a.step_inc != nullptr) a.step_inc[0] = a.step_inc[0] + 1;
   }
 }
 
@@ -785,8 +791,10 @@ __device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int 
 // ------------------------------------------------------------------------------------------------
 // k_cover: coverage of every (unit, pixel) into the fixed-point accumulators.
 // ------------------------------------------------------------------------------------------------
+// The persistent kernels assume that all their workgroups are resident at once (kPersistWaves waves
+// per workgroup, four workgroups per CU): the second launch bound keeps four waves per SIMD.
 template <int T>
-__global__ __launch_bounds__(256) void k_cover(KArgs a) {
+__global__ __launch_bounds__(256, 4) void k_cover(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
@@ -828,61 +836,86 @@ __global__ __launch_bounds__(256) void k_cover(KArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// k_pixel: S, S_pad, loss terms (per tile) and dLoss/dS, dLoss/dS_pad per pixel.
+// k_pixel: S, S_pad, the loss terms (summed per block of kPixelBlock pixels of one layout) and
+// dLoss/dS, dLoss/dS_pad per pixel.  Each thread takes four pixels, kPixelBlock / 4 apart, with all
+// their loads issued together.
 // ------------------------------------------------------------------------------------------------
-template <int T, bool GRAD>
-__global__ __launch_bounds__(T *T) void k_pixel(KArgs a) {
-  constexpr int NT = T * T, NW = NT / 64;
-  __shared__ double s_loss[NW][5];
-  const int tile = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  cptr<LayoutRec> LS = konst(a.layouts);
-  const int b = layout_of_tile(LS, a.num_layouts, tile);
-  const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
-  const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
-  const int pxi = txi * T + tid % T, pyi = tyi * T + tid / T;
-  const bool valid = pxi < W && pyi < H;
-  const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
-  double S = 0.0, Sp = 0.0, M = 0.0;
-  if (valid) {
-    S = (double)a.acc[2 * pix] * kFixInv;
-    Sp = (double)a.acc[2 * pix + 1] * kFixInv;
-    M = (double)a.mask[pix];
-    if (a.cov_out) a.cov_out[pix] = (float)S;
-    if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
+__device__ __forceinline__ int layout_of_pblk(cptr<LayoutRec> L, int B, int blk) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L[mid].pblk_off <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-  const double yinv = (double)H - (pyi + 0.5);
-  const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
+  return lo;
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_pixel(KArgs a) {
+  constexpr int PER = kPixelBlock / 256;
+  __shared__ double s_loss[4][5];
+  const int blk = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  cptr<LayoutRec> LS = konst(a.layouts);
+  const int b = layout_of_pblk(LS, a.num_layouts, blk);
+  const int W = LS[b].W, H = LS[b].H;
+  const int npx = W * H;
+  const int base = (blk - LS[b].pblk_off) * kPixelBlock;
+  double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
+  if (GRAD && a.dloss) {
+    c_ov *= (double)a.dloss[5 * b + 0];
+    c_c *= (double)a.dloss[5 * b + 1];
+    c_f *= (double)a.dloss[5 * b + 2];
+    c_p *= (double)a.dloss[5 * b + 3];
+    c_d *= (double)a.dloss[5 * b + 4];
+  }
+  unsigned long long s0[PER], s1[PER];
+  float mk[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = base + k * 256 + tid;
+    s0[k] = s1[k] = 0ull;
+    mk[k] = 0.0f;
+    if (i < npx) {
+      const int64_t pix = LS[b].pix_off + i;
+      s0[k] = a.acc[2 * pix];
+      s1[k] = a.acc[2 * pix + 1];
+      mk[k] = a.mask[pix];
+    }
+  }
+  double term[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = base + k * 256 + tid;
+    if (i < npx) {
+      const int64_t pix = LS[b].pix_off + i;
+      const double S = (double)s0[k] * kFixInv, Sp = (double)s1[k] * kFixInv, M = (double)mk[k];
+      if (a.cov_out) a.cov_out[pix] = (float)S;
+      if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
+      const int pyi = i / W;
+      const double yinv = (double)H - (pyi + 0.5);
+      const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
+      term[0] += ov * ov;
+      term[1] += S * (1.0 - M);
+      term[2] += M * (un * un);
+      term[3] += pv * pv;
+      term[4] += S * yinv;
+      if (GRAD) {
+        const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
+        const double Gp = 2.0 * c_p * pv;
+        a.gbuf[pix] = make_double2(G, Gp);
+      }
+    }
+  }
   if (a.write_loss) {
-    double term[5];
-    term[0] = valid ? (double)a.w[0] * (ov * ov) : 0.0;
-    term[1] = valid ? (double)a.w[1] * (S * (1.0 - M)) : 0.0;
-    term[2] = valid ? (double)a.w[2] * (M * (un * un)) : 0.0;
-    term[3] = valid ? (double)a.w[3] * (pv * pv) : 0.0;
-    term[4] = valid ? (double)a.w[4] * (S * yinv) : 0.0;
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
-      const double v = wave_sum(term[t]);
+      const double v = wave_sum((double)a.w[t] * term[t]);
       if (l == 0) s_loss[w][t] = v;
     }
     __syncthreads();
-    if (tid < 5) {
-      double v = s_loss[0][tid];
-      for (int j = 1; j < NW; ++j) v += s_loss[j][tid];
-      a.tile_loss[(int64_t)tile * 5 + tid] = v;
-    }
-  }
-  if (GRAD && valid) {
-    double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
-    if (a.dloss) {
-      c_ov *= (double)a.dloss[5 * b + 0];
-      c_c *= (double)a.dloss[5 * b + 1];
-      c_f *= (double)a.dloss[5 * b + 2];
-      c_p *= (double)a.dloss[5 * b + 3];
-      c_d *= (double)a.dloss[5 * b + 4];
-    }
-    const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
-    const double Gp = 2.0 * c_p * pv;
-    a.gbuf[pix] = make_double2(G, Gp);
+    if (tid < 5) a.block_loss[(int64_t)blk * 5 + tid] = ((s_loss[0][tid] + s_loss[1][tid]) + s_loss[2][tid]) + s_loss[3][tid];
   }
 }
 
@@ -890,7 +923,7 @@ __global__ __launch_bounds__(T *T) void k_pixel(KArgs a) {
 // k_adjoint: per unit, the gradient terms of its pixels reduced to one partial per (tile, item).
 // ------------------------------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
+__global__ __launch_bounds__(256, 4) void k_adjoint(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
@@ -905,34 +938,79 @@ __global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
     const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
     const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
     const double cx = SR[item].cx, cy = SR[item].cy;
+    // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
-    if (staged && q + wk.jhi > a.code_cap) stage_edges(a.edges + eo, ec, S, lane);
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int j = wk.jlo; j < wk.jhi; ++j) {
-      int pxi, pyi;
+    if (q + wk.jhi <= a.code_cap) {
+      // every chunk of the piece has its nearest-edge codes: a three-stage pipeline over the chunks
+      // (codes two chunks ahead, the edge record and dLoss/dS one chunk ahead), since each chunk's
+      // loads depend on its codes and the wave has nothing else to cover their latency
+      const uint16_t *C = a.codes + q * 64 + lane;
+      const int j0 = wk.jlo, j1 = wk.jhi;
+      unsigned c_cur = C[(int64_t)j0 * 64];
+      unsigned c_nxt = j0 + 1 < j1 ? C[(int64_t)(j0 + 1) * 64] : 0u;
+      int px, py;
       bool in;
-      chunk_pixel(r, j, lane, pxi, pyi, in);
-      const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
-      int bi = 0;
-      bool par = false;
-      if (q + j < a.code_cap) {
-        const unsigned code = a.codes[(q + j) * 64 + lane];
-        bi = (int)(code & 0x7fffu);
-        par = (code & 0x8000u) != 0u;
-      } else {
-        scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
-        if (ec > 0) bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+      chunk_pixel(r, j0, lane, px, py, in);
+      EdgeD e_cur = a.edges_d[eo + (int)(c_cur & 0x7fffu)];
+      double2 g_cur = a.gbuf[wk.pix_off + (int64_t)py * wk.W + px];
+      for (int j = j0; j < j1; ++j) {
+        const unsigned c_far = j + 2 < j1 ? C[(int64_t)(j + 2) * 64] : 0u;
+        int pn_x = px, pn_y = py;
+        bool in_n = false;
+        EdgeD e_nxt = e_cur;
+        double2 g_nxt = g_cur;
+        if (j + 1 < j1) {
+          chunk_pixel(r, j + 1, lane, pn_x, pn_y, in_n);
+          e_nxt = a.edges_d[eo + (int)(c_nxt & 0x7fffu)];
+          g_nxt = a.gbuf[wk.pix_off + (int64_t)pn_y * wk.W + pn_x];
+        }
+        if (in) {
+          const double rx = px + 0.5 - cx, ry = py + 0.5 - cy;
+          const bool par = (c_cur & 0x8000u) != 0u;
+          const PairD pr = pair_eval(e_cur, rx, ry, par);
+          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y);
+          acc.x += t.x;
+          acc.y += t.y;
+          acc.z += t.z;
+          acc.w += t.w;
+        }
+        c_cur = c_nxt;
+        c_nxt = c_far;
+        e_cur = e_nxt;
+        g_cur = g_nxt;
+        px = pn_x;
+        py = pn_y;
+        in = in_n;
       }
-      if (ec > 0 && in) {
-        const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
-        const double2 g = a.gbuf[pix];
-        const EdgeD e = a.edges_d[eo + bi];
-        const PairD pr = pair_eval(e, rx, ry, par);
-        const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y);
-        acc.x += t.x;
-        acc.y += t.y;
-        acc.z += t.z;
-        acc.w += t.w;
+    } else {
+      if (staged) stage_edges(a.edges + eo, ec, S, lane);
+      for (int j = wk.jlo; j < wk.jhi; ++j) {
+        int pxi, pyi;
+        bool in;
+        chunk_pixel(r, j, lane, pxi, pyi, in);
+        const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
+        int bi = 0;
+        bool par = false;
+        if (q + j < a.code_cap) {
+          const unsigned code = a.codes[(q + j) * 64 + lane];
+          bi = (int)(code & 0x7fffu);
+          par = (code & 0x8000u) != 0u;
+        } else {
+          scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+          bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+        }
+        if (in) {
+          const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
+          const double2 g = a.gbuf[pix];
+          const EdgeD e = a.edges_d[eo + bi];
+          const PairD pr = pair_eval(e, rx, ry, par);
+          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y);
+          acc.x += t.x;
+          acc.y += t.y;
+          acc.z += t.z;
+          acc.w += t.w;
+        }
       }
     }
     acc.x = wave_sum(acc.x);
@@ -948,19 +1026,30 @@ __global__ __launch_bounds__(256) void k_adjoint(KArgs a) {
 // ------------------------------------------------------------------------------------------------
 // k_finalize: per-item gradient (fixed tile order) + optional Adam; per-layout loss.
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void adam_update(const KArgs &a, int sid, float4 g, float k) {
+// The parameters, moments and rim radius an Adam step of item sid reads (loaded ahead of the gradient).
+struct AdamIn {
+  float4 p, m, v;
+  float rho;
+};
+
+__device__ __forceinline__ AdamIn adam_load(const KArgs &a, int sid) {
+  AdamIn r;
+  r.p = reinterpret_cast<const float4 *>(a.param_io)[sid];
+  r.m = reinterpret_cast<const float4 *>(a.adam_m)[sid];
+  r.v = reinterpret_cast<const float4 *>(a.adam_v)[sid];
+  r.rho = a.rho ? a.rho[sid] : 0.0f;
+  return r;
+}
+
+__device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g, float k, const AdamIn &in) {
   const float t = (float)a.step[0];
   const float bc1 = 1.0f - powf(a.beta1, t), bc2 = 1.0f - powf(a.beta2, t);
-  const float rho = a.rho ? a.rho[sid] : 0.0f;
   const float lr_t = a.lr_px / k;
-  const float lr_r = rho > 0.0f ? a.lr_px / (k * rho) : 0.0f;
+  const float lr_r = in.rho > 0.0f ? a.lr_px / (k * in.rho) : 0.0f;
   const float gg[4] = {g.x, g.y, g.z, g.w};
   const float lr[4] = {lr_t, lr_t, lr_r, lr_r};
-  float4 *P = reinterpret_cast<float4 *>(a.param_io);
-  float4 *Mv = reinterpret_cast<float4 *>(a.adam_m);
-  float4 *Vv = reinterpret_cast<float4 *>(a.adam_v);
-  const float4 p4 = P[sid], m4 = Mv[sid], v4 = Vv[sid];
-  float pp[4] = {p4.x, p4.y, p4.z, p4.w}, mm[4] = {m4.x, m4.y, m4.z, m4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w};
+  float pp[4] = {in.p.x, in.p.y, in.p.z, in.p.w}, mm[4] = {in.m.x, in.m.y, in.m.z, in.m.w};
+  float vv[4] = {in.v.x, in.v.y, in.v.z, in.v.w};
   const float sqbc2 = sqrtf(bc2);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -969,13 +1058,14 @@ __device__ __forceinline__ void adam_update(const KArgs &a, int sid, float4 g, f
     const float denom = sqrtf(vv[j]) / sqbc2 + a.eps;
     pp[j] = pp[j] - (lr[j] / bc1) * mm[j] / denom;
   }
-  P[sid] = make_float4(pp[0], pp[1], pp[2], pp[3]);
-  Mv[sid] = make_float4(mm[0], mm[1], mm[2], mm[3]);
-  Vv[sid] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+  reinterpret_cast<float4 *>(a.param_io)[sid] = make_float4(pp[0], pp[1], pp[2], pp[3]);
+  reinterpret_cast<float4 *>(a.adam_m)[sid] = make_float4(mm[0], mm[1], mm[2], mm[3]);
+  reinterpret_cast<float4 *>(a.adam_v)[sid] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+  return make_float4(pp[0], pp[1], pp[2], pp[3]);
 }
 
 template <int T>
-__device__ void finalize_grad(const KArgs &a, bool do_adam) {
+__device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sid = blockIdx.x * 4 + wave;
   if (sid >= a.num_shapes) return;
@@ -984,41 +1074,29 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
   const int b = SR[sid].layout;
   const float k = SR[sid].k;
   const int4 bb = load_box(konst(a.bbox), sid);
-  const int ntx = LS[b].ntx, nb = LS[b].shape_end - LS[b].shape_begin;
+  AdamIn ain;
+  if (do_adam && lane == 0) ain = adam_load(a, sid);
+  const int ntx = LS[b].ntx, ntiles = ntx * LS[b].nty, nb = LS[b].shape_end - LS[b].shape_begin;
   const int tile_off = LS[b].tile_off;
   const int64_t list_off = LS[b].list_off;
+  const int32_t *slot_of = a.item_slot + list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
+  const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
   if (bb.x <= bb.z && bb.y <= bb.w) {
+    // every tile that the support box meets lists the item; its units' adjoint partials are summed
+    // in tile order, then chunk order
     const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
     for (int j = lane; j < nt; j += 64) {
-      const int ty = ty0 + j / tw, tx = tx0 + j % tw;
-      const int lt = ty * ntx + tx;
-      const int cnt = a.tile_count[tile_off + lt];
-      const int32_t *list = a.tile_list + list_off + (int64_t)lt * nb;
-      int lo = 0, hi = cnt - 1, slot = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = list[mid];
-        if (v == sid) {
-          slot = mid;
-          break;
-        }
-        if (v < sid)
-          lo = mid + 1;
-        else
-          hi = mid - 1;
-      }
-      if (slot >= 0) {
-        const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot];
-        const double4 *pp = a.partial + a.tile_pre[(a.total_tiles + 1) + tile_off + lt] + ax.z;
-        for (int c = 0; c < ax.x; ++c) {
-          const double4 v = pp[c];
-          acc.x += v.x;
-          acc.y += v.y;
-          acc.z += v.z;
-          acc.w += v.w;
-        }
+      const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
+      const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot_of[lt]];
+      const double4 *pp = a.partial + q0[lt] + ax.z;
+      for (int c = 0; c < ax.x; ++c) {
+        const double4 v = pp[c];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
       }
     }
   }
@@ -1026,11 +1104,20 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam) {
   acc.y = wave_sum(acc.y);
   acc.z = wave_sum(acc.z);
   acc.w = wave_sum(acc.w);
+  float4 pn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (lane == 0) {
     float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * acc.y), (float)acc.z, (float)acc.w);
     if (SR[sid].bad != 0) g = make_float4(NAN, NAN, NAN, NAN);
     if (a.grad_out) reinterpret_cast<float4 *>(a.grad_out)[sid] = g;
-    if (do_adam) adam_update(a, sid, g, k);
+    if (do_adam) pn = adam_update(a, sid, g, k, ain);
+  }
+  if (do_transform) {
+    // the next epoch of the same call starts from the updated parameters: transform them now
+    pn.x = __shfl(pn.x, 0, 64);
+    pn.y = __shfl(pn.y, 0, 64);
+    pn.z = __shfl(pn.z, 0, 64);
+    pn.w = __shfl(pn.w, 0, 64);
+    transform_item(a, sid, lane, pn);
   }
 }
 
@@ -1038,12 +1125,13 @@ __device__ void finalize_loss(const KArgs &a, int b) {
   __shared__ double s_part[4][5];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   cptr<LayoutRec> LS = konst(a.layouts);
-  const int t0 = LS[b].tile_off, nt = LS[b].ntx * LS[b].nty;
+  const int p0 = LS[b].pblk_off;
+  const int np = (int)(((int64_t)LS[b].W * LS[b].H + kPixelBlock - 1) / kPixelBlock);
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < nt; j += 256) {
-    const double *tl = a.tile_loss + (int64_t)(t0 + j) * 5;
+  for (int j = threadIdx.x; j < np; j += 256) {
+    const double *bl = a.block_loss + (int64_t)(p0 + j) * 5;
 #pragma unroll
-    for (int t = 0; t < 5; ++t) s[t] += tl[t];
+    for (int t = 0; t < 5; ++t) s[t] += bl[t];
   }
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
@@ -1059,10 +1147,10 @@ __device__ void finalize_loss(const KArgs &a, int b) {
 }
 
 template <int T>
-__global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int do_adam, int do_loss) {
+__global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int flags) {
   if ((int)blockIdx.x < grad_blocks) {
-    finalize_grad<T>(a, do_adam != 0);
-  } else if (do_loss) {
+    finalize_grad<T>(a, (flags & 1) != 0, (flags & 4) != 0);
+  } else if (flags & 2) {
     finalize_loss(a, blockIdx.x - grad_blocks);
   }
 }
@@ -1088,7 +1176,7 @@ __global__ __launch_bounds__(256) void k_adam(KArgs a) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_shape(LS, a.num_layouts, sid);
   const float4 g = reinterpret_cast<const float4 *>(a.grad_out)[sid];
-  adam_update(a, sid, g, LS[b].k);
+  adam_update(a, sid, g, LS[b].k, adam_load(a, sid));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1169,13 +1257,11 @@ hipError_t launch_cover(const KArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
-  if (a.total_tiles <= 0) return hipSuccess;
-  const dim3 g(a.total_tiles);
-  if (grad) {
-    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_pixel<T, true>), g, dim3(T * T), 0, st, a));
-  } else {
-    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_pixel<T, false>), g, dim3(T * T), 0, st, a));
-  }
+  if (a.total_pblk <= 0) return hipSuccess;
+  if (grad)
+    hipLaunchKernelGGL(k_pixel<true>, dim3(a.total_pblk), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_pixel<false>, dim3(a.total_pblk), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1184,12 +1270,13 @@ hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st) {
+hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
+                           bool do_transform) {
   const int gb = do_grad ? (a.num_shapes + 3) / 4 : 0;
   const int lb = do_loss ? a.num_layouts : 0;
   if (gb + lb == 0) return hipSuccess;
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, do_adam ? 1 : 0,
-                                              do_loss ? 1 : 0));
+  const int flags = (do_adam ? 1 : 0) | (do_loss ? 2 : 0) | (do_adam && do_transform ? 4 : 0);
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, flags));
   return hipGetLastError();
 }
 

@@ -164,6 +164,26 @@ def test_iterate_equals_fused_then_step():
     assert int(s1.item()) == 3 and int(s2.item()) == 3
 
 
+@pytest.mark.parametrize("tile", [8, 32])
+def test_iterate_n_equals_repeated_iterate(tile):
+    # inside collage_iterate_n the update kernel transforms the items for the next epoch; the result
+    # must be bitwise that of separate epochs
+    sc = S.random_scene(4, [(60, 44), (33, 47)], [12, 7], off_canvas=0.2)
+    _say("iterate_n", tile)
+    cs = CollageScene(sc, tile=tile)
+    p1 = cs.params_tensor()
+    m1, v1, s1 = cs.new_state()
+    for _ in range(5):
+        l1, g1 = cs.iterate(p1, m1, v1, s1)
+    p2 = cs.params_tensor()
+    m2, v2, s2 = cs.new_state()
+    l2, g2 = cs.iterate_n(p2, m2, v2, s2, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    assert int(s1.item()) == int(s2.item()) == 5
+
+
 def test_graph_replay_matches_eager():
     sc = S.config1(0)
     _say("graph")
