@@ -1,28 +1,30 @@
 // HIP kernels (gfx950, wave64) of the image-space collage hot path.
 //
-// One call is a short chain of launches with grids fixed by the scene:
-//   k_transform  one wave per item: eq. 2 applied to the outline (in double precision), float edge
+// One epoch is a short chain of launches with grids fixed by the scene:
+//   k_transform  one wave per item: eq. 2 applied to the outline in double precision; float edge
 //                records for the scan and double edge records for the per-pixel evaluation, both
-//                relative to the item's origin, the pixel box of the item's coverage support and the
-//                outline orientation.  Also clears the work counters.
+//                relative to the item's origin; the pixel box of the item's coverage support; the
+//                outline orientation.  (Within a multi-epoch call the update kernel does this for the
+//                next epoch.)
 //   k_bin        one workgroup per screen tile: the layout's items whose support box meets the tile,
-//                in item order (LDS list copied to the workspace); every (tile, item) becomes one
-//                work unit with a mask of the tile's 8 x 8 quadrants the item touches.  Clears the
-//                tile's coverage accumulators.
-//   k_cover      persistent waves pull work units from a global counter (so heavy and light regions
-//                balance across the whole chip); per unit and pixel: float32 scan of the item's edges
-//                (records read through the scalar cache, shared by the wave) for the nearest edge and
-//                the even-odd parity, then the signed distance to that edge and the coverage in double
-//                precision, added to the pixel's S and S_pad as 2^-40 fixed point with 64-bit integer
-//                atomics (exact, so the result does not depend on the order of the units).  Adjoint
-//                calls keep a 2-byte nearest-edge code per (unit, pixel).
-//   k_pixel      one thread per pixel: S, S_pad, the five loss terms (summed per tile in a fixed order)
-//                and dLoss/dS, dLoss/dS_pad.
-//   k_adjoint    persistent waves again: per unit, the gradient terms of its pixels (double) reduced to
-//                one partial per (tile, item).
-//   k_finalize   one wave per item sums its tiles' partials in a fixed order (gradient, then the
-//                optional Adam update); one workgroup per layout sums its tiles' loss partials.
-// Results are deterministic.
+//                in item order; each (tile, item) is a work unit, the box clipped to the tile, packed
+//                row by row into 64-pixel chunks.  Clears the tile's coverage accumulators.
+//   k_scan       one workgroup: prefix sums of the tiles' work costs and chunk counts.
+//   k_cover      persistent waves, each taking an equal share of the pass's cost (split at chunk
+//                granularity); per unit the wave stages the item's edge records in LDS, and per chunk
+//                every lane scans them in float32 for its pixel's nearest edge and crossing parity,
+//                then evaluates the signed distance and the coverage in double precision and adds
+//                them to S and S_pad as 2^-40 fixed point with 64-bit integer atomics (exact, so the
+//                result does not depend on the order of the work).  Backward calls keep a 2-byte
+//                nearest-edge code per (chunk, lane).
+//   k_pixel      S, S_pad, the five loss terms (summed per pixel block in a fixed order) and
+//                dLoss/dS, dLoss/dS_pad per pixel.
+//   k_adjoint    persistent waves again: per chunk, the gradient terms of its pixels (double), one
+//                partial per piece of a unit.
+//   k_finalize   one wave per item sums its units' partials in a fixed order (gradient, then the
+//                optional Adam update and the next epoch's transform); one workgroup per layout sums
+//                the loss blocks in a fixed order.
+// Results are bitwise reproducible.
 #include "collage_internal.h"
 
 #include <math.h>

@@ -288,6 +288,31 @@ def test_degenerate_scales():
         check_grad(_np(grad), g_ref)
 
 
+@pytest.mark.parametrize("code_capacity", [-1, 0])
+def test_items_with_more_edges_than_one_lds_stage(code_capacity):
+    # outlines of 300 and 700 edges are staged in LDS in segments of 256 edges (coverage, and the
+    # adjoint's rescan when codes are not kept)
+    rng = np.random.default_rng(8)
+    outlines = [S.regular_polygon(700, 14.0, 0.1), S.star_polygon(150, 12.0, 0.8),
+                S.jittered_bezier(rng, 12, 9.0), S.regular_polygon(7, 5.0)]
+    params = np.array([[30.3, 29.1, 0.2, 1.0], [44.7, 40.2, 0.4, 1.0], [20.2, 45.9, 0.1, 1.1],
+                       [52.6, 18.4, 1.3, 0.9]])
+    sc = S.multi_shape_scene(outlines, params, 70, 64, mask="disk", w_overlap=1, w_contain=1, w_fill=1,
+                             w_pad=1, r_pad=2.0, w_down=1e-3)
+    assert max(np.diff(sc.vert_off)) == 700
+    o = Oracle(sc)
+    S_, Sp, L = o.forward(sc.params)
+    g_ref = o.backward(sc.params)
+    for tile in (8, 16, 32):
+        _say("long outlines", tile, code_capacity)
+        cs = CollageScene(sc, tile=tile, code_capacity=code_capacity)
+        cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+        check_image(_np(cov), S_, "S")
+        check_image(_np(cov_pad), Sp, "S_pad")
+        check_loss(_np(loss), L)
+        check_grad(_np(grad), g_ref)
+
+
 def test_more_items_than_one_bin_chunk():
     # 1100 items in one layout: the binning kernel takes the layout in two LDS chunks (1024 + 76)
     sc = S.random_scene(21, [(96, 80)], [1100], radius=(1.5, 4.0), off_canvas=0.1)
