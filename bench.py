@@ -15,6 +15,7 @@ also transforms the items for the next epoch).  Prints one JSON line.  `value` i
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -85,6 +86,32 @@ def cpu_baseline(scene, level, budget_s=12.0, max_iters=2000):
     return {"value": n / dt, "unit": "it/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": f"{n} oracle epochs (forward, backward, Adam; FP64) of the same 512x512 / 500-item "
                       f"scene from the seed-0 layout, {dt:.1f} s"}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cover_512px_500items_traffic.md")
+
+
+def kernel_digest() -> str:
+    """Digest of the kernel sources: a traffic figure measured on other sources is not reported."""
+    h = hashlib.sha256()
+    for name in ("collage_kernels.hip", "collage_internal.h"):
+        with open(os.path.join(ROOT, "paper_2406_04008_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tile: int):
+    """HBM bytes per launch of the coverage kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size), or None when it was taken on other kernel
+    sources or another tile size."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fields = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
+        if fields.get("kernel_digest") != kernel_digest() or int(fields.get("tile", -1)) != tile:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def coarse_to_fine(sc):
@@ -165,6 +192,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the coarse-to-fine schedule and the batched-vs-loop comparison")
     ap.add_argument("--batched-steps", type=int, default=30)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="after the timed region, copy 256 MiB device to device (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
@@ -289,7 +318,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(cfg.tile),
             "ops_per_pair": OPS_PER_PAIR,
             "kernel_ms_mean": tile_ms,
             "kernel_ms_median": float(np.median(tiles_ms)),
@@ -298,6 +327,13 @@ def main():
         "cpu_baseline": None,
         "autotune_ms_per_epoch": tune_times,
     }
+    if args.calibration_copy:
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_extras:
         out["coarse_to_fine"] = coarse_to_fine(sc)
         out["batched"] = batched_vs_loop(args.batched_steps)

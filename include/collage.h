@@ -169,8 +169,8 @@ void collage_timer_destroy(collage_timer *timer);
  * `epochs` (1..65536) consecutive collage_iterate epochs in one call, on `stream`.  Equivalent to that
  * many collage_iterate calls; loss, grad and the optional images are those of the last epoch.  Within
  * the call, the update of each epoch also transforms the items for the next one (one launch fewer per
- * epoch).  With a non-NULL `timer` (at least `epochs` pairs), pair e is recorded around epoch e's
- * coverage kernel.  Errors: those of collage_iterate; COLLAGE_ERR_SIZE if the timer is too small.
+ * epoch).  With a non-NULL `timer` (at least `epochs` pairs), pair e is timestamped with the start and
+ * the end of epoch e's coverage kernel.  Errors: those of collage_iterate; COLLAGE_ERR_SIZE if the timer is too small.
  */
 int collage_iterate_n(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                       float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,

@@ -464,9 +464,7 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
   for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
     e = launch_bin(a, st);
     if (e == hipSuccess) e = launch_scan(a, st);
-    if (e == hipSuccess && timer) e = hipEventRecord(timer->start[i], st);
-    if (e == hipSuccess) e = launch_cover(a, st);
-    if (e == hipSuccess && timer) e = hipEventRecord(timer->stop[i], st);
+    if (e == hipSuccess) e = launch_cover(a, st, timer ? timer->start[i] : nullptr, timer ? timer->stop[i] : nullptr);
     if (e == hipSuccess) e = launch_pixel(a, true, st);
     if (e == hipSuccess) e = launch_adjoint(a, st);
     if (e == hipSuccess) e = launch_finalize(a, true, true, true, st, i + 1 < n);

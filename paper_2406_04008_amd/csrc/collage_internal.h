@@ -124,7 +124,8 @@ struct KArgs {
 hipError_t launch_transform(const KArgs &a, hipStream_t st);
 hipError_t launch_bin(const KArgs &a, hipStream_t st);
 hipError_t launch_scan(const KArgs &a, hipStream_t st);
-hipError_t launch_cover(const KArgs &a, hipStream_t st);
+// ev_start / ev_stop (both or neither): HIP events timestamped at the kernel's start and end
+hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
 // do_transform: after the update, transform every item with its new parameters (the next epoch of the

@@ -27,6 +27,8 @@
 // Results are bitwise reproducible.
 #include "collage_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace collage {
@@ -1253,8 +1255,14 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cover(const KArgs &a, hipStream_t st) {
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
+hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (ev_start) {
+    // the events are timestamped with the dispatch itself (kernel start and end)
+    COLLAGE_TILE_DISPATCH(T, hipExtLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, ev_start,
+                                                   ev_stop, 0, a));
+  } else {
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
+  }
   return hipGetLastError();
 }
 
