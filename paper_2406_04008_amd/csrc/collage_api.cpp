@@ -41,7 +41,7 @@ struct collage_scene {
   int64_t code_cap = 0;
   int64_t chunk_cap = 0;
   int32_t bin_chunk = kDefaultBinChunk;
-  int32_t persist_grid = 1;
+  int32_t cover_grid = 1, adjoint_grid = 1;
   uint32_t flags = 0;
   std::vector<LayoutRec> layouts;
   std::vector<int32_t> vert_off;
@@ -132,7 +132,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.unit_cap = (int32_t)s->unit_cap;
   a.chunk_cap = s->chunk_cap;
   a.code_cap = s->code_cap;
-  a.persist_grid = s->persist_grid;
+  a.cover_grid = s->cover_grid;
+  a.adjoint_grid = s->adjoint_grid;
   a.vert_off = s->d_vert_off;
   a.verts = s->verts;
   a.rho = s->rho;
@@ -157,6 +158,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.inv_tau = 1.0f / s->tau;
   a.r_cut = s->r_cut;
   a.r_pad = s->r_pad;
+  a.inv_tau_d = 1.0 / (double)s->tau;
+  a.pad_factor = std::exp(-(double)s->r_pad / (double)s->tau);
   for (int i = 0; i < 5; ++i) a.w[i] = s->w[i];
   return a;
 }
@@ -276,7 +279,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  s->persist_grid = cus * 4;
+  s->cover_grid = cus * kCoverBlocksPerCU;
+  s->adjoint_grid = cus * kAdjointBlocksPerCU;
   s->off_aux = off;
   off = align256(off + sizeof(int4) * (size_t)list);
   s->off_tcost = off;

@@ -58,7 +58,9 @@ struct alignas(16) EdgeD {
 
 // Work counters at the start of the workspace (zeroed by the transform kernel of every call).
 enum Counter { CNT_UNITS = 0, CNT_WORDS = 8 };
-constexpr int kPersistWaves = 4;  // waves per workgroup of the persistent kernels
+constexpr int kPersistWaves = 4;      // waves per workgroup of the persistent kernels
+constexpr int kCoverBlocksPerCU = 5;  // resident workgroups per CU: coverage kernel (LDS and VGPR bound)
+constexpr int kAdjointBlocksPerCU = 4;  // and adjoint kernel (VGPR bound)
 
 // Kernel arguments (one struct, passed by value).
 struct KArgs {
@@ -73,7 +75,8 @@ struct KArgs {
   int64_t chunk_cap;     // upper bound of the number of 64-pixel chunks of a pass
   int64_t code_cap;      // 64-pixel chunks whose nearest-edge codes are kept between the coverage and
                          // adjoint passes (the first code_cap chunks of the pass)
-  int32_t persist_grid;  // workgroups of the persistent kernels
+  int32_t cover_grid;    // workgroups of the persistent coverage kernel (all resident at once)
+  int32_t adjoint_grid;  // and of the persistent adjoint kernel
   const int32_t *vert_off;
   const float *verts;
   const float *rho;
@@ -109,6 +112,8 @@ struct KArgs {
   int32_t keep_codes;    // the coverage pass stores nearest-edge codes (adjoint calls)
   // constants
   float tau, inv_tau, r_cut, r_pad;
+  double inv_tau_d;      // 1 / tau
+  double pad_factor;     // e^(-r_pad / tau)
   float w[5];
   // finalize / Adam
   float *loss_out;
@@ -141,7 +146,7 @@ constexpr int kDefaultTile = 16;
 constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
-constexpr int kStageEdges = 256;   // edge records a wave stages in LDS at a time (8 KiB)
+constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
 constexpr int kPixelBlock = 1024;  // pixels per workgroup of the per-pixel kernel (4 per thread)
 constexpr int kEpilogueCost = 16;  // per-pixel work after the scan, in edge evaluations (work partition)
 constexpr int kMaxVertsPerItem = 32767;

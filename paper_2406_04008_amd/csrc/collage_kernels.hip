@@ -74,15 +74,6 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Logistic function and its derivative, a = 1 / (1 + e^-x) and da/dx = a (1 - a), both from
-// t = e^-|x| so that neither loses precision when a is close to 0 or 1.
-__device__ __forceinline__ void sigmoid_d(double x, double &a, double &da) {
-  const double t = exp(-fabs(x));
-  const double r = 1.0 / (1.0 + t);
-  a = x >= 0.0 ? r : t * r;
-  da = t * r * r;
-}
-
 __device__ __forceinline__ int layout_of_shape(cptr<LayoutRec> L, int B, int sid) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
@@ -308,7 +299,12 @@ __device__ __forceinline__ PairD pair_eval(const EdgeD &e, double rx, double ry,
 // (near the boundary between a vertex's fan and an edge's perpendicular strip), where the choice does
 // not change the distance much but does tilt the gradient direction.  So the nearest edge is decided
 // again in double among the scan's choice and its two neighbours (lowest index on exact ties).
-__device__ __forceinline__ int nearest_refined(const EdgeD *E, int ec, int bi, double rx, double ry) {
+struct Nearest {
+  int e;                 // the nearest edge
+  double d2, u, qx, qy;  // its squared distance, clamped parameter and p - nearest point
+};
+
+__device__ __forceinline__ Nearest nearest_refined(const EdgeD *E, int ec, int bi, double rx, double ry) {
   const int lo = bi == 0 ? ec - 1 : bi - 1, hi = bi + 1 == ec ? 0 : bi + 1;
   int c0 = lo, c1 = bi, c2 = hi;
   // visit in increasing index so that strict '<' keeps the lowest index on ties
@@ -327,41 +323,45 @@ __device__ __forceinline__ int nearest_refined(const EdgeD *E, int ec, int bi, d
     c0 = c1;
     c1 = t;
   }
+  Nearest n;
+  pair_d2(E[c0], rx, ry, n.d2, n.u, n.qx, n.qy);
+  n.e = c0;
   double d2, u, qx, qy;
-  pair_d2(E[c0], rx, ry, d2, u, qx, qy);
-  int best = c0;
-  double bd = d2;
   if (c1 != c0) {
     pair_d2(E[c1], rx, ry, d2, u, qx, qy);
-    if (d2 < bd) {
-      bd = d2;
-      best = c1;
-    }
+    if (d2 < n.d2) n = Nearest{c1, d2, u, qx, qy};
   }
   if (c2 != c1) {
     pair_d2(E[c2], rx, ry, d2, u, qx, qy);
-    if (d2 < bd) best = c2;
+    if (d2 < n.d2) n = Nearest{c2, d2, u, qx, qy};
   }
-  return best;
+  return n;
 }
 
-// Coverage of one item at one pixel from its signed distance: alpha, alpha_pad (0 past the cut-off).
-__device__ __forceinline__ void coverage(const KArgs &a, double sd, double &al, double &dal, double &alp,
-                                         double &dalp) {
-  const double inv_tau = 1.0 / (double)a.tau;
-  al = dal = alp = dalp = 0.0;
-  if (sd >= -(double)a.r_cut) sigmoid_d(sd * inv_tau, al, dal);
-  if (sd + (double)a.r_pad >= -(double)a.r_cut) sigmoid_d((sd + (double)a.r_pad) * inv_tau, alp, dalp);
-  dal *= inv_tau;
-  dalp *= inv_tau;
+// alpha and alpha_pad of one (pixel, item) from its signed distance, with one exponential: for
+// x = sd / tau, e^-(x + r_pad / tau) = e^-x pad_factor.  Wherever either is not cut to zero,
+// x >= -(r_cut + r_pad) / tau, so e^-x does not overflow.
+__device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double &al, double &alp) {
+  al = alp = 0.0;
+  if (sd + (double)a.r_pad < -(double)a.r_cut) return;
+  const double E = exp(-sd * a.inv_tau_d);
+  if (sd >= -(double)a.r_cut) al = 1.0 / (1.0 + E);
+  alp = 1.0 / (1.0 + E * a.pad_factor);
 }
 
 // Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
 // translation terms applied by the finalize kernel.  omega = G dalpha/dsd + G_pad dalpha_pad/dsd.
 __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
                                                  bool par, float orient, double G, double Gp) {
-  double al, dal, alp, dalp;
-  coverage(a, q.sd, al, dal, alp, dalp);
+  // d alpha / d sd and d alpha_pad / d sd from one exponential: with E = e^-x (x = sd / tau),
+  // sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used (x >= -(r_cut + r_pad) / tau)
+  double dal = 0.0, dalp = 0.0;
+  if (q.sd + (double)a.r_pad >= -(double)a.r_cut) {
+    const double E = exp(-q.sd * a.inv_tau_d), Ep = E * a.pad_factor;
+    const double r = 1.0 / (1.0 + E), rp = 1.0 / (1.0 + Ep);
+    if (q.sd >= -(double)a.r_cut) dal = E * r * r * a.inv_tau_d;
+    dalp = Ep * rp * rp * a.inv_tau_d;
+  }
   const double om = G * dal + Gp * dalp;
   double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
   if (om == 0.0 || q.d == 0.0) return t;
@@ -796,9 +796,10 @@ __device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int 
 // k_cover: coverage of every (unit, pixel) into the fixed-point accumulators.
 // ------------------------------------------------------------------------------------------------
 // The persistent kernels assume that all their workgroups are resident at once (kPersistWaves waves
-// per workgroup, four workgroups per CU): the second launch bound keeps four waves per SIMD.
+// per workgroup, k*BlocksPerCU workgroups per CU): the second launch bound keeps that many waves per
+// SIMD within the register file.
 template <int T>
-__global__ __launch_bounds__(256, 4) void k_cover(KArgs a) {
+__global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
@@ -824,11 +825,12 @@ __global__ __launch_bounds__(256, 4) void k_cover(KArgs a) {
       scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
       if (ec > 0) {
         const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
-        bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+        const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+        bi = nr.e;
         if (in) {
-          const PairD pr = pair_eval(a.edges_d[eo + bi], rx, ry, par);
-          double al, dal, alp, dalp;
-          coverage(a, pr.sd, al, dal, alp, dalp);
+          const double d = sqrt(nr.d2);
+          double al, alp;
+          coverage_pair(a, par ? d : -d, al, alp);
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
           if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
           if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
@@ -927,7 +929,7 @@ __global__ __launch_bounds__(256) void k_pixel(KArgs a) {
 // k_adjoint: per unit, the gradient terms of its pixels reduced to one partial per (tile, item).
 // ------------------------------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(256, 4) void k_adjoint(KArgs a) {
+__global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
@@ -1002,7 +1004,7 @@ __global__ __launch_bounds__(256, 4) void k_adjoint(KArgs a) {
           par = (code & 0x8000u) != 0u;
         } else {
           scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
-          bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+          bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry).e;
         }
         if (in) {
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
@@ -1209,10 +1211,9 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
     bool par;
     edge_scan(konst(a.edges) + eo, ec, pxi + 0.5f - SR[q].cxf, pyi + 0.5f - SR[q].cyf, bi, par);
     const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
-    bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
-    const PairD pr = pair_eval(a.edges_d[eo + bi], rx, ry, par);
-    double dal, dalp;
-    coverage(a, pr.sd, al, dal, alp, dalp);
+    const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
+    const double d = sqrt(nr.d2);
+    coverage_pair(a, par ? d : -d, al, alp);
   }
   alpha[off + pix] = (float)al;
   if (alpha_pad) alpha_pad[off + pix] = (float)alp;
@@ -1258,10 +1259,10 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st) {
 hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (ev_start) {
     // the events are timestamped with the dispatch itself (kernel start and end)
-    COLLAGE_TILE_DISPATCH(T, hipExtLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, ev_start,
+    COLLAGE_TILE_DISPATCH(T, hipExtLaunchKernelGGL(k_cover<T>, dim3(a.cover_grid), dim3(256), 0, st, ev_start,
                                                    ev_stop, 0, a));
   } else {
-    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_cover<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_cover<T>, dim3(a.cover_grid), dim3(256), 0, st, a));
   }
   return hipGetLastError();
 }
@@ -1276,7 +1277,7 @@ hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
 }
 
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_adjoint<T>, dim3(a.persist_grid), dim3(256), 0, st, a));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_adjoint<T>, dim3(a.adjoint_grid), dim3(256), 0, st, a));
   return hipGetLastError();
 }
 
