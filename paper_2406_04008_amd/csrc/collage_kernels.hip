@@ -1089,20 +1089,49 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
   const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
   if (bb.x <= bb.z && bb.y <= bb.w) {
-    // every tile that the support box meets lists the item; its units' adjoint partials are summed
-    // in tile order, then chunk order
+    // every tile that the support box meets lists the item; its units' adjoint partials (one per
+    // chunk) are spread over the lanes and summed by a fixed reduction
     const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
-    for (int j = lane; j < nt; j += 64) {
-      const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
-      const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot_of[lt]];
-      const double4 *pp = a.partial + q0[lt] + ax.z;
-      for (int c = 0; c < ax.x; ++c) {
-        const double4 v = pp[c];
-        acc.x += v.x;
-        acc.y += v.y;
-        acc.z += v.z;
-        acc.w += v.w;
+    for (int r0 = 0; r0 < nt; r0 += 64) {
+      // up to 64 tiles at a time, one per lane: the unit's chunk count and first partial
+      const int nl = min(nt - r0, 64), j = r0 + lane;
+      int cnt = 0;
+      long long first = 0;
+      if (j < nt) {
+        const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
+        const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot_of[lt]];
+        cnt = ax.x;
+        first = q0[lt] + ax.z;
+      }
+      int x = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const int pre = x - cnt, total = __shfl(x, 63, 64);
+      // then the chunks of those units, one per lane, all loads in flight together
+      for (int kb = 0; kb < total; kb += 64) {
+        const int kk = kb + lane;
+        int lo = 0, hi = nl - 1;  // the last tile whose first chunk is <= kk
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (__shfl(pre, mid, 64) <= kk)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const long long f = __shfl(first, lo, 64);
+        const int pt = __shfl(pre, lo, 64);
+        if (kk < total) {
+          const double4 v = a.partial[f + (kk - pt)];
+          acc.x += v.x;
+          acc.y += v.y;
+          acc.z += v.z;
+          acc.w += v.w;
+        }
       }
     }
   }

@@ -349,3 +349,23 @@ def test_batched_layouts_match_separate_scenes():
         assert torch.equal(c1, imgs[b].reshape(-1))
         assert torch.equal(l1[0], loss[b])
         assert torch.equal(g1, grad[lay.shape_begin:lay.shape_end])
+
+
+@pytest.mark.parametrize("tile", [32, 16])
+def test_full_batch_sampled_layouts(tile):
+    # the 64-layout batch at full resolution, in the benchmark's launch; the oracle evaluates a
+    # sample of its layouts on their own (layouts are independent)
+    sc = S.config4(0)
+    _say("full batch", sc.num_layouts, sc.num_shapes, "tile", tile)
+    cs = CollageScene(sc, tile=tile)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    imgs, imgs_pad = cs.layout_images(cov), cs.layout_images(cov_pad)
+    for b in (0, 17, 42, 63):
+        sub = sc.layout_subset(b)
+        o = Oracle(sub)
+        S_, Sp, L = o.forward(sub.params)
+        lay = sc.layouts[b]
+        check_image(_np(imgs[b]).reshape(-1), S_, f"S[{b}]")
+        check_image(_np(imgs_pad[b]).reshape(-1), Sp, f"S_pad[{b}]")
+        check_loss(_np(loss[b:b + 1]), L)
+        check_grad(_np(grad[lay.shape_begin:lay.shape_end]), o.backward(sub.params))
