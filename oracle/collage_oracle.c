@@ -15,6 +15,9 @@
  *     Euclidean signed distance to the closed outline (positive inside by the even-odd rule), with a
  *     hard zero once sd < -r_cut; a padded coverage alpha_pad = sigmoid((sd + r_pad) / tau) with the
  *     same cut-off on sd + r_pad.  S = sum_i alpha_i, S_pad = sum_i alpha_pad_i.
+ *     An open item (stroke half-width w > 0) is the polyline through its vertices (no closing
+ *     segment) thickened by a disk of radius w, transformed with the item: sd = k |s| w - d, where d
+ *     is the distance to the polyline.
  *   - Image-space losses (Sec. 4.2, eqs. for containment and non-overlap, in their differentiable
  *     reading) plus padding and the downward force of Sec. 5 ("Force Attraction"):
  *        L_ov   = sum_p relu(S - 1)^2           L_cont = sum_p S (1 - M)
@@ -52,6 +55,7 @@ typedef struct {
   double w[5];              /* overlap, contain, fill, pad, down */
   int32_t use_cutoff;       /* 1: hard zero below -r_cut (the definition); 0: no cut-off */
   int32_t use_bbox;         /* 1: skip pixels provably beyond the cut-off support (needs use_cutoff) */
+  const double *stroke;     /* [N] stroke half-width, canonical px (> 0: open polyline), or NULL */
 } oracle_scene;
 
 static int64_t pixel_offset(const oracle_scene *sc, int b) {
@@ -132,6 +136,58 @@ static sd_result signed_distance(double px, double py, const double *P, int n) {
   return r;
 }
 
+/* Euclidean distance to the open polyline P[0], ..., P[n-1] (segments m -> m + 1; one point if n = 1). */
+static sd_result polyline_distance(double px, double py, const double *P, int n) {
+  sd_result r;
+  double best = INFINITY;
+  int best_m = 0;
+  double best_u = 0.0;
+  const int ns = n > 1 ? n - 1 : 1;
+  for (int m = 0; m < ns; ++m) {
+    const double ax = P[2 * m], ay = P[2 * m + 1];
+    const int mn = n > 1 ? m + 1 : m;
+    const double ex = P[2 * mn] - ax, ey = P[2 * mn + 1] - ay;
+    const double ee = ex * ex + ey * ey;
+    double u = 0.0;
+    if (ee > 0.0) {
+      u = ((px - ax) * ex + (py - ay) * ey) / ee;
+      if (u < 0.0) u = 0.0;
+      if (u > 1.0) u = 1.0;
+    }
+    const double qx = ax + u * ex, qy = ay + u * ey;
+    const double d2 = (px - qx) * (px - qx) + (py - qy) * (py - qy);
+    if (d2 < best) {
+      best = d2;
+      best_m = m;
+      best_u = u;
+      r.qx = qx;
+      r.qy = qy;
+    }
+  }
+  r.d = sqrt(best);
+  r.sd = -r.d;
+  r.edge = best_m;
+  r.u = best_u;
+  r.inside = 0;
+  return r;
+}
+
+static int is_open(const oracle_scene *sc, int q) { return sc->stroke && sc->stroke[q] > 0.0; }
+
+/* Stroke radius of item q in level px: the half-width transformed with the item, k |s| w. */
+static double stroke_radius(const oracle_scene *sc, const double *params, int q, double k) {
+  return is_open(sc, q) ? k * fabs(params[4 * q + 3]) * sc->stroke[q] : 0.0;
+}
+
+/* Signed distance of pixel (px, py) for item q with transformed vertices P (n of them). */
+static sd_result item_distance(const oracle_scene *sc, const double *params, int q, double k, double px, double py,
+                               const double *P, int n) {
+  if (!is_open(sc, q)) return signed_distance(px, py, P, n);
+  sd_result r = polyline_distance(px, py, P, n);
+  r.sd = stroke_radius(sc, params, q, k) - r.d;
+  return r;
+}
+
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 /* Derivative of the logistic function, sigma'(x) = sigma(x) (1 - sigma(x)), written as
@@ -161,8 +217,8 @@ static void coverage(const oracle_scene *sc, double sd, double *a, double *da, d
 }
 
 /* Pixel index range that can receive non-zero coverage from polygon P (cut-off on), inclusive. */
-static void support_box(const oracle_scene *sc, const double *P, int n, int W, int H, int *x0, int *y0, int *x1,
-                        int *y1) {
+static void support_box(const oracle_scene *sc, const double *P, int n, double extra, int W, int H, int *x0, int *y0,
+                        int *x1, int *y1) {
   double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
   for (int m = 0; m < n; ++m) {
     if (P[2 * m] < mnx) mnx = P[2 * m];
@@ -170,7 +226,7 @@ static void support_box(const oracle_scene *sc, const double *P, int n, int W, i
     if (P[2 * m + 1] < mny) mny = P[2 * m + 1];
     if (P[2 * m + 1] > mxy) mxy = P[2 * m + 1];
   }
-  const double ext = sc->r_cut + (sc->r_pad > 0.0 ? sc->r_pad : 0.0) + 1.0;
+  const double ext = sc->r_cut + (sc->r_pad > 0.0 ? sc->r_pad : 0.0) + extra + 1.0;
   double fx0 = floor(mnx - ext - 0.5), fx1 = ceil(mxx + ext - 0.5);
   double fy0 = floor(mny - ext - 0.5), fy1 = ceil(mxy + ext - 0.5);
   if (fx0 < 0) fx0 = 0;
@@ -191,11 +247,13 @@ static void support_box(const oracle_scene *sc, const double *P, int n, int W, i
 }
 
 typedef struct {
-  double *P;  /* transformed vertices of all items, [V*2] */
-  int *box;   /* [N*4] x0, y0, x1, y1 */
+  double *P;             /* transformed vertices of all items, [V*2] */
+  int *box;              /* [N*4] x0, y0, x1, y1 */
+  const double *params;  /* [N*4] the parameters they were transformed with */
 } prepared;
 
 static void prepare(const oracle_scene *sc, const double *params, prepared *pr) {
+  pr->params = params;
   pr->P = (double *)malloc(sizeof(double) * 2 * (sc->V > 0 ? sc->V : 1));
   pr->box = (int *)malloc(sizeof(int) * 4 * (sc->N > 0 ? sc->N : 1));
   for (int b = 0; b < sc->B; ++b) {
@@ -204,8 +262,8 @@ static void prepare(const oracle_scene *sc, const double *params, prepared *pr) 
       double *P = pr->P + 2 * sc->vert_off[i];
       transform_item(sc, params, i, sc->scale[b], P);
       if (sc->use_bbox && sc->use_cutoff) {
-        support_box(sc, P, n, sc->width[b], sc->height[b], &pr->box[4 * i], &pr->box[4 * i + 1],
-                    &pr->box[4 * i + 2], &pr->box[4 * i + 3]);
+        support_box(sc, P, n, stroke_radius(sc, params, i, sc->scale[b]), sc->width[b], sc->height[b],
+                    &pr->box[4 * i], &pr->box[4 * i + 1], &pr->box[4 * i + 2], &pr->box[4 * i + 3]);
       } else {
         pr->box[4 * i] = 0;
         pr->box[4 * i + 1] = 0;
@@ -240,7 +298,7 @@ static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, 
           if (!in_box(pr->box + 4 * q, i, j)) continue;
           const int n = sc->vert_off[q + 1] - sc->vert_off[q];
           if (n == 0) continue;
-          const sd_result r = signed_distance(px, py, pr->P + 2 * sc->vert_off[q], n);
+          const sd_result r = item_distance(sc, pr->params, q, sc->scale[b], px, py, pr->P + 2 * sc->vert_off[q], n);
           double a, da, ap, dap;
           coverage(sc, r.sd, &a, &da, &ap, &dap);
           s += a;
@@ -310,7 +368,7 @@ int oracle_render(const oracle_scene *sc, const double *params, int first, int c
       for (int i = 0; i < W; ++i) {
         double a = 0.0, ap = 0.0, da, dap;
         if (n > 0 && in_box(pr.box + 4 * q, i, j)) {
-          const sd_result r = signed_distance(i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
+          const sd_result r = item_distance(sc, params, q, sc->scale[b], i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
           coverage(sc, r.sd, &a, &da, &ap, &dap);
         }
         if (alpha) alpha[out + (int64_t)j * W + i] = a;
@@ -340,7 +398,7 @@ int oracle_signed_distance(const oracle_scene *sc, const double *params, int fir
       for (int i = 0; i < W; ++i) {
         sd_result r;
         if (n > 0) {
-          r = signed_distance(i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
+          r = item_distance(sc, params, q, sc->scale[b], i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
         } else {
           r.sd = -INFINITY;
           r.edge = -1;
@@ -360,7 +418,8 @@ int oracle_signed_distance(const oracle_scene *sc, const double *params, int fir
  * dLoss/dS(p) and dLoss/dS_pad(p) follow from the loss definitions (relu'(0) = 0).  Each item's
  * contribution at pixel p is omega * dsd/dparam, omega = G * dalpha/dsd + G_pad * dalpha_pad/dsd.
  * dsd/dparam is taken through the vertices: for the nearest point q = a + u (b - a) on the nearest
- * edge (a, b), with g = (p - q)/|p - q| and sign +1 inside / -1 outside,
+ * edge (a, b), with g = (p - q)/|p - q| and sign +1 inside / -1 outside (always -1 for an open
+ * item, whose sd = k |s| w - d also has the direct term d sd / ds = k w sign(s)),
  *     dsd/da = -sign (1 - u) g,  dsd/db = -sign u g          (0 < u < 1)
  *     dsd/da = -sign g (u = 0),  dsd/db = -sign g (u = 1)    (nearest point is an end point)
  * and through eq. 2, v' = k (R(theta) s v + t):
@@ -409,15 +468,19 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
         const double th = params[4 * q + 2], s = params[4 * q + 3];
         const double c = cos(th), sn = sin(th);
         const int *bx = pr.box + 4 * q;
+        const int open = is_open(sc, q);
         for (int j = bx[1]; j <= bx[3]; ++j)
           for (int i = bx[0]; i <= bx[2]; ++i) {
             const int64_t idx = off + (int64_t)j * W + i;
             const double px = i + 0.5, py = j + 0.5;
-            const sd_result r = signed_distance(px, py, P, n);
+            const sd_result r = item_distance(sc, params, q, k, px, py, P, n);
             double a, da, ap, dap;
             coverage(sc, r.sd, &a, &da, &ap, &dap);
             const double omega = G[idx] * da + Gp[idx] * dap;
-            if (omega == 0.0 || r.d == 0.0) continue;
+            if (omega == 0.0) continue;
+            /* an open item's stroke radius k |s| w grows with |s| */
+            if (open) g[3] += omega * k * sc->stroke[q] * (s > 0.0 ? 1.0 : (s < 0.0 ? -1.0 : 0.0));
+            if (r.d == 0.0) continue;
             const double sgn = r.inside ? 1.0 : -1.0;
             const double gx = (px - r.qx) / r.d, gy = (py - r.qy) / r.d;
             /* dsd/d(vertex) for the two end points of the nearest edge */
@@ -432,7 +495,7 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
               wa = 1.0 - r.u;
               wb = r.u;
             }
-            const int ma = r.edge, mb = (r.edge + 1 == n) ? 0 : r.edge + 1;
+            const int ma = r.edge, mb = open ? (n > 1 ? r.edge + 1 : r.edge) : ((r.edge + 1 == n) ? 0 : r.edge + 1);
             const int vm[2] = {ma, mb};
             const double wv[2] = {wa, wb};
             for (int e = 0; e < 2; ++e) {

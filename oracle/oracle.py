@@ -28,6 +28,7 @@ class _OracleScene(ctypes.Structure):
         ("tau", ctypes.c_double), ("r_cut", ctypes.c_double), ("r_pad", ctypes.c_double),
         ("w", ctypes.c_double * 5),
         ("use_cutoff", ctypes.c_int32), ("use_bbox", ctypes.c_int32),
+        ("stroke", _dp),
     ]
 
 
@@ -94,6 +95,8 @@ class Oracle:
         for i, wv in enumerate(scene.weights()):
             s.w[i] = wv
         s.use_cutoff, s.use_bbox = int(use_cutoff), int(use_bbox and use_cutoff)
+        self.stroke = None if getattr(scene, "stroke", None) is None else _d(scene.stroke)
+        s.stroke = _ptr(self.stroke) if self.stroke is not None and self.stroke.size else None
         self._s = s
 
     @property

@@ -61,6 +61,10 @@ class Scene:
     layouts: List[Layout]
     levels: List[int]  # level sides for coarse-to-fine; scale k = level / level_ref
     level_ref: int
+    # per item stroke half-width in canonical px: 0 for a closed outline (coverage from the signed
+    # distance, positive inside); > 0 for an open polyline stroked to that half-width (coverage from
+    # k |s| w - d, with d the distance to the polyline); None = every item is a closed outline
+    stroke: Optional[np.ndarray] = None
     tau: float = 0.5
     r_cut: float = 8.0
     r_pad: float = 0.0
@@ -119,7 +123,7 @@ class Scene:
 
     def signature(self) -> str:
         h = hashlib.sha1()
-        for a in (self.verts, self.vert_off, self.params):
+        for a in (self.verts, self.vert_off, self.params) + (() if self.stroke is None else (self.stroke,)):
             h.update(np.ascontiguousarray(a).tobytes())
         for L in self.layouts:
             h.update(np.array([L.width_ref, L.height_ref, L.shape_begin, L.shape_end], np.int64).tobytes())
@@ -131,6 +135,7 @@ class Scene:
         v0, v1 = int(self.vert_off[lay.shape_begin]), int(self.vert_off[lay.shape_end])
         return dataclasses.replace(
             self, name=f"{self.name}[{b}]", verts=self.verts[v0:v1],
+            stroke=None if self.stroke is None else self.stroke[lay.shape_begin:lay.shape_end],
             vert_off=(self.vert_off[lay.shape_begin:lay.shape_end + 1] - v0).astype(np.int32),
             rho=self.rho[lay.shape_begin:lay.shape_end], params=self.params[lay.shape_begin:lay.shape_end],
             layouts=[Layout(lay.width_ref, lay.height_ref, 0, lay.num_shapes, lay.ellipses, lay.rects, lay.full)])
@@ -294,16 +299,31 @@ def place_in_mask(rng: np.random.Generator, mask: np.ndarray, count: int) -> np.
 # Assembly
 # ----------------------------------------------------------------------------------------------------
 def assemble(name: str, outlines: Sequence[np.ndarray], params: np.ndarray, layouts: List[Layout],
-             levels: List[int], level_ref: int, **consts) -> Scene:
-    outlines = [recentre(np.asarray(P, np.float64)) for P in outlines]
+             levels: List[int], level_ref: int, stroke: Optional[Sequence[float]] = None, **consts) -> Scene:
+    """Items with stroke > 0 are open polylines: centred on their vertex mean (a polyline has no area),
+    rim radius max |v| + stroke."""
+    w = np.zeros(len(outlines)) if stroke is None else np.asarray(stroke, np.float64)
+    outlines = [(np.asarray(P, np.float64) - np.asarray(P, np.float64).mean(0)) if w[i] > 0 else
+                recentre(np.asarray(P, np.float64)) for i, P in enumerate(outlines)]
     counts = [P.shape[0] for P in outlines]
     vert_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     verts = (np.concatenate(outlines, 0) if outlines else np.zeros((0, 2))).astype(np.float32)
-    rho = np.array([np.sqrt((np.asarray(P, np.float32).astype(np.float64) ** 2).sum(1)).max() for P in outlines]
-                   if outlines else [], np.float32)
+    rho = np.array([np.sqrt((np.asarray(P, np.float32).astype(np.float64) ** 2).sum(1)).max() + w[i]
+                    for i, P in enumerate(outlines)] if outlines else [], np.float32)
     return Scene(name=name, verts=np.ascontiguousarray(verts), vert_off=vert_off, rho=rho,
                  params=np.ascontiguousarray(params, np.float32).reshape(-1, 4), layouts=layouts,
-                 levels=levels, level_ref=level_ref, **consts)
+                 levels=levels, level_ref=level_ref,
+                 stroke=None if stroke is None else np.ascontiguousarray(w, np.float32), **consts)
+
+
+def random_walk_polyline(rng: np.random.Generator, vertices: int, step_lo: float, step_hi: float) -> np.ndarray:
+    """An open polyline: `vertices` points, each step of length U(step_lo, step_hi) in a uniform direction."""
+    steps = rng.uniform(step_lo, step_hi, vertices - 1)
+    ang = rng.uniform(0.0, TWO_PI, vertices - 1)
+    P = np.zeros((vertices, 2))
+    P[1:, 0] = np.cumsum(steps * np.cos(ang))
+    P[1:, 1] = np.cumsum(steps * np.sin(ang))
+    return P
 
 
 def config1(seed: int = 0) -> Scene:
@@ -379,13 +399,31 @@ def config4(seed: int = 0, num_layouts: int = 64) -> Scene:
                     steps_per_level=300, seed=seed)
 
 
+def config5(seed: int = 0, num_shapes: int = 2000) -> Scene:
+    """Open shapes: 2048 x 2048 canvas (coarse-to-fine 256 -> 512 -> 1024 -> 2048, reference 2048), a
+    container made of 10 ellipses and 10 rotated rectangles (sizes U(30, 90) x 2048 / 256), 2000 open
+    polylines of 3..12 vertices (random-walk steps U(3, 15) px) stroked to half-width 1.5 px, padding 2 px,
+    downward force weight 1e-3."""
+    rng = np.random.default_rng(seed)
+    W = H = 2048
+    f = W / 256.0
+    lay = Layout(W, H, 0, num_shapes, ellipses=random_ellipses(rng, 10, W, H, 30.0 * f, 90.0 * f),
+                 rects=random_rects(rng, 10, W, H, 30.0 * f, 90.0 * f))
+    nv = rng.integers(3, 13, num_shapes)
+    outlines = [random_walk_polyline(rng, int(n), 3.0, 15.0) for n in nv]
+    params = place_in_mask(rng, container_mask(lay, W, H, 1.0), num_shapes)
+    return assemble("config5", outlines, params, [lay], [256, 512, 1024, 2048], 2048,
+                    stroke=np.full(num_shapes, 1.5), tau=0.5, r_cut=8.0, r_pad=2.0, w_overlap=1.0,
+                    w_contain=1.0, w_fill=1.0, w_pad=1.0, w_down=1e-3, steps_per_level=300, seed=seed)
+
+
 def random_scene(seed: int, sizes: Sequence[tuple], shapes_per_layout: Sequence[int], kinds=("poly", "star", "bezier"),
                  radius=(3.0, 12.0), r_pad: float = 2.0, w_pad: float = 1.0, w_down: float = 1e-3,
                  off_canvas: float = 0.0, name: str = "random") -> Scene:
     """Generic test scenes: any canvas sizes (ragged w.r.t. tiles), mixed outline kinds, random
     scale in [0.7, 1.4], and optionally a fraction of items pushed partly or wholly off the canvas."""
     rng = np.random.default_rng(seed)
-    outlines, params, layouts = [], [], []
+    outlines, params, layouts, stroke = [], [], [], []
     begin = 0
     for (W, H), n in zip(sizes, shapes_per_layout):
         ell = random_ellipses(rng, 3, W, H, 0.15 * min(W, H), 0.45 * min(W, H))
@@ -393,12 +431,17 @@ def random_scene(seed: int, sizes: Sequence[tuple], shapes_per_layout: Sequence[
         for _ in range(n):
             kind = kinds[int(rng.integers(0, len(kinds)))]
             r = float(rng.uniform(*radius))
+            w = 0.0
             if kind == "poly":
                 outlines.append(regular_polygon(int(rng.integers(3, 20)), r, float(rng.uniform(0, TWO_PI))))
             elif kind == "star":
                 outlines.append(star_polygon(int(rng.integers(5, 13)), r, float(rng.uniform(0.4, 0.8))))
+            elif kind == "open":
+                outlines.append(random_walk_polyline(rng, int(rng.integers(2, 9)), 0.3 * r, 0.9 * r))
+                w = float(rng.uniform(0.6, 2.5))
             else:
                 outlines.append(jittered_bezier(rng, int(rng.integers(4, 9)), r))
+            stroke.append(w)
         p = place_in_mask(rng, container_mask(lay, W, H, 1.0), n)
         p[:, 3] = rng.uniform(0.7, 1.4, n)
         if off_canvas > 0 and n > 0:
@@ -408,8 +451,9 @@ def random_scene(seed: int, sizes: Sequence[tuple], shapes_per_layout: Sequence[
         layouts.append(lay)
         begin += n
     P = np.concatenate(params, 0) if params else np.zeros((0, 4))
-    return assemble(name, outlines, P, layouts, [1], 1, tau=0.5, r_cut=8.0, r_pad=r_pad, w_overlap=1.0,
-                    w_contain=1.0, w_fill=1.0, w_pad=w_pad, w_down=w_down, seed=seed)
+    return assemble(name, outlines, P, layouts, [1], 1, stroke=stroke if "open" in kinds else None, tau=0.5,
+                    r_cut=8.0, r_pad=r_pad, w_overlap=1.0, w_contain=1.0, w_fill=1.0, w_pad=w_pad, w_down=w_down,
+                    seed=seed)
 
 
 def single_shape_scene(outline: np.ndarray, width: int, height: int, t, theta: float = 0.0, s: float = 1.0,
@@ -433,7 +477,7 @@ def single_shape_scene(outline: np.ndarray, width: int, height: int, t, theta: f
 
 
 def multi_shape_scene(outlines: Sequence[np.ndarray], params: np.ndarray, width: int, height: int,
-                      mask: str = "none", **consts) -> Scene:
+                      mask: str = "none", stroke: Optional[Sequence[float]] = None, **consts) -> Scene:
     if mask == "full":
         lay = Layout(width, height, 0, len(outlines), full=True)
     elif mask == "disk":
@@ -441,11 +485,11 @@ def multi_shape_scene(outlines: Sequence[np.ndarray], params: np.ndarray, width:
         lay = Layout(width, height, 0, len(outlines), ellipses=np.array([[width / 2, height / 2, r, r, 0.0]]))
     else:
         lay = Layout(width, height, 0, len(outlines))
-    sc = assemble("multi", outlines, np.asarray(params, np.float64), [lay], [1], 1)
+    sc = assemble("multi", outlines, np.asarray(params, np.float64), [lay], [1], 1, stroke=stroke)
     return dataclasses.replace(sc, **consts)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 
 def make_scene(config_id: int, seed: int = 0) -> Scene:

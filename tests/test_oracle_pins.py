@@ -342,3 +342,61 @@ def test_empty_and_offcanvas_items():
     assert S_.max() == 0.0 and L[0, 0] == 0 and L[0, 1] == 0 and L[0, 4] == 0
     assert L[0, 2] == pytest.approx(sc.w_fill * sc.masks()[0].sum())
     assert np.all(o.backward(p) == 0.0)
+
+
+# --------------------------------------------------------------------------------------------------
+# Open items: a polyline thickened by a disk of radius w (transformed with the item)
+# --------------------------------------------------------------------------------------------------
+def _stadium(L, w, c, theta, s=1.0, size=48):
+    seg = np.array([[-L / 2, 0.0], [L / 2, 0.0]])
+    return S.multi_shape_scene([seg], np.array([[c[0], c[1], theta, s]]), size, size, stroke=[w],
+                               w_overlap=0, w_contain=1, w_fill=0)
+
+
+def test_open_segment_distance_closed_form():
+    """sd = s w - dist(p, segment): in the segment's frame, dist = hypot(max(|x'| - s L / 2, 0), y')."""
+    L, w, th, s, c = 14.6, 1.7, 0.37, 1.2, (23.41, 22.73)
+    sc = _stadium(L, w, c, th, s)
+    sd = Oracle(sc).signed_distance(sc.params)[0].reshape(48, 48)
+    t = sc.params[0].astype(np.float64)
+    j, i = np.mgrid[0:48, 0:48]
+    dx, dy = i + 0.5 - t[0], j + 0.5 - t[1]
+    xr = math.cos(t[2]) * dx + math.sin(t[2]) * dy
+    yr = -math.sin(t[2]) * dx + math.cos(t[2]) * dy
+    # the scene stores the end points and the half-width as float32
+    half, wf = float(sc.verts[1, 0]), float(sc.stroke[0])
+    assert float(sc.verts[0, 0]) == -half and float(sc.verts[0, 1]) == 0.0 == float(sc.verts[1, 1])
+    ref = t[3] * wf - np.hypot(np.maximum(np.abs(xr) - t[3] * half, 0.0), yr)
+    assert np.abs(sd - ref).max() < 1e-9
+
+
+def test_open_P1_stadium_area_closed_form():
+    """sum_p alpha = 2 w L + pi w^2 + pi^3 tau^2 / 3: the inner and outer parallel bodies of a stadium
+    have perimeters P -/+ 2 pi x, as for a smooth convex outline."""
+    L, w = 14.6, 6.0
+    area = 2 * w * L + math.pi * w * w
+
+    def f(c):
+        sc = _stadium(L, w, c, 0.31)
+        return Oracle(sc).forward(sc.params)[2][0, 1]
+
+    val = _offset_average(f, (23.9, 23.3))
+    excess = math.pi ** 3 * TAU ** 2 / 3
+    assert abs(val - (area + excess)) < 1e-3, (val, area + excess)
+
+
+def test_open_P3_scale_derivative():
+    """d(sum alpha)/ds = 2 A s: the stroke radius scales with the item (a dropped d(k|s|w)/ds term
+    fails this by 4 w (w + L) s)."""
+    L, w, s = 14.6, 4.0, 1.3
+    area = 2 * w * L + math.pi * w * w
+    sc = _stadium(L, w, (24.21, 23.67), 0.2, s, size=64)
+    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0])
+    assert abs(g[0, 3] - 2 * area * s) / (2 * area * s) < 2e-3, (g[0, 3], 2 * area * s)
+    assert abs(g[0, 0]) < 2e-3 * area and abs(g[0, 1]) < 2e-3 * area and abs(g[0, 2]) < 2e-3 * area
+
+
+def test_open_P7_backward_vs_central_differences():
+    sc = S.random_scene(12, [(56, 48)], [7], kinds=("open", "star", "open"), radius=(4.0, 9.0))
+    assert sc.stroke is not None and (sc.stroke > 0).sum() >= 3
+    _fd_check(sc)
