@@ -73,11 +73,17 @@ typedef struct collage_scene_desc {
   const int32_t *layout_shapes; /* host [B+1], item ranges: [0] = 0, nondecreasing, [B] = N */
   const int32_t *vert_offset;   /* host [N+1], vertex ranges: [0] = 0, nondecreasing, [N] = V;
                                    at most 32767 vertices per item */
-  const float *verts;           /* device [V,2], closed outlines in the item frame (canonical px),
-                                   edge m joins vertex m and vertex m+1 (the last joins the first) */
+  const float *verts;           /* device [V,2], outlines in the item frame (canonical px); for a
+                                   closed item edge m joins vertex m and vertex m+1 (the last joins
+                                   the first), for an open item only consecutive vertices are joined */
   const float *rho;             /* device [N], rim radius of each item (canonical px); used only by
                                    the update (rotation and scale learning rates); may be NULL */
   const float *mask;            /* device, packed [sum W*H] container masks in [0, 1] */
+  const float *stroke;          /* device [N], stroke half-width w of each item (canonical px): 0 for
+                                   a closed outline (signed distance positive inside, even-odd rule),
+                                   > 0 for an open polyline thickened by a disk of radius w and
+                                   transformed with the item (signed distance k |s| w - d); NULL =
+                                   every item closed */
   float tau;                    /* sigmoid temperature, level px, > 0 */
   float r_cut;                  /* coverage cut-off, level px, >= 0 */
   float r_pad;                  /* padding offset, level px, >= 0 */

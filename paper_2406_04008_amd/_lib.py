@@ -31,7 +31,7 @@ class SceneDesc(ctypes.Structure):
         ("num_layouts", ctypes.c_int32), ("num_shapes", ctypes.c_int32), ("num_verts", ctypes.c_int32),
         ("layout_width", _i32p), ("layout_height", _i32p), ("layout_scale", _f32p), ("layout_shapes", _i32p),
         ("vert_offset", _i32p),
-        ("verts", _vp), ("rho", _vp), ("mask", _vp),
+        ("verts", _vp), ("rho", _vp), ("mask", _vp), ("stroke", _vp),
         ("tau", ctypes.c_float), ("r_cut", ctypes.c_float), ("r_pad", ctypes.c_float),
         ("w_overlap", ctypes.c_float), ("w_contain", ctypes.c_float), ("w_fill", ctypes.c_float),
         ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float),

@@ -60,6 +60,9 @@ class CollageScene:
         self.rho = torch.from_numpy(np.ascontiguousarray(scene.rho, np.float32)).to(dev)
         m = scene.packed_mask(level) if mask is None else np.ascontiguousarray(mask, np.float32).reshape(-1)
         self.mask = torch.from_numpy(m).to(dev)
+        self.stroke = None
+        if getattr(scene, "stroke", None) is not None and scene.num_shapes > 0:
+            self.stroke = torch.from_numpy(np.ascontiguousarray(scene.stroke, np.float32)).to(dev)
         d = _lib.SceneDesc()
         d.num_layouts, d.num_shapes, d.num_verts = self.B, self.N, scene.num_verts
         d.layout_width = self._w.ctypes.data_as(_lib._i32p)
@@ -70,6 +73,7 @@ class CollageScene:
         d.verts = self.verts.data_ptr() if self.verts.numel() else None
         d.rho = self.rho.data_ptr() if self.rho.numel() else None
         d.mask = self.mask.data_ptr()
+        d.stroke = self.stroke.data_ptr() if self.stroke is not None else None
         d.tau, d.r_cut, d.r_pad = scene.tau, scene.r_cut, scene.r_pad
         d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down = scene.weights()
         d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags

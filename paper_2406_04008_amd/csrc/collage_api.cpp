@@ -45,7 +45,7 @@ struct collage_scene {
   uint32_t flags = 0;
   std::vector<LayoutRec> layouts;
   std::vector<int32_t> vert_off;
-  const float *verts = nullptr, *rho = nullptr, *mask = nullptr;
+  const float *verts = nullptr, *rho = nullptr, *mask = nullptr, *stroke = nullptr;
   float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
   float w[5] = {1, 1, 1, 0, 0};
   int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_pblk = 0;
@@ -138,6 +138,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.verts = s->verts;
   a.rho = s->rho;
   a.mask = s->mask;
+  a.stroke = s->stroke;
   a.counters = reinterpret_cast<int32_t *>(w + s->off_counters);
   a.shapes = reinterpret_cast<ShapeRec *>(w + s->off_shapes);
   a.bbox = reinterpret_cast<int4 *>(w + s->off_bbox);
@@ -204,6 +205,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->verts = desc->verts;
   s->rho = desc->rho;
   s->mask = desc->mask;
+  s->stroke = desc->stroke;
   s->tau = desc->tau;
   s->r_cut = desc->r_cut;
   s->r_pad = desc->r_pad;

@@ -28,10 +28,12 @@ struct alignas(16) ShapeRec {
   float s;           // uniform scale parameter
   float orient;      // +1 if the outline is counter-clockwise in (x, y) coordinates, -1 otherwise
   int32_t edge_off;  // first edge record (= first vertex of the item)
-  int32_t edge_cnt;  // edges (= vertices) of the item
+  int32_t edge_cnt;  // edges of the item: its vertices (closed), one fewer (open, at least 1)
   int32_t layout;
   int32_t bad;       // 1 if a parameter is not finite (the item is skipped, its gradient is NaN)
-  int32_t pad;
+  int32_t open;      // 1: open polyline, sd = sw - d; 0: closed outline, sd = +-d (even-odd)
+  double sw;         // open: stroke radius k |s| w in level px
+  double sw_ds;      // open: d sw / d s = k w sign(s)
 };
 
 // Per edge (a, b) of an item, in level px relative to the item's origin (cx, cy).
@@ -81,6 +83,7 @@ struct KArgs {
   const float *verts;
   const float *rho;
   const float *mask;
+  const float *stroke;   // [N] stroke half-width (canonical px), or null (every item closed)
   const float *params;
   // transform outputs
   ShapeRec *shapes;

@@ -123,11 +123,16 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
   const double s = finite ? (double)p.w : 1.0;
   const double cx = k * (double)p.x, cy = k * (double)p.y;
   const float2 *V = reinterpret_cast<const float2 *>(a.verts) + v0;
+  // an open item has edges between consecutive vertices only (a single vertex: one point edge)
+  const float wst = a.stroke ? a.stroke[sid] : 0.0f;
+  const bool open = wst > 0.0f;
+  const int ec = open ? (n > 1 ? n - 1 : n) : n;
   double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY, area2 = 0.0;
-  for (int m = lane; m < n; m += 64) {
+  for (int m = lane; m < ec; m += 64) {
+    const int mb = open ? min(m + 1, n - 1) : (m + 1 == n ? 0 : m + 1);
     double ax, ay, bx, by;
     place_vertex(c, sn, s, k, V[m], ax, ay);
-    place_vertex(c, sn, s, k, V[m + 1 == n ? 0 : m + 1], bx, by);
+    place_vertex(c, sn, s, k, V[mb], bx, by);
     const double ex = bx - ax, ey = by - ay;
     const double ee = ex * ex + ey * ey;
     const double inv = ee > 0.0 ? 1.0 / ee : 0.0;
@@ -149,17 +154,17 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
     rd.inv_ee = inv;
     // d v' / d s = k R(theta) v for both end points (exact also when s = 0)
     {
-      const float2 va = V[m], vb = V[m + 1 == n ? 0 : m + 1];
+      const float2 va = V[m], vb = V[mb];
       rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
       rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
       rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
       rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
     }
     a.edges_d[v0 + m] = rd;
-    mnx = fmin(mnx, ax);
-    mxx = fmax(mxx, ax);
-    mny = fmin(mny, ay);
-    mxy = fmax(mxy, ay);
+    mnx = fmin(mnx, fmin(ax, bx));
+    mxx = fmax(mxx, fmax(ax, bx));
+    mny = fmin(mny, fmin(ay, by));
+    mxy = fmax(mxy, fmax(ay, by));
     area2 += ax * by - bx * ay;
   }
   mnx = wave_min(mnx);
@@ -167,8 +172,11 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
   mxx = wave_max(mxx);
   mxy = wave_max(mxy);
   area2 = wave_sum(area2);
+  // stroke radius of an open item: the half-width transformed with the item, and its derivative in s
+  const double sw = open ? k * fabs(s) * (double)wst : 0.0;
+  const double sw_ds = open ? k * (double)wst * (s > 0.0 ? 1.0 : (s < 0.0 ? -1.0 : 0.0)) : 0.0;
   if (lane == 0) {
-    const double ext = (double)a.r_cut + fmax((double)a.r_pad, 0.0);
+    const double ext = (double)a.r_cut + fmax((double)a.r_pad, 0.0) + sw;
     int4 box = make_int4(1, 1, 0, 0);  // empty
     if (n > 0 && finite) {
       // pixel centres i + 1/2 in [cx + mnx - ext, cx + mxx + ext] (widened by 1e-6 px against
@@ -192,10 +200,12 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
     sr.s = p.w;
     sr.orient = area2 >= 0.0 ? 1.0f : -1.0f;
     sr.edge_off = v0;
-    sr.edge_cnt = n;
+    sr.edge_cnt = ec;
     sr.layout = b;
     sr.bad = finite ? 0 : 1;
-    sr.pad = 0;
+    sr.open = open ? 1 : 0;
+    sr.sw = sw;
+    sr.sw_ds = sw_ds;
     a.shapes[sid] = sr;
   }
 }
@@ -351,8 +361,11 @@ __device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double 
 
 // Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
 // translation terms applied by the finalize kernel.  omega = G dalpha/dsd + G_pad dalpha_pad/dsd.
+// For an open item (sw_ds != 0 or open) q.sd = sw - d, par is false (the gradient of -d), and the
+// stroke radius adds d sd / d s = sw_ds.
 __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
-                                                 bool par, float orient, double G, double Gp) {
+                                                 bool par, float orient, double G, double Gp, bool open,
+                                                 double sw_ds) {
   // d alpha / d sd and d alpha_pad / d sd from one exponential: with E = e^-x (x = sd / tau),
   // sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used (x >= -(r_cut + r_pad) / tau)
   double dal = 0.0, dalp = 0.0;
@@ -364,7 +377,10 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
   }
   const double om = G * dal + Gp * dalp;
   double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (om == 0.0 || q.d == 0.0) return t;
+  if (om == 0.0) return t;
+  const double stroke_term = open ? om * sw_ds : 0.0;
+  t.w = stroke_term;
+  if (q.d == 0.0) return t;
   double nx, ny;
   if (q.u > 0.0 && q.u < 1.0) {
     // nearest point inside the edge: grad sd is the unit edge normal, oriented (inside ? +1 : -1)
@@ -372,7 +388,7 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
     // not reliable, but the product of the two is the outline orientation
     const double il = sqrt(e.inv_ee);
     double sg = (double)orient;
-    if (q.d >= 1e-4) {
+    if (q.d >= 1e-4 || open) {
       const double side = q.qy * e.ex - q.qx * e.ey;
       sg = (par == (side > 0.0)) ? 1.0 : -1.0;
     }
@@ -387,7 +403,7 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
   t.y = om * ny;
   t.z = om * (nx * ry - ny * rx);
   // d sd / d s = -n . (k R (v_a + u (v_b - v_a))): the nearest point of the unscaled outline
-  t.w = -om * (nx * (e.kra_x + q.u * e.kre_x) + ny * (e.kra_y + q.u * e.kre_y));
+  t.w = stroke_term - om * (nx * (e.kra_x + q.u * e.kre_x) + ny * (e.kra_y + q.u * e.kre_y));
   return t;
 }
 
@@ -814,6 +830,8 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
     const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
     const float cxf = SR[item].cxf, cyf = SR[item].cyf;
     const double cx = SR[item].cx, cy = SR[item].cy;
+    const bool open = SR[item].open != 0;
+    const double sw = SR[item].sw;
     const bool staged = ec <= kStageEdges;
     if (staged) stage_edges(a.edges + eo, ec, S, lane);
     for (int j = wk.jlo; j < wk.jhi; ++j) {
@@ -830,7 +848,7 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
         if (in) {
           const double d = sqrt(nr.d2);
           double al, alp;
-          coverage_pair(a, par ? d : -d, al, alp);
+          coverage_pair(a, open ? sw - d : (par ? d : -d), al, alp);
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
           if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
           if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
@@ -944,6 +962,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
     const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
     const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
     const double cx = SR[item].cx, cy = SR[item].cy;
+    const bool open = SR[item].open != 0;
+    const double sw = SR[item].sw, sw_ds = SR[item].sw_ds;
     // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -973,9 +993,10 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
         }
         if (in) {
           const double rx = px + 0.5 - cx, ry = py + 0.5 - cy;
-          const bool par = (c_cur & 0x8000u) != 0u;
-          const PairD pr = pair_eval(e_cur, rx, ry, par);
-          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y);
+          const bool par = !open && (c_cur & 0x8000u) != 0u;
+          PairD pr = pair_eval(e_cur, rx, ry, par);
+          if (open) pr.sd = sw - pr.d;
+          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y, open, sw_ds);
           acc.x += t.x;
           acc.y += t.y;
           acc.z += t.z;
@@ -1010,8 +1031,10 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
           const double2 g = a.gbuf[pix];
           const EdgeD e = a.edges_d[eo + bi];
-          const PairD pr = pair_eval(e, rx, ry, par);
-          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y);
+          if (open) par = false;
+          PairD pr = pair_eval(e, rx, ry, par);
+          if (open) pr.sd = sw - pr.d;
+          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y, open, sw_ds);
           acc.x += t.x;
           acc.y += t.y;
           acc.z += t.z;
@@ -1242,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
     const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
     const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
     const double d = sqrt(nr.d2);
-    coverage_pair(a, par ? d : -d, al, alp);
+    coverage_pair(a, SR[q].open ? SR[q].sw - d : (par ? d : -d), al, alp);
   }
   alpha[off + pix] = (float)al;
   if (alpha_pad) alpha_pad[off + pix] = (float)alp;

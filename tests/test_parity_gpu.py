@@ -30,6 +30,9 @@ SCENES = {
     "config1": lambda: S.config1(0),
     "ragged": lambda: S.random_scene(3, [(37, 29), (50, 61), (16, 16), (23, 9)], [4, 9, 1, 0], off_canvas=0.3),
     "config2": lambda: S.config2(0),
+    # open stroked polylines mixed with closed outlines, ragged canvases, some items off canvas
+    "open": lambda: S.random_scene(6, [(71, 53), (40, 66)], [11, 8], kinds=("open", "poly", "open", "star"),
+                                   radius=(3.0, 10.0), off_canvas=0.2),
 }
 
 
@@ -108,7 +111,7 @@ def test_metric_scene_levels(level, tile, code_capacity):
 
 
 def test_render_parity(oracles):
-    for name in ("config1", "ragged"):
+    for name in ("config1", "ragged", "open"):
         sc, o = oracles(name)
         _say("render", name)
         cs = CollageScene(sc)
@@ -232,6 +235,37 @@ def test_gradient_vs_central_differences_config2():
     for c in range(4):
         err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
         assert err.max() <= 1e-4, (c, err)
+
+
+def test_open_items_vs_central_differences():
+    sc = SCENES["open"]()
+    _say("fd open")
+    cs = CollageScene(sc)
+    p = cs.params_tensor().requires_grad_(True)
+    CollageLoss.apply(p, cs).sum().backward()
+    o = Oracle(sc)
+    items = [i for i in range(sc.num_shapes) if sc.stroke[i] > 0][:6]
+    fd = o.fd_gradient(sc.params, shapes=items)
+    g = _np(p.grad)
+    floor = 0.01 * np.abs(o.backward(sc.params)).max(0)
+    for c in range(4):
+        err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
+        assert err.max() <= 1e-4, (c, err)
+
+
+@pytest.mark.parametrize("level,tile", [(256, 16), (2048, 32)])
+def test_open_scene_levels(level, tile):
+    """2000 stroked polylines on the 2048 x 2048 scene at its coarsest and finest levels."""
+    sc = S.config5(0)
+    _say("config5 level", level, "tile", tile)
+    o = Oracle(sc, level=level)
+    cs = CollageScene(sc, level=level, tile=tile)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_image(_np(cov_pad), Sp, "S_pad")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
 
 
 def test_edge_cases():
