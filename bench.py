@@ -38,20 +38,25 @@ OPS_PER_PAIR = 20
 
 def support_pairs(scene, params, level):
     """Algorithmic (pixel, edge) pairs of one scan: for every item, the pixels whose centres lie in its
-    vertex bounding box widened by r_cut + r_pad (clipped to its canvas), times its edge count."""
+    vertex bounding box widened by r_cut + r_pad (and an open item's stroke radius), clipped to its
+    canvas, times its edge count."""
     w, h, k, off = scene.layout_arrays(level)
-    ext = scene.r_cut + max(scene.r_pad, 0.0)
     V = scene.verts.astype(np.float64)
     vo = scene.vert_off.astype(np.int64)
-    cnt = np.diff(vo)
+    nv = np.diff(vo)
+    stroke = np.zeros(scene.num_shapes) if scene.stroke is None else scene.stroke.astype(np.float64)
+    # an open item (stroke > 0) has one edge fewer than vertices (at least one)
+    cnt = np.where(stroke > 0, np.maximum(nv - 1, np.minimum(nv, 1)), nv)
     P = np.asarray(params, np.float64).reshape(-1, 4)
     lay = np.searchsorted(off, np.arange(scene.num_shapes), side="right") - 1
     kk = k.astype(np.float64)[lay]
-    rep = np.repeat(np.arange(scene.num_shapes), cnt)
+    rep = np.repeat(np.arange(scene.num_shapes), nv)
     c, sn = np.cos(P[rep, 2]), np.sin(P[rep, 2])
     x = kk[rep] * (P[rep, 3] * (c * V[:, 0] - sn * V[:, 1]) + P[rep, 0])
     y = kk[rep] * (P[rep, 3] * (sn * V[:, 0] + c * V[:, 1]) + P[rep, 1])
     starts = vo[:-1]
+    # support: r_cut + r_pad beyond the vertex box, plus an open item's stroke radius k |s| w
+    ext = scene.r_cut + max(scene.r_pad, 0.0) + kk * np.abs(P[:, 3]) * stroke
     i0 = np.maximum(np.ceil(np.minimum.reduceat(x, starts) - ext - 0.5), 0)
     i1 = np.minimum(np.floor(np.maximum.reduceat(x, starts) + ext - 0.5), w[lay] - 1)
     j0 = np.maximum(np.ceil(np.minimum.reduceat(y, starts) - ext - 0.5), 0)
@@ -115,8 +120,8 @@ def measured_traffic(tile: int):
 
 
 def coarse_to_fine(sc):
-    """The whole schedule of the metric scene (128 -> 256 -> 512 -> 1024, 300 epochs each), one captured
-    hipGraph per level, launch configurations autotuned per level."""
+    """The whole coarse-to-fine schedule of a scene (300 epochs per level), one captured hipGraph per
+    level, launch configurations autotuned per level."""
     import torch
 
     from paper_2406_04008_amd import autotune
@@ -127,9 +132,14 @@ def coarse_to_fine(sc):
     sched.run(keep_level_params=False)  # warm-up (instantiated graphs, caches)
     res = sched.run(keep_level_params=False)
     assert np.all(np.isfinite(res.params)), "non-finite parameters after the schedule"
-    return {"epochs": res.epochs, "gpu_s": res.gpu_ms / 1e3, "it_per_s": res.epochs / (res.gpu_ms / 1e3),
+    last = sched.levels[-1]
+    pairs = support_pairs(sc, sc.params, last)
+    return {"scene": sc.name, "epochs": res.epochs, "gpu_s": res.gpu_ms / 1e3,
+            "it_per_s": res.epochs / (res.gpu_ms / 1e3),
             "levels": [{"level": l.level, "tile": l.tile, "ms_per_epoch": l.gpu_ms / l.steps,
-                        "final_loss": [float(x) for x in l.loss.sum(0)]} for l in res.levels]}
+                        "final_loss": [float(x) for x in l.loss.sum(0)]} for l in res.levels],
+            "finest_level_pixel_edge_pairs_seed0": pairs,
+            "finest_level_pixel_edge_evals_per_s": 2.0 * pairs / (res.levels[-1].gpu_ms / 1e3 / res.levels[-1].steps)}
 
 
 def batched_vs_loop(steps):
@@ -336,6 +346,8 @@ def main():
         del src, dst
     if not args.no_extras:
         out["coarse_to_fine"] = coarse_to_fine(sc)
+        # open stroked polylines: 2000 on 2048 x 2048, schedule 256 -> 512 -> 1024 -> 2048
+        out["open_shapes"] = coarse_to_fine(scenes.config5(0))
         out["batched"] = batched_vs_loop(args.batched_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.level)

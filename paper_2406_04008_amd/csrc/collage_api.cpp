@@ -48,7 +48,7 @@ struct collage_scene {
   const float *verts = nullptr, *rho = nullptr, *mask = nullptr, *stroke = nullptr;
   float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
   float w[5] = {1, 1, 1, 0, 0};
-  int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_pblk = 0;
+  int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_pblk = 0, total_rows = 0, row_list_total = 0;
   int32_t max_canvas = 0;
   // device tables owned by the scene
   LayoutRec *d_layouts = nullptr;
@@ -56,7 +56,7 @@ struct collage_scene {
   // workspace layout
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_islot = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_list = 0, off_islot = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0;
   size_t ws_bytes = 0;
 };
@@ -127,6 +127,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.num_shapes = s->N;
   a.total_tiles = (int32_t)s->total_tiles;
   a.total_pblk = (int32_t)s->total_pblk;
+  a.total_rows = (int32_t)s->total_rows;
+  a.rowbin = s->list_total > kRowBinTests ? 1 : 0;
   a.tile = s->tile;
   a.bin_chunk = s->bin_chunk;
   a.unit_cap = (int32_t)s->unit_cap;
@@ -148,6 +150,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.block_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
   a.item_slot = reinterpret_cast<int32_t *>(w + s->off_islot);
+  a.row_count = reinterpret_cast<int32_t *>(w + s->off_rcount);
+  a.row_list = reinterpret_cast<int32_t *>(w + s->off_rlist);
   a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
@@ -216,7 +220,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->w[4] = desc->w_down;
   s->vert_off.assign(desc->vert_offset, desc->vert_offset + s->N + 1);
   s->layouts.resize(s->B);
-  int64_t pix = 0, tiles = 0, list = 0, pblk = 0;
+  int64_t pix = 0, tiles = 0, list = 0, pblk = 0, rows = 0, rlist = 0;
   for (int b = 0; b < s->B; ++b) {
     LayoutRec &L = s->layouts[b];
     std::memset(&L, 0, sizeof(L));
@@ -231,6 +235,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     L.list_off = list;
     L.k = desc->layout_scale[b];
     L.pblk_off = (int32_t)pblk;
+    L.row_off = (int32_t)rows;
+    L.row_list_off = rlist;
+    rows += L.nty;
+    rlist += (int64_t)L.nty * (L.shape_end - L.shape_begin);
     pblk += ((int64_t)L.W * L.H + kPixelBlock - 1) / kPixelBlock;
     pix += (int64_t)L.W * L.H;
     tiles += (int64_t)L.ntx * L.nty;
@@ -244,6 +252,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->total_pixels = pix;
   s->total_tiles = tiles;
   s->total_pblk = pblk;
+  s->total_rows = rows;
+  s->row_list_total = rlist;
   s->list_total = list;
   // every (tile, item) pair is one work unit: at most one per list entry
   s->unit_cap = list;
@@ -277,6 +287,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + sizeof(int32_t) * (size_t)list);
   s->off_islot = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
+  s->off_rcount = off;
+  off = align256(off + sizeof(int32_t) * (size_t)rows);
+  s->off_rlist = off;
+  off = align256(off + sizeof(int32_t) * (size_t)(list > kRowBinTests ? rlist : 0));
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)

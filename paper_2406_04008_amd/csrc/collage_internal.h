@@ -17,7 +17,8 @@ struct alignas(16) LayoutRec {
   int64_t pix_off;      // first pixel in packed images
   int64_t list_off;     // first entry of this layout's per-tile item lists (capacity: items of the layout per tile)
   float k;              // level scale
-  float pad1, pad2, pad3;
+  int32_t row_off;      // first global tile row of the layout
+  int64_t row_list_off; // first entry of this layout's per-row item lists (capacity: items per row)
 };
 
 // Per item, written by the transform kernel every call.
@@ -95,6 +96,10 @@ struct KArgs {
   int32_t *tile_count;
   int32_t *tile_list;
   int32_t *item_slot;    // per layout [items][tiles]: the item's slot in the tile's list (set where listed)
+  int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
+  int32_t total_rows;    // tile rows over all layouts
+  int32_t *row_count;    // [rows] items whose support box meets the row band
+  int32_t *row_list;     // per layout [tile rows][items]: those items, in item order
   int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
                          // chunks of the tile's earlier units, 0)
   int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units
@@ -130,7 +135,7 @@ struct KArgs {
 
 // Launchers (collage_kernels.hip).  Each returns hipGetLastError() of its launches.
 hipError_t launch_transform(const KArgs &a, hipStream_t st);
-hipError_t launch_bin(const KArgs &a, hipStream_t st);
+hipError_t launch_bin(const KArgs &a, hipStream_t st);  // (with the row pass first when a.rowbin)
 hipError_t launch_scan(const KArgs &a, hipStream_t st);
 // ev_start / ev_stop (both or neither): HIP events timestamped at the kernel's start and end
 hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
@@ -150,6 +155,7 @@ constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
+constexpr int64_t kRowBinTests = 1 << 21;  // box tests (tiles x items) above which the row pass is used
 constexpr int kPixelBlock = 1024;  // pixels per workgroup of the per-pixel kernel (4 per thread)
 constexpr int kEpilogueCost = 16;  // per-pixel work after the scan, in edge evaluations (work partition)
 constexpr int kMaxVertsPerItem = 32767;

@@ -408,16 +408,18 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
 }
 
 // Bins items [cb, ce) of a layout whose support box meets the tile rectangle, in item order.
+// Candidates are items cb .. ce - 1, or with src the items src[cb] .. src[ce - 1] (in item order).
 template <int NT>
 __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1, int y1, int *s_list, int *s_wcnt,
-                         int32_t *glist) {
+                         int32_t *glist, const int32_t *src = nullptr) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   int count = 0;
   for (int base = cb; base < ce; base += NT) {
-    const int sid = base + tid;
+    const int pos = base + tid;
+    const int sid = pos < ce ? (src ? src[pos] : pos) : 0;
     bool hit = false;
-    if (sid < ce) {
+    if (pos < ce) {
       const int4 bb = a.bbox[sid];
       // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
       hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x1 || bb.z < x0 || bb.y > y1 || bb.w < y0);
@@ -578,11 +580,45 @@ __device__ __forceinline__ Rect unit_rect(int4 bb, int tx0, int ty0, int T) {
 __device__ __forceinline__ int global_wave() { return uniform((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6))); }
 
 // ------------------------------------------------------------------------------------------------
+// k_rowbin: per tile row of a layout, the ordered list of items whose support box meets the row band
+// (large scenes: the tiles then test only their row's items instead of every item of the layout).
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ int layout_of_row(cptr<LayoutRec> L, int B, int row) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L[mid].row_off <= row)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_rowbin(KArgs a) {
+  __shared__ int s_list[kMaxBinChunk];
+  __shared__ int s_wcnt[4];
+  const int row = blockIdx.x;
+  cptr<LayoutRec> LS = konst(a.layouts);
+  const int b = layout_of_row(LS, a.num_layouts, row);
+  const int tyi = row - LS[b].row_off;
+  const int sb = LS[b].shape_begin, se = LS[b].shape_end, nb = se - sb;
+  int32_t *out = a.row_list + LS[b].row_list_off + (int64_t)tyi * nb;
+  int n = 0;
+  for (int cb = sb; cb < se; cb += kMaxBinChunk) {
+    const int ce = min(cb + kMaxBinChunk, se);
+    n += bin_chunk<256>(a, cb, ce, 0, tyi * T, LS[b].W - 1, tyi * T + T - 1, s_list, s_wcnt, out + n);
+  }
+  if (threadIdx.x == 0) a.row_count[row] = n;
+}
+
+// ------------------------------------------------------------------------------------------------
 // k_bin: per tile, the ordered item list and one work unit per (tile, item).
 // ------------------------------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
-  constexpr int NT = T * T, NW = NT / 64;
+__global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
+  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64;
   __shared__ int s_list[kMaxBinChunk];
   __shared__ int s_wcnt[NW];
   const int tile = blockIdx.x, tid = threadIdx.x;
@@ -594,8 +630,8 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
   const int ntiles = ntx * LS[b].nty;
   const int x0 = txi * T, y0 = tyi * T;
   const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
-  {
-    const int pxi = x0 + tid % T, pyi = y0 + tid / T;
+  for (int q = tid; q < T * T; q += NT) {
+    const int pxi = x0 + q % T, pyi = y0 + q / T;
     if (pxi < W && pyi < H) {
       const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
       a.acc[2 * pix] = 0ull;
@@ -604,9 +640,13 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
   }
   int slots = 0;
   long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
-  for (int cb = sb; cb < se; cb += a.bin_chunk) {
-    const int ce = min(cb + a.bin_chunk, se);
-    const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots);
+  // candidates: every item of the layout, or the items listed for the tile's row
+  const int32_t *src = a.rowbin ? a.row_list + LS[b].row_list_off + (int64_t)tyi * nb : nullptr;
+  const int c0 = a.rowbin ? 0 : sb, c1 = a.rowbin ? a.row_count[LS[b].row_off + tyi] : se;
+  for (int cb = c0; cb < c1; cb += a.bin_chunk) {
+    const int ce = min(cb + a.bin_chunk, c1);
+    const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots,
+                                  src);
     for (int q = tid; q < cnt; q += NT) {
       const int sid = s_list[q];
       a.item_slot[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = slots + q;
@@ -658,8 +698,7 @@ __global__ __launch_bounds__(T *T) void k_bin(KArgs a) {
 
 // ------------------------------------------------------------------------------------------------
 // k_scan: one workgroup.  Prefix sums over the tiles of the coverage cost and of the chunk count (the
-// work partition of the persistent kernels).  Every thread owns a contiguous segment: one pass to
-// sum it, one block scan of the 1024 sums, one pass to write.
+// work partition of the persistent kernels): every thread owns a contiguous run of tiles.
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ long long block_exclusive_scan(long long v, long long *s_w, long long &total) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -686,22 +725,35 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
   const int tid = threadIdx.x;
   const int nt = a.total_tiles;
   const int per = (nt + 1023) / 1024, t0 = min(tid * per, nt), t1 = min(t0 + per, nt);
+  // the thread's run of tiles, eight loads in flight at a time
   long long cc = 0, cq = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int2 c = a.tile_cost[t];
-    cc += c.x;
-    cq += c.y;
+  for (int t = t0; t < t1; t += 8) {
+    int2 c[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c[j] = t + j < t1 ? a.tile_cost[t + j] : make_int2(0, 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      cc += c[j].x;
+      cq += c[j].y;
+    }
   }
   long long tot_c, tot_q;
   long long pc = block_exclusive_scan(cc, s_w, tot_c);
   long long pq = block_exclusive_scan(cq, s_w, tot_q);
   long long *prc = a.tile_pre, *prq = a.tile_pre + (nt + 1);
-  for (int t = t0; t < t1; ++t) {
-    prc[t] = pc;
-    prq[t] = pq;
-    const int2 c = a.tile_cost[t];
-    pc += c.x;
-    pq += c.y;
+  for (int t = t0; t < t1; t += 8) {
+    int2 c[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c[j] = t + j < t1 ? a.tile_cost[t + j] : make_int2(0, 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (t + j < t1) {
+        prc[t + j] = pc;
+        prq[t + j] = pq;
+      }
+      pc += c[j].x;
+      pq += c[j].y;
+    }
   }
   if (tid == 0) {
     prc[nt] = tot_c;
@@ -1299,7 +1351,8 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
 
 hipError_t launch_bin(const KArgs &a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles), dim3(T * T), 0, st, a));
+  if (a.rowbin) COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_rowbin<T>, dim3(a.total_rows), dim3(256), 0, st, a));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles), dim3(T * T < 256 ? T * T : 256), 0, st, a));
   return hipGetLastError();
 }
 
