@@ -23,7 +23,11 @@
  *        L_ov   = sum_p relu(S - 1)^2           L_cont = sum_p S (1 - M)
  *        L_fill = sum_p M relu(1 - S)^2         L_pad  = sum_p relu(S_pad - 1)^2
  *        L_down = sum_p S (H - y_p)
- *     reported weighted: loss[b][term] = w_term * L_term.
+ *     and the uniform loss of Sec. 4.2 (eq. 7), read as: O = min(S, 1); for bandwidths
+ *     b_j = 5 + 6 j (j < NUNI), A_j(p) = sum of O over the b_j x b_j window centred on p (clipped to
+ *     the canvas);  L_unif = sum_j (b_j / b_0) sum_p M(p) relu(1 - A_j(p))  -- container pixels with
+ *     no item within the window, larger windows weighted more.
+ *     reported weighted: loss[b][term] = w_term * L_term (NTERMS terms per layout).
  *   - The gradient of sum_b sum_term dloss[b][term] * loss[b][term] with respect to every item's
  *     (t_x, t_y, theta, s) (Sec. 4, eq. 4 needs dL/dt, dL/dr, dL/ds), by the chain rule through the
  *     two end points of each pixel's nearest edge and then through eq. 2.
@@ -40,6 +44,12 @@
 #include <omp.h>
 #endif
 
+#define NTERMS 6 /* loss terms per layout */
+#define NUNI 4   /* window sizes of the uniform loss */
+
+static int uni_radius(int j) { return 2 + 3 * j; }                     /* window (2 r + 1) = 5 + 6 j */
+static double uni_weight(int j) { return (5.0 + 6.0 * j) / 5.0; }     /* b_j / b_0 */
+
 typedef struct {
   int32_t B;                /* layouts */
   int32_t N;                /* items (all layouts) */
@@ -52,7 +62,7 @@ typedef struct {
   const double *verts;      /* [V*2] local frame, canonical px */
   const double *mask;       /* packed masks, layout b at pixel offset sum_{c<b} W_c*H_c */
   double tau, r_cut, r_pad;
-  double w[5];              /* overlap, contain, fill, pad, down */
+  double w[6];              /* overlap, contain, fill, pad, down, uniform */
   int32_t use_cutoff;       /* 1: hard zero below -r_cut (the definition); 0: no cut-off */
   int32_t use_bbox;         /* 1: skip pixels provably beyond the cut-off support (needs use_cutoff) */
   const double *stroke;     /* [N] stroke half-width, canonical px (> 0: open polyline), or NULL */
@@ -281,7 +291,78 @@ static void release(prepared *pr) {
 
 static int in_box(const int *bx, int i, int j) { return i >= bx[0] && i <= bx[2] && j >= bx[1] && j <= bx[3]; }
 
-/* S and S_pad for all layouts (packed), and the weighted loss terms [B*5]. */
+/* A_j(p): sum of min(S, 1) over the window of radius r around pixel (i, j), clipped to the canvas. */
+static double window_occupancy(const double *S, int W, int H, int i, int j, int r) {
+  double a = 0.0;
+  for (int y = j - r; y <= j + r; ++y) {
+    if (y < 0 || y >= H) continue;
+    for (int x = i - r; x <= i + r; ++x) {
+      if (x < 0 || x >= W) continue;
+      const double s = S[(int64_t)y * W + x];
+      a += s < 1.0 ? s : 1.0;
+    }
+  }
+  return a;
+}
+
+/* Unweighted uniform loss of layout b with coverage sums S (the layout's own image). */
+static double uniform_loss(const oracle_scene *sc, int b, const double *S) {
+  const int W = sc->width[b], H = sc->height[b];
+  const double *M = sc->mask ? sc->mask + pixel_offset(sc, b) : NULL;
+  double tot = 0.0;
+  for (int q = 0; q < NUNI; ++q) {
+    double *rows = (double *)calloc((size_t)(H > 0 ? H : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < W; ++i) {
+        const double m = M ? M[(int64_t)j * W + i] : 0.0;
+        if (m == 0.0) continue;
+        const double a = window_occupancy(S, W, H, i, j, uni_radius(q));
+        if (a < 1.0) acc += m * (1.0 - a);
+      }
+      rows[j] = acc;
+    }
+    double t = 0.0;
+    for (int j = 0; j < H; ++j) t += rows[j];
+    free(rows);
+    tot += uni_weight(q) * t;
+  }
+  return tot;
+}
+
+/* dL_unif/dS of layout b, added (times c) into G: at pixel q,
+ *   -1(S(q) < 1) sum_j (b_j / b_0) sum over pixels p whose window contains q of M(p) 1(A_j(p) < 1). */
+static void uniform_grad(const oracle_scene *sc, int b, const double *S, double c, double *G) {
+  const int W = sc->width[b], H = sc->height[b];
+  const double *M = sc->mask ? sc->mask + pixel_offset(sc, b) : NULL;
+  if (!M || c == 0.0) return;
+  double *F = (double *)malloc(sizeof(double) * (size_t)W * H);
+  for (int q = 0; q < NUNI; ++q) {
+    const int r = uni_radius(q);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < W; ++i) {
+        const double m = M[(int64_t)j * W + i];
+        F[(int64_t)j * W + i] = (m != 0.0 && window_occupancy(S, W, H, i, j, r) < 1.0) ? m : 0.0;
+      }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < W; ++i) {
+        if (!(S[(int64_t)j * W + i] < 1.0)) continue;
+        double f = 0.0;  /* the window is symmetric: p's window contains q iff q's contains p */
+        for (int y = j - r; y <= j + r; ++y) {
+          if (y < 0 || y >= H) continue;
+          for (int x = i - r; x <= i + r; ++x)
+            if (x >= 0 && x < W) f += F[(int64_t)y * W + x];
+        }
+        G[(int64_t)j * W + i] -= c * uni_weight(q) * f;
+      }
+  }
+  free(F);
+}
+
+/* S and S_pad for all layouts (packed), and the weighted loss terms [B*NTERMS]. */
 static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, double *Sp, double *loss) {
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b], H = sc->height[b];
@@ -333,11 +414,12 @@ static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, 
     }
     free(rows);
     if (loss) {
-      loss[5 * b + 0] = sc->w[0] * lo;
-      loss[5 * b + 1] = sc->w[1] * lc;
-      loss[5 * b + 2] = sc->w[2] * lf;
-      loss[5 * b + 3] = sc->w[3] * lp;
-      loss[5 * b + 4] = sc->w[4] * ld;
+      loss[NTERMS * b + 0] = sc->w[0] * lo;
+      loss[NTERMS * b + 1] = sc->w[1] * lc;
+      loss[NTERMS * b + 2] = sc->w[2] * lf;
+      loss[NTERMS * b + 3] = sc->w[3] * lp;
+      loss[NTERMS * b + 4] = sc->w[4] * ld;
+      loss[NTERMS * b + 5] = sc->w[5] != 0.0 && S ? sc->w[5] * uniform_loss(sc, b, S + off) : 0.0;
     }
   }
 }
@@ -347,7 +429,14 @@ int oracle_forward(const oracle_scene *sc, const double *params, double *S, doub
   if (sc->use_bbox && !sc->use_cutoff) return -1;
   prepared pr;
   prepare(sc, params, &pr);
+  double *Stmp = NULL;
+  if (!S && loss && sc->w[5] != 0.0) {
+    const int64_t total = pixel_offset(sc, sc->B);
+    Stmp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+    S = Stmp;
+  }
   forward_impl(sc, &pr, S, Sp, loss);
+  free(Stmp);
   release(&pr);
   return 0;
 }
@@ -415,7 +504,8 @@ int oracle_signed_distance(const oracle_scene *sc, const double *params, int fir
 /*
  * Gradient of sum_b sum_t dloss[b,t] * loss[b,t] with respect to params [N*4].
  *
- * dLoss/dS(p) and dLoss/dS_pad(p) follow from the loss definitions (relu'(0) = 0).  Each item's
+ * dLoss/dS(p) and dLoss/dS_pad(p) follow from the loss definitions (relu'(0) = 0, and the uniform
+ * term's min(S, 1) has derivative 1(S < 1)).  Each item's
  * contribution at pixel p is omega * dsd/dparam, omega = G * dalpha/dsd + G_pad * dalpha_pad/dsd.
  * dsd/dparam is taken through the vertices: for the nearest point q = a + u (b - a) on the nearest
  * edge (a, b), with g = (p - q)/|p - q| and sign +1 inside / -1 outside (always -1 for an open
@@ -440,9 +530,9 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b], H = sc->height[b];
     const int64_t off = pixel_offset(sc, b);
-    const double c_ov = dloss[5 * b + 0] * sc->w[0], c_c = dloss[5 * b + 1] * sc->w[1];
-    const double c_f = dloss[5 * b + 2] * sc->w[2], c_p = dloss[5 * b + 3] * sc->w[3];
-    const double c_d = dloss[5 * b + 4] * sc->w[4];
+    const double c_ov = dloss[NTERMS * b + 0] * sc->w[0], c_c = dloss[NTERMS * b + 1] * sc->w[1];
+    const double c_f = dloss[NTERMS * b + 2] * sc->w[2], c_p = dloss[NTERMS * b + 3] * sc->w[3];
+    const double c_d = dloss[NTERMS * b + 4] * sc->w[4];
     for (int j = 0; j < H; ++j)
       for (int i = 0; i < W; ++i) {
         const int64_t idx = off + (int64_t)j * W + i;
@@ -454,6 +544,7 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
         G[idx] = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * M * un + c_d * (H - (j + 0.5));
         Gp[idx] = 2.0 * c_p * pv;
       }
+    uniform_grad(sc, b, S + off, dloss[NTERMS * b + 5] * sc->w[5], G + off);
   }
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b];

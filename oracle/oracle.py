@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "collage_oracle.c")
 
+NTERMS = 6  # loss terms per layout: overlap, contain, fill, pad, down, uniform
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
 
@@ -26,7 +28,7 @@ class _OracleScene(ctypes.Structure):
         ("width", _ip), ("height", _ip), ("scale", _dp), ("shape_off", _ip), ("vert_off", _ip),
         ("verts", _dp), ("mask", _dp),
         ("tau", ctypes.c_double), ("r_cut", ctypes.c_double), ("r_pad", ctypes.c_double),
-        ("w", ctypes.c_double * 5),
+        ("w", ctypes.c_double * 6),
         ("use_cutoff", ctypes.c_int32), ("use_bbox", ctypes.c_int32),
         ("stroke", _dp),
     ]
@@ -107,10 +109,10 @@ class Oracle:
         p = _d(params).reshape(-1)
         S = np.zeros(self.num_pixels)
         Sp = np.zeros(self.num_pixels)
-        loss = np.zeros(5 * self.scene.num_layouts)
+        loss = np.zeros(NTERMS * self.scene.num_layouts)
         rc = lib().oracle_forward(ctypes.byref(self._s), _ptr(p), _ptr(S), _ptr(Sp), _ptr(loss))
         assert rc == 0
-        return S, Sp, loss.reshape(-1, 5)
+        return S, Sp, loss.reshape(-1, NTERMS)
 
     def loss(self, params, dloss=None):
         _, _, L = self.forward(params)
@@ -148,7 +150,9 @@ class Oracle:
     def backward(self, params, dloss=None):
         p = _d(params).reshape(-1)
         B = self.scene.num_layouts
-        dl = np.ones(5 * B) if dloss is None else _d(dloss).reshape(-1)
+        dl = np.ones(NTERMS * B) if dloss is None else _d(dloss).reshape(-1)
+        if dl.size != NTERMS * B:
+            raise ValueError(f"dloss must have {NTERMS} entries per layout")
         g = np.zeros(4 * max(self.scene.num_shapes, 1))
         rc = lib().oracle_backward(ctypes.byref(self._s), _ptr(p), _ptr(dl), _ptr(g))
         assert rc == 0

@@ -75,7 +75,10 @@ class CollageScene:
         d.mask = self.mask.data_ptr()
         d.stroke = self.stroke.data_ptr() if self.stroke is not None else None
         d.tau, d.r_cut, d.r_pad = scene.tau, scene.r_cut, scene.r_pad
-        d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down = scene.weights()
+        w = scene.weights()
+        if w[5] != 0.0:
+            raise NotImplementedError("the uniform loss term is not available on the GPU path yet")
+        d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down = w[:5]
         d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags
         self._desc = d
         h_ = ctypes.c_void_p()

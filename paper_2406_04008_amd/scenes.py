@@ -73,6 +73,7 @@ class Scene:
     w_fill: float = 1.0
     w_pad: float = 0.0
     w_down: float = 0.0
+    w_uniform: float = 0.0  # uniform (dilation) term, off unless a scene sets it
     steps_per_level: int = 300
     lr_px: float = 0.5
     seed: int = 0
@@ -119,7 +120,8 @@ class Scene:
         return np.concatenate([[0], np.cumsum(w.astype(np.int64) * h)]).astype(np.int64)
 
     def weights(self):
-        return (self.w_overlap, self.w_contain, self.w_fill, self.w_pad, self.w_down)
+        """Loss weights in term order: overlap, contain, fill, pad, down, uniform."""
+        return (self.w_overlap, self.w_contain, self.w_fill, self.w_pad, self.w_down, self.w_uniform)
 
     def signature(self) -> str:
         h = hashlib.sha1()

@@ -4,6 +4,7 @@ None of these tests re-types the oracle's formulas: each compares it with a clos
 independent algorithm (winding numbers, 1-D quadrature of a radially symmetric integrand), an
 invariant, a library routine (torch.optim.Adam) or its own central finite differences.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -202,7 +203,7 @@ def test_P3_scale_derivative_is_twice_area_over_s():
     area = 0.5 * 128 * 81.0 * math.sin(2 * math.pi / 128)
     s = 1.3
     sc = S.single_shape_scene(P, 48, 48, (24.21, 23.67), 0.2, s, w_overlap=0, w_contain=1, w_fill=0)
-    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0])
+    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0])
     assert abs(g[0, 3] - 2 * area * s) / (2 * area * s) < 1e-3  # d(s^2 A)/ds
     # translation and rotation leave the total coverage unchanged
     assert abs(g[0, 0]) < 2e-3 * area and abs(g[0, 1]) < 2e-3 * area and abs(g[0, 2]) < 2e-3 * area
@@ -216,7 +217,7 @@ def test_P4_gravity_identity():
         sc = S.single_shape_scene(P, 48, 48, c, 0.2, 1.0, w_overlap=0, w_contain=1, w_fill=0, w_down=1.0)
         o = Oracle(sc)
         mass = o.forward(sc.params)[2][0, 1]
-        g = o.backward(sc.params, dloss=[0, 0, 0, 0, 1])[0]
+        g = o.backward(sc.params, dloss=[0, 0, 0, 0, 1, 0])[0]
         return np.array([mass, g[0], g[1]])
 
     mass, gx, gy = _offset_average(f, (23.9, 20.3))
@@ -391,7 +392,7 @@ def test_open_P3_scale_derivative():
     L, w, s = 14.6, 4.0, 1.3
     area = 2 * w * L + math.pi * w * w
     sc = _stadium(L, w, (24.21, 23.67), 0.2, s, size=64)
-    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0])
+    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0])
     assert abs(g[0, 3] - 2 * area * s) / (2 * area * s) < 2e-3, (g[0, 3], 2 * area * s)
     assert abs(g[0, 0]) < 2e-3 * area and abs(g[0, 1]) < 2e-3 * area and abs(g[0, 2]) < 2e-3 * area
 
@@ -399,4 +400,40 @@ def test_open_P3_scale_derivative():
 def test_open_P7_backward_vs_central_differences():
     sc = S.random_scene(12, [(56, 48)], [7], kinds=("open", "star", "open"), radius=(4.0, 9.0))
     assert sc.stroke is not None and (sc.stroke > 0).sum() >= 3
+    _fd_check(sc)
+
+
+# --------------------------------------------------------------------------------------------------
+# Uniform (dilation) term: O = min(S, 1), A_j = box sum of O over (5 + 6 j)^2 windows (j < 4),
+# L = sum_j (b_j / 5) sum_p M relu(1 - A_j)
+# --------------------------------------------------------------------------------------------------
+UNI_B = (5, 11, 17, 23)
+
+
+def test_uniform_term_of_an_empty_layout():
+    """No items: A_j = 0 everywhere, so the term is (sum_j b_j / 5) * sum_p M = 11.2 sum_p M."""
+    sc = dataclasses.replace(S.random_scene(2, [(37, 29)], [0]), w_uniform=1.0)
+    _, _, L = Oracle(sc).forward(sc.params)
+    M = sc.packed_mask(None).astype(np.float64)
+    assert abs(L[0, 5] - sum(b / 5 for b in UNI_B) * M.sum()) < 1e-9 * M.sum()
+
+
+def test_uniform_term_matches_a_convolution():
+    """The term recomputed from the oracle's S with scipy's 2-D convolution as the box sum."""
+    from scipy.signal import convolve2d
+
+    sc = dataclasses.replace(S.random_scene(5, [(61, 47)], [6], radius=(3.0, 7.0)), w_uniform=0.7)
+    S_, _, L = Oracle(sc).forward(sc.params)
+    O = np.minimum(S_.reshape(47, 61), 1.0)
+    M = sc.packed_mask(None).astype(np.float64).reshape(47, 61)
+    ref = 0.0
+    for b in UNI_B:
+        A = convolve2d(O, np.ones((b, b)), mode="same", boundary="fill", fillvalue=0.0)
+        ref += (b / 5) * (M * np.maximum(1.0 - A, 0.0)).sum()
+    assert ref > 1.0 and abs(L[0, 5] - 0.7 * ref) < 1e-10 * ref
+
+
+def test_uniform_term_backward_vs_central_differences():
+    sc = dataclasses.replace(S.random_scene(9, [(52, 44)], [5], radius=(3.0, 6.0)), w_uniform=3.0,
+                             w_overlap=0.2, w_contain=0.2, w_fill=0.2)
     _fd_check(sc)
