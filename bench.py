@@ -148,7 +148,7 @@ def batched_vs_loop(steps):
     stream, same epochs from the same start.  Per-layout results are bitwise identical in the two forms."""
     import torch
 
-    from paper_2406_04008_amd import autotune, scenes
+    from paper_2406_04008_amd import _lib, autotune, scenes
     from paper_2406_04008_amd.collage import CollageScene
 
     sc = scenes.config4(0)
@@ -161,7 +161,7 @@ def batched_vs_loop(steps):
         for c in css:
             p = c.params_tensor()
             m, v, st = c.new_state()
-            state.append((c, p, m, v, st, torch.empty(c.B, 5, device="cuda"), torch.empty(c.N, 4, device="cuda")))
+            state.append((c, p, m, v, st, torch.empty(c.B, _lib.LOSS_TERMS, device="cuda"), torch.empty(c.N, 4, device="cuda")))
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -190,6 +190,36 @@ def batched_vs_loop(steps):
             "speedup": tl / tb, "batched_matches_loop": bool(np.array_equal(pb, pl))}
 
 
+def uniform_term(sc, level, cfg, steps, weight=2e-3):
+    """The benchmark scene and launch configuration with the uniform term of eq. 7 switched on: epochs
+    per second with and without it, each from the seed-0 layout after a warm-up."""
+    import dataclasses
+
+    import torch
+
+    from paper_2406_04008_amd.collage import CollageScene
+
+    out = {"w_uniform": weight, "steps": steps, "tile": cfg.tile}
+    stream = torch.cuda.Stream()
+    for name, w in (("without", 0.0), ("with", weight)):
+        cs = CollageScene(dataclasses.replace(sc, w_uniform=w), level=level, **cfg.scene_kwargs())
+        for timed in (False, True):
+            p = cs.params_tensor()
+            m, v, st = cs.new_state()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            with torch.cuda.stream(stream):
+                cs.iterate_n(p, m, v, st, steps if timed else 20, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+        assert np.all(np.isfinite(p.cpu().numpy())), "non-finite parameters"
+        out[f"it_per_s_{name}"] = steps / (e0.elapsed_time(e1) / 1e3)
+    out["ms_per_epoch_added"] = 1e3 / out["it_per_s_with"] - 1e3 / out["it_per_s_without"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,7 +230,9 @@ def main():
     ap.add_argument("--code-capacity", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the coarse-to-fine schedule and the batched-vs-loop comparison")
+                    help="skip every extra measurement (schedules, batched-vs-loop, uniform term)")
+    ap.add_argument("--extras", default="c2f,open,batched,uniform",
+                    help="comma-separated extra measurements: c2f, open, batched, uniform")
     ap.add_argument("--batched-steps", type=int, default=30)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed region, copy 256 MiB device to device (reference for HBM counters)")
@@ -215,7 +247,7 @@ def main():
 
     import torch
 
-    from paper_2406_04008_amd import autotune, scenes
+    from paper_2406_04008_amd import _lib, autotune, scenes
     from paper_2406_04008_amd.collage import CollageScene, Timer
 
     if not torch.cuda.is_available():
@@ -229,7 +261,7 @@ def main():
     cs = CollageScene(sc, level=args.level, **cfg.scene_kwargs())
     params = cs.params_tensor()
     m, v, step = cs.new_state()
-    loss = torch.empty(cs.B, 5, device="cuda")
+    loss = torch.empty(cs.B, _lib.LOSS_TERMS, device="cuda")
     grad = torch.empty(cs.N, 4, device="cuda")
     stream = torch.cuda.Stream()
     timer = Timer(args.steps)
@@ -344,11 +376,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not args.no_extras:
+    extras = set() if args.no_extras else {x.strip() for x in args.extras.split(",") if x.strip()}
+    if "c2f" in extras:
         out["coarse_to_fine"] = coarse_to_fine(sc)
+    if "open" in extras:
         # open stroked polylines: 2000 on 2048 x 2048, schedule 256 -> 512 -> 1024 -> 2048
         out["open_shapes"] = coarse_to_fine(scenes.config5(0))
+    if "batched" in extras:
         out["batched"] = batched_vs_loop(args.batched_steps)
+    if "uniform" in extras:
+        out["uniform_term"] = uniform_term(sc, args.level, cfg, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.level)
     print(json.dumps(out), flush=True)

@@ -26,7 +26,14 @@
  *       [2] fill     w_fill    * sum_p M relu(1 - S)^2
  *       [3] pad      w_pad     * sum_p relu(S_pad - 1)^2
  *       [4] down     w_down    * sum_p S (H - y_p)
- *     M is the container mask (1 inside), the complement of the paper's container image I_C.
+ *       [5] uniform  w_uniform * sum_j (b_j / 5) sum_p M relu(1 - A_j(p))           (Sec. 4.2, eq. 7)
+ *     M is the container mask (1 inside), the complement of the paper's container image I_C.  For the
+ *     uniform term, b_j = 5 + 6 j (j = 0..3) and A_j(p) is the sum of min(S, 1) over the b_j x b_j
+ *     window centred on p, clipped to the canvas: it charges container pixels with no item nearby,
+ *     the more the larger the empty window.  Its gradient with respect to S is
+ *     -1(S(q) < 1) sum_j (b_j / 5) sum_{p: q in window_j(p)} M(p) 1(A_j(p) < 1) (relu'(0) = 0).  The
+ *     window sums are exact integer sums of S in 2^-40 fixed point, so the A_j < 1 decisions depend
+ *     only on the accumulated S.
  *   - All buffers passed to compute calls are DEVICE memory owned by the caller, float32 unless stated,
  *     contiguous.  Packed images hold the layouts one after another, layout b starting at pixel
  *     sum_{c<b} W_c * H_c.  Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream)
@@ -88,6 +95,8 @@ typedef struct collage_scene_desc {
   float r_cut;                  /* coverage cut-off, level px, >= 0 */
   float r_pad;                  /* padding offset, level px, >= 0 */
   float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
+  float w_uniform;              /* weight of the uniform term, finite; 0 = the term is skipped (no
+                                   launches) and reported as 0 */
   int32_t tile;                 /* screen tile edge in px: 8, 16 or 32; 0 = default (16) */
   int32_t code_capacity;        /* 64-pixel chunks of (tile, item) work whose nearest-edge codes (2 bytes
                                    per pixel) are kept between the coverage and adjoint passes; the
@@ -114,7 +123,7 @@ int collage_scene_info(const collage_scene *scene, int64_t *num_pixels, int64_t 
  *   params  [N,4]        item parameters
  *   cov     [pixels]     S, written (may be NULL)
  *   cov_pad [pixels]     S_pad, written (may be NULL)
- *   loss    [B,5]        weighted loss terms, written
+ *   loss    [B,6]        weighted loss terms, written
  */
 int collage_forward(const collage_scene *scene, const float *params, float *cov, float *cov_pad, float *loss,
                     void *workspace, size_t workspace_bytes, void *stream);
@@ -123,7 +132,7 @@ int collage_forward(const collage_scene *scene, const float *params, float *cov,
  * Backward pass (the gradient used by eq. 4): d(sum_b sum_t dloss[b,t] * loss[b,t]) / d params.
  * Recomputes the coverage and every pixel's nearest edge from params (no per-pixel, per-item
  * intermediates are stored between calls, and no image from the forward pass is needed).
- *   dloss [B,5]  upstream gradient of each loss term
+ *   dloss [B,6]  upstream gradient of each loss term
  *   grad  [N,4]  overwritten
  */
 int collage_backward(const collage_scene *scene, const float *params, const float *dloss, float *grad,
@@ -147,8 +156,8 @@ int collage_step(const collage_scene *scene, float *params, const float *grad, f
 
 /*
  * One optimization epoch of Fig. 2: forward, loss, backward and the Adam update of collage_step,
- * in three kernel launches with fixed grids (safe to capture in a hipGraph and replay).
- * cov / cov_pad may be NULL.  loss [B,5] and grad [N,4] receive this epoch's values (before the update).
+ * in kernel launches with fixed grids (safe to capture in a hipGraph and replay).
+ * cov / cov_pad may be NULL.  loss [B,6] and grad [N,4] receive this epoch's values (before the update).
  */
 int collage_iterate(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                     float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,

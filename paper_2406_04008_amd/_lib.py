@@ -20,6 +20,7 @@ ERR_WORKSPACE = -3
 ERR_HIP = -4
 ERR_UNSUPPORTED = -5
 FLAG_NONE = 0
+LOSS_TERMS = 6  # overlap, contain, fill, pad, down, uniform
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -34,7 +35,7 @@ class SceneDesc(ctypes.Structure):
         ("verts", _vp), ("rho", _vp), ("mask", _vp), ("stroke", _vp),
         ("tau", ctypes.c_float), ("r_cut", ctypes.c_float), ("r_pad", ctypes.c_float),
         ("w_overlap", ctypes.c_float), ("w_contain", ctypes.c_float), ("w_fill", ctypes.c_float),
-        ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float),
+        ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float), ("w_uniform", ctypes.c_float),
         ("tile", ctypes.c_int32), ("code_capacity", ctypes.c_int32), ("bin_chunk", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
     ]

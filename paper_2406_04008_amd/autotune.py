@@ -18,6 +18,7 @@ from typing import Dict, Iterable, List, Optional, Tuple
 
 import torch
 
+from . import _lib
 from .collage import CollageScene
 from .scenes import Scene
 
@@ -50,7 +51,7 @@ def time_config(scene: Scene, level: Optional[int], cfg: LaunchConfig, epochs: i
     p0 = cs.params_tensor()
     p = p0.clone()
     m, v, st = cs.new_state()
-    loss = torch.empty(cs.B, 5, device=cs.device)
+    loss = torch.empty(cs.B, _lib.LOSS_TERMS, device=cs.device)
     grad = torch.empty(cs.N, 4, device=cs.device)
     stream = torch.cuda.Stream(cs.device)
     times: List[float] = []

@@ -76,9 +76,7 @@ class CollageScene:
         d.stroke = self.stroke.data_ptr() if self.stroke is not None else None
         d.tau, d.r_cut, d.r_pad = scene.tau, scene.r_cut, scene.r_pad
         w = scene.weights()
-        if w[5] != 0.0:
-            raise NotImplementedError("the uniform loss term is not available on the GPU path yet")
-        d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down = w[:5]
+        d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down, d.w_uniform = w
         d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags
         self._desc = d
         h_ = ctypes.c_void_p()
@@ -114,7 +112,7 @@ class CollageScene:
         _need(params, (self.N, 4), "params")
         cov = torch.empty(self.num_pixels, device=self.device) if want_cov else None
         cov_pad = torch.empty(self.num_pixels, device=self.device) if want_cov else None
-        loss = torch.empty(self.B, 5, device=self.device)
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device)
         ws, nb = self._ws()
         rc = self.lib.collage_forward(self.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss), ws, nb,
                                       _stream(self.device))
@@ -123,7 +121,7 @@ class CollageScene:
 
     def backward(self, params: torch.Tensor, dloss: torch.Tensor):
         _need(params, (self.N, 4), "params")
-        _need(dloss, (self.B, 5), "dloss")
+        _need(dloss, (self.B, _lib.LOSS_TERMS), "dloss")
         grad = torch.empty(self.N, 4, device=self.device)
         ws, nb = self._ws()
         rc = self.lib.collage_backward(self.handle, _ptr(params), _ptr(dloss), _ptr(grad), ws, nb,
@@ -135,7 +133,7 @@ class CollageScene:
         _need(params, (self.N, 4), "params")
         cov = torch.empty(self.num_pixels, device=self.device) if want_cov else None
         cov_pad = torch.empty(self.num_pixels, device=self.device) if want_cov else None
-        loss = torch.empty(self.B, 5, device=self.device)
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device)
         grad = torch.empty(self.N, 4, device=self.device)
         ws, nb = self._ws()
         rc = self.lib.collage_forward_backward(self.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss),
@@ -171,7 +169,7 @@ class CollageScene:
                 betas=(0.9, 0.999), eps=1e-8):
         """One epoch: forward, loss, backward, Adam.  Returns (loss, grad) of this epoch."""
         lr_px = self.scene.lr_px if lr_px is None else lr_px
-        loss = torch.empty(self.B, 5, device=self.device) if loss is None else loss
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device) if loss is None else loss
         grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
         ws, nb = self._ws()
         rc = self.lib.collage_iterate(self.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss), _ptr(grad),
@@ -185,7 +183,7 @@ class CollageScene:
         """`epochs` epochs in one call (collage_iterate_n); with `timer`, one event pair per epoch around the
         coverage kernel.  Returns (loss, grad) of the last epoch."""
         lr_px = self.scene.lr_px if lr_px is None else lr_px
-        loss = torch.empty(self.B, 5, device=self.device) if loss is None else loss
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device) if loss is None else loss
         grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
         ws, nb = self._ws()
         st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
@@ -280,7 +278,7 @@ class Timer:
 
 
 class CollageLoss(torch.autograd.Function):
-    """loss[B,5] = CollageLoss.apply(params[N,4], scene): the weighted loss terms of every layout.
+    """loss[B,6] = CollageLoss.apply(params[N,4], scene): the weighted loss terms of every layout.
 
     The backward recomputes the coverage and each pixel's nearest edge in the HIP adjoint kernel;
     only the parameters are saved between the passes."""

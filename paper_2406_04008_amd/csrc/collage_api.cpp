@@ -47,8 +47,8 @@ struct collage_scene {
   std::vector<int32_t> vert_off;
   const float *verts = nullptr, *rho = nullptr, *mask = nullptr, *stroke = nullptr;
   float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
-  float w[5] = {1, 1, 1, 0, 0};
-  int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_pblk = 0, total_rows = 0, row_list_total = 0;
+  float w[6] = {1, 1, 1, 0, 0, 0};
+  int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_ptiles = 0, total_rows = 0, row_list_total = 0;
   int32_t max_canvas = 0;
   // device tables owned by the scene
   LayoutRec *d_layouts = nullptr;
@@ -57,7 +57,7 @@ struct collage_scene {
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_islot = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
-         off_gbuf = 0, off_codes = 0;
+         off_gbuf = 0, off_codes = 0, off_uflags = 0;
   size_t ws_bytes = 0;
 };
 
@@ -106,7 +106,7 @@ int validate_desc(const collage_scene_desc *d) {
   if (!(d->tau > 0.0f) || !std::isfinite(d->tau)) return fail(COLLAGE_ERR_INVALID, "tau must be finite and > 0");
   if (!(d->r_cut >= 0.0f) || !std::isfinite(d->r_cut)) return fail(COLLAGE_ERR_INVALID, "r_cut must be finite and >= 0");
   if (!(d->r_pad >= 0.0f) || !std::isfinite(d->r_pad)) return fail(COLLAGE_ERR_INVALID, "r_pad must be finite and >= 0");
-  const float ws[5] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down};
+  const float ws[6] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down, d->w_uniform};
   for (float x : ws)
     if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32)
@@ -126,7 +126,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.num_layouts = s->B;
   a.num_shapes = s->N;
   a.total_tiles = (int32_t)s->total_tiles;
-  a.total_pblk = (int32_t)s->total_pblk;
+  a.total_ptiles = (int32_t)s->total_ptiles;
   a.total_rows = (int32_t)s->total_rows;
   a.rowbin = s->list_total > kRowBinTests ? 1 : 0;
   a.tile = s->tile;
@@ -159,13 +159,14 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.acc = reinterpret_cast<unsigned long long *>(w + s->off_acc);
   a.gbuf = reinterpret_cast<double2 *>(w + s->off_gbuf);
   a.codes = reinterpret_cast<uint16_t *>(w + s->off_codes);
+  a.uflags = reinterpret_cast<uint8_t *>(w + s->off_uflags);
   a.tau = s->tau;
   a.inv_tau = 1.0f / s->tau;
   a.r_cut = s->r_cut;
   a.r_pad = s->r_pad;
   a.inv_tau_d = 1.0 / (double)s->tau;
   a.pad_factor = std::exp(-(double)s->r_pad / (double)s->tau);
-  for (int i = 0; i < 5; ++i) a.w[i] = s->w[i];
+  for (int i = 0; i < 6; ++i) a.w[i] = s->w[i];
   return a;
 }
 
@@ -218,9 +219,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->w[2] = desc->w_fill;
   s->w[3] = desc->w_pad;
   s->w[4] = desc->w_down;
+  s->w[5] = desc->w_uniform;
   s->vert_off.assign(desc->vert_offset, desc->vert_offset + s->N + 1);
   s->layouts.resize(s->B);
-  int64_t pix = 0, tiles = 0, list = 0, pblk = 0, rows = 0, rlist = 0;
+  int64_t pix = 0, tiles = 0, list = 0, ptiles = 0, rows = 0, rlist = 0;
   for (int b = 0; b < s->B; ++b) {
     LayoutRec &L = s->layouts[b];
     std::memset(&L, 0, sizeof(L));
@@ -234,24 +236,24 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     L.pix_off = pix;
     L.list_off = list;
     L.k = desc->layout_scale[b];
-    L.pblk_off = (int32_t)pblk;
+    L.ptile_off = (int32_t)ptiles;
     L.row_off = (int32_t)rows;
     L.row_list_off = rlist;
     rows += L.nty;
     rlist += (int64_t)L.nty * (L.shape_end - L.shape_begin);
-    pblk += ((int64_t)L.W * L.H + kPixelBlock - 1) / kPixelBlock;
+    ptiles += (int64_t)((L.W + kPixTile - 1) / kPixTile) * ((L.H + kPixTile - 1) / kPixTile);
     pix += (int64_t)L.W * L.H;
     tiles += (int64_t)L.ntx * L.nty;
     list += (int64_t)L.ntx * L.nty * (L.shape_end - L.shape_begin);
     if (L.W * L.H > s->max_canvas) s->max_canvas = L.W * L.H;
   }
-  if (tiles > (int64_t)0x7fffffff || pblk > (int64_t)0x7fffffff) {
+  if (tiles > (int64_t)0x7fffffff || ptiles > (int64_t)0x7fffffff) {
     delete s;
     return fail(COLLAGE_ERR_INVALID, "too many screen tiles");
   }
   s->total_pixels = pix;
   s->total_tiles = tiles;
-  s->total_pblk = pblk;
+  s->total_ptiles = ptiles;
   s->total_rows = rows;
   s->row_list_total = rlist;
   s->list_total = list;
@@ -282,7 +284,9 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->off_count = off;
   off = align256(off + sizeof(int32_t) * (size_t)tiles);
   s->off_loss = off;
-  off = align256(off + sizeof(double) * 5 * (size_t)pblk);
+  off = align256(off + sizeof(double) * kLossTerms * (size_t)ptiles);
+  s->off_uflags = off;
+  off = align256(off + (size_t)pix);
   s->off_list = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
   s->off_islot = off;
@@ -390,6 +394,7 @@ int collage_backward(const collage_scene *s, const float *params, const float *d
   if (e == hipSuccess) e = launch_scan(a, st);
   if (e == hipSuccess) e = launch_cover(a, st);
   if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_uniform_grad(a, st);
   if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, false, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward launch");
@@ -415,6 +420,7 @@ int collage_forward_backward(const collage_scene *s, const float *params, float 
   if (e == hipSuccess) e = launch_scan(a, st);
   if (e == hipSuccess) e = launch_cover(a, st);
   if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_uniform_grad(a, st);
   if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, true, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_forward_backward launch");
@@ -486,6 +492,7 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
     if (e == hipSuccess) e = launch_scan(a, st);
     if (e == hipSuccess) e = launch_cover(a, st, timer ? timer->start[i] : nullptr, timer ? timer->stop[i] : nullptr);
     if (e == hipSuccess) e = launch_pixel(a, true, st);
+    if (e == hipSuccess) e = launch_uniform_grad(a, st);
     if (e == hipSuccess) e = launch_adjoint(a, st);
     if (e == hipSuccess) e = launch_finalize(a, true, true, true, st, i + 1 < n);
   }

@@ -13,7 +13,7 @@ struct alignas(16) LayoutRec {
   int32_t tile_off;     // first global tile index
   int32_t shape_begin;  // item range [shape_begin, shape_end)
   int32_t shape_end;
-  int32_t pblk_off;     // first pixel block (kPixelBlock pixels) of the layout
+  int32_t ptile_off;    // first kPixTile x kPixTile pixel tile of the layout (per-pixel and window passes)
   int64_t pix_off;      // first pixel in packed images
   int64_t list_off;     // first entry of this layout's per-tile item lists (capacity: items of the layout per tile)
   float k;              // level scale
@@ -71,7 +71,7 @@ struct KArgs {
   int32_t num_layouts;
   int32_t num_shapes;
   int32_t total_tiles;
-  int32_t total_pblk;    // pixel blocks over all layouts
+  int32_t total_ptiles;  // pixel tiles over all layouts
   int32_t tile;          // tile edge in px (8, 16 or 32)
   int32_t bin_chunk;     // items binned per pass
   int32_t unit_cap;      // upper bound of the number of units (list entries)
@@ -110,19 +110,20 @@ struct KArgs {
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
   double4 *partial;         // [chunks of the pass] adjoint sums (n_x, n_y, theta, scale terms) of the
                             // piece of a unit that starts at the chunk, 0 for other chunks
-  double *block_loss;       // per pixel block: the 5 loss-term sums
+  double *block_loss;       // per pixel tile: the kLossTerms weighted loss-term sums
+  uint8_t *uflags;          // [pixels] bit j: M != 0 and A_j < 1 (the uniform term's active windows)
   int32_t *step_inc;        // incremented once per epoch by the scan kernel when not null
   // images
   float *cov_out;
   float *cov_pad_out;
-  const float *dloss;    // [B,5] or null (= 1)
+  const float *dloss;    // [B,kLossTerms] or null (= 1)
   int32_t write_loss;    // tile loss partials are written (forward and fused calls)
   int32_t keep_codes;    // the coverage pass stores nearest-edge codes (adjoint calls)
   // constants
   float tau, inv_tau, r_cut, r_pad;
   double inv_tau_d;      // 1 / tau
   double pad_factor;     // e^(-r_pad / tau)
-  float w[5];
+  float w[6];            // overlap, contain, fill, pad, down, uniform
   // finalize / Adam
   float *loss_out;
   float *grad_out;
@@ -141,6 +142,9 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st);
 hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
+// the uniform term's share of dLoss/dS, added into gbuf after launch_pixel(grad = true) (nothing is
+// launched when its weight is 0)
+hipError_t launch_uniform_grad(const KArgs &a, hipStream_t st);
 // do_transform: after the update, transform every item with its new parameters (the next epoch of the
 // same call then needs no transform launch)
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
@@ -156,10 +160,15 @@ constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
 constexpr int64_t kRowBinTests = 1 << 21;  // box tests (tiles x items) above which the row pass is used
-constexpr int kPixelBlock = 1024;  // pixels per workgroup of the per-pixel kernel (4 per thread)
+constexpr int kLossTerms = 6;   // overlap, contain, fill, pad, down, uniform
+constexpr int kUniWindows = 4;  // window sizes 5 + 6 j of the uniform term
+constexpr int kUniHalo = 11;    // largest window radius (2 + 3 (kUniWindows - 1))
+constexpr int kPixTile = 32;    // pixel tile edge of the per-pixel and window passes
+constexpr int kPixThreads = kPixTile * kPixTile;  // their workgroup: one thread per pixel
 constexpr int kEpilogueCost = 16;  // per-pixel work after the scan, in edge evaluations (work partition)
 constexpr int kMaxVertsPerItem = 32767;
 constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point scale of the coverage accumulators
 constexpr double kFixInv = 1.0 / 1099511627776.0;
+constexpr unsigned long long kFixOne = 1ull << 40;  // 1.0 in that fixed point
 
 }  // namespace collage

@@ -56,6 +56,43 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// v moved between lanes by the DPP control CTRL (rows outside ROW_MASK and lanes whose source is out of
+// the row read 0); the two 32-bit halves move separately.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: Hillis-Steele within each row of 16 lanes
+// (row_shr 1, 2, 4, 8), then the last lane of row 0 / 2 added into row 1 / 3 (row_bcast 15) and the last
+// lane of row 1 into rows 2 and 3 (row_bcast 31).
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
+  v += dpp_u64<0x111, 0xf>(v);
+  v += dpp_u64<0x112, 0xf>(v);
+  v += dpp_u64<0x114, 0xf>(v);
+  v += dpp_u64<0x118, 0xf>(v);
+  v += dpp_u64<0x142, 0xa>(v);
+  v += dpp_u64<0x143, 0xc>(v);
+  return v;
+}
+
+// Sum over the 64 lanes of a wave in a fixed order (the scan pattern of wave_incl_scan_u64 with double
+// additions; the total ends in lane 63 and is broadcast from there).  Every lane must be active.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += __longlong_as_double((long long)dpp_u64<0x111, 0xf>((unsigned long long)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_u64<0x112, 0xf>((unsigned long long)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_u64<0x114, 0xf>((unsigned long long)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_u64<0x118, 0xf>((unsigned long long)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_u64<0x142, 0xa>((unsigned long long)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_u64<0x143, 0xc>((unsigned long long)__double_as_longlong(v)));
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)bits, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)bits >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -912,87 +949,287 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// k_pixel: S, S_pad, the loss terms (summed per block of kPixelBlock pixels of one layout) and
-// dLoss/dS, dLoss/dS_pad per pixel.  Each thread takes four pixels, kPixelBlock / 4 apart, with all
-// their loads issued together.
+// Per-pixel pass and the uniform term.  Both work on kPixTile x kPixTile pixel tiles of a layout, one
+// pixel per thread.
+//
+// The uniform term (Sec. 4.2, eq. 7).  With O = min(S, 1) and windows of 5 + 6 j pixels (radius
+// 2 + 3 j, j < kUniWindows) clipped to the canvas, A_j(p) is the sum of O over the window around p;
+//   L_unif = sum_j (b_j / b_0) sum_p M(p) relu(1 - A_j(p)),
+//   dL_unif/dS(q) = -1(S(q) < 1) sum_j (b_j / b_0) sum_{p : q in window_j(p)} M(p) 1(A_j(p) < 1).
+// A tile and a halo of the largest radius go into LDS in the 2^-40 fixed point of the coverage
+// accumulators and become a summed-area table, from which every window sum is four lookups.  The sums
+// are integers, so A_j is exact given the accumulated S and neither the A_j < 1 decisions nor the
+// results depend on an order of summation.
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ int layout_of_pblk(cptr<LayoutRec> L, int B, int blk) {
+constexpr int kPixWaves = kPixThreads / 64;
+constexpr int kUniReg = kPixTile + 2 * kUniHalo;  // region edge: tile + halo on both sides
+constexpr int kUniPitch = kUniReg + 1;            // table row pitch (row 0 and column 0 hold zeros)
+constexpr int kUniBand = (kUniReg + kPixWaves - 1) / kPixWaves;  // region rows per wave
+static_assert(kPixTile * kPixTile == kPixThreads, "one pixel per thread");
+static_assert(kUniHalo == 2 + 3 * (kUniWindows - 1), "halo must be the largest window radius");
+static_assert(kUniReg <= 64, "a region row must fit one wave");
+
+__device__ __forceinline__ int uni_radius(int j) { return 2 + 3 * j; }
+__device__ __forceinline__ double uni_weight(int j) { return (5.0 + 6.0 * j) / 5.0; }
+
+struct PixTile {
+  int b, W, H;
+  int x0, y0;  // pixel of the tile's top-left corner
+  int64_t pix_off;
+};
+
+__device__ __forceinline__ PixTile pix_tile(cptr<LayoutRec> L, int B, int blk) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (L[mid].pblk_off <= blk)
+    if (L[mid].ptile_off <= blk)
       lo = mid;
     else
       hi = mid - 1;
   }
-  return lo;
+  PixTile u;
+  u.b = lo;
+  u.W = L[lo].W;
+  u.H = L[lo].H;
+  const int ntx = (u.W + kPixTile - 1) / kPixTile;
+  const int t = blk - L[lo].ptile_off;
+  const int ty = t / ntx;
+  u.y0 = ty * kPixTile;
+  u.x0 = (t - ty * ntx) * kPixTile;
+  u.pix_off = L[lo].pix_off;
+  return u;
 }
 
-template <bool GRAD>
-__global__ __launch_bounds__(256) void k_pixel(KArgs a) {
-  constexpr int PER = kPixelBlock / 256;
-  __shared__ double s_loss[4][5];
-  const int blk = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  cptr<LayoutRec> LS = konst(a.layouts);
-  const int b = layout_of_pblk(LS, a.num_layouts, blk);
-  const int W = LS[b].W, H = LS[b].H;
-  const int npx = W * H;
-  const int base = (blk - LS[b].pblk_off) * kPixelBlock;
-  double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
-  if (GRAD && a.dloss) {
-    c_ov *= (double)a.dloss[5 * b + 0];
-    c_c *= (double)a.dloss[5 * b + 1];
-    c_f *= (double)a.dloss[5 * b + 2];
-    c_p *= (double)a.dloss[5 * b + 3];
-    c_d *= (double)a.dloss[5 * b + 4];
+// The pixel of region cell (rx, ry) (0 <= rx, ry < kUniReg), or -1 off the canvas or the region.
+__device__ __forceinline__ int64_t uni_cell_pixel(const PixTile &u, int rx, int ry) {
+  const int gx = u.x0 - kUniHalo + rx, gy = u.y0 - kUniHalo + ry;
+  if (rx >= kUniReg || ry >= kUniReg || gx < 0 || gx >= u.W || gy < 0 || gy >= u.H) return -1;
+  return u.pix_off + (int64_t)gy * u.W + gx;
+}
+
+// Zeroes row 0 and column 0 of NCH tables.
+template <int NCH>
+__device__ __forceinline__ void uni_zero_border(unsigned long long *T) {
+  for (int i = threadIdx.x; i < NCH * kUniPitch; i += kPixThreads) {
+    unsigned long long *t = T + (i / kUniPitch) * kUniPitch * kUniPitch;
+    const int k = i % kUniPitch;
+    t[k] = 0ull;
+    t[k * kUniPitch] = 0ull;
   }
-  unsigned long long s0[PER], s1[PER];
-  float mk[PER];
+}
+
+// Summed-area tables of NCH sets of region values v[c] (wave w holds rows w kUniBand + i in v[c][i],
+// lane = column; zero at lanes and rows outside the region) into T + c kUniPitch^2:
+// T[(ry + 1) kUniPitch + rx + 1] = sum of the values at rows <= ry, columns <= rx.  Row prefix sums are
+// wave scans, column sums run down each wave's band in registers and are then offset by the totals of
+// the bands above.  Two barriers: band totals are exchanged after the first (so every read of T before
+// the call is complete when T is rewritten), and T is complete after the second.
+template <int NCH>
+__device__ void sat_build(unsigned long long *T, unsigned long long *band_tot,
+                          unsigned long long (&v)[NCH][kUniBand]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long col[NCH];
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = base + k * 256 + tid;
-    s0[k] = s1[k] = 0ull;
-    mk[k] = 0.0f;
-    if (i < npx) {
-      const int64_t pix = LS[b].pix_off + i;
-      s0[k] = a.acc[2 * pix];
-      s1[k] = a.acc[2 * pix + 1];
-      mk[k] = a.mask[pix];
+  for (int c = 0; c < NCH; ++c) col[c] = 0ull;
+#pragma unroll
+  for (int i = 0; i < kUniBand; ++i) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      col[c] += wave_incl_scan_u64(v[c][i]);
+      v[c][i] = col[c];
     }
   }
-  double term[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = base + k * 256 + tid;
-    if (i < npx) {
-      const int64_t pix = LS[b].pix_off + i;
-      const double S = (double)s0[k] * kFixInv, Sp = (double)s1[k] * kFixInv, M = (double)mk[k];
-      if (a.cov_out) a.cov_out[pix] = (float)S;
-      if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
-      const int pyi = i / W;
-      const double yinv = (double)H - (pyi + 0.5);
-      const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
-      term[0] += ov * ov;
-      term[1] += S * (1.0 - M);
-      term[2] += M * (un * un);
-      term[3] += pv * pv;
-      term[4] += S * yinv;
-      if (GRAD) {
-        const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
-        const double Gp = 2.0 * c_p * pv;
-        a.gbuf[pix] = make_double2(G, Gp);
+  for (int c = 0; c < NCH; ++c) band_tot[(c * kPixWaves + w) * 64 + lane] = col[c];
+  __syncthreads();
+  if (lane < kUniReg) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      // every band total is loaded (issued together), those of the bands above are added
+      unsigned long long off = 0ull;
+#pragma unroll
+      for (int q = 0; q < kPixWaves; ++q) {
+        const unsigned long long t = band_tot[(c * kPixWaves + q) * 64 + lane];
+        off += q < w ? t : 0ull;
+      }
+#pragma unroll
+      for (int i = 0; i < kUniBand; ++i) {
+        const int ry = w * kUniBand + i;
+        if (ry < kUniReg) T[c * kUniPitch * kUniPitch + (ry + 1) * kUniPitch + lane + 1] = v[c][i] + off;
       }
     }
   }
+  __syncthreads();
+}
+
+// Sum of the values in the window of radius r around region cell (cx, cy) (0-based region coordinates).
+// Unsigned wrap-around cancels in the four-corner difference, so the result is exact whenever the
+// window sum itself fits.
+__device__ __forceinline__ unsigned long long sat_box(const unsigned long long *T, int cx, int cy, int r) {
+  const int xa = cx - r, xb = cx + r + 1, ya = (cy - r) * kUniPitch, yb = (cy + r + 1) * kUniPitch;
+  return ((T[yb + xb] - T[ya + xb]) - T[yb + xa]) + T[ya + xa];
+}
+
+// k_pixel: S, S_pad, the loss terms (summed per tile) and dLoss/dS, dLoss/dS_pad of the per-pixel
+// terms.  UNI (uniform weight != 0): also the A_j of the tile's pixels, the uniform term, and for the
+// gradient the bits M != 0 and A_j < 1 that k_unif_grad needs.
+template <bool GRAD, bool UNI>
+__global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
+  __shared__ double s_loss[kPixWaves][kLossTerms];
+  __shared__ unsigned long long T[UNI ? kUniPitch * kUniPitch : 1];
+  __shared__ unsigned long long band_tot[UNI ? kPixWaves * 64 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const PixTile u = pix_tile(konst(a.layouts), a.num_layouts, blockIdx.x);
+  const int ox = tid % kPixTile, oy = tid / kPixTile;
+  const int px = u.x0 + ox, py = u.y0 + oy;
+  const bool mine = px < u.W && py < u.H;
+  const int64_t pix = u.pix_off + (int64_t)py * u.W + px;
+  unsigned long long s0 = 0ull, s1 = 0ull;
+  float mk = 0.0f;
+  if (mine) {
+    s0 = a.acc[2 * pix];
+    s1 = a.acc[2 * pix + 1];
+    mk = a.mask[pix];
+  }
+  unsigned long long v[1][kUniBand];
+  if (UNI) {
+    uni_zero_border<1>(T);
+#pragma unroll
+    for (int i = 0; i < kUniBand; ++i) {
+      const int64_t q = uni_cell_pixel(u, lane, w * kUniBand + i);
+      v[0][i] = q >= 0 ? a.acc[2 * q] : 0ull;
+    }
+  }
+  double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
+  if (GRAD && a.dloss) {
+    const float *dl = a.dloss + kLossTerms * u.b;
+    c_ov *= (double)dl[0];
+    c_c *= (double)dl[1];
+    c_f *= (double)dl[2];
+    c_p *= (double)dl[3];
+    c_d *= (double)dl[4];
+  }
+  double term[kLossTerms] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (mine) {
+    const double S = (double)s0 * kFixInv, Sp = (double)s1 * kFixInv, M = (double)mk;
+    if (a.cov_out) a.cov_out[pix] = (float)S;
+    if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
+    const double yinv = (double)u.H - (py + 0.5);
+    const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
+    term[0] = ov * ov;
+    term[1] = S * (1.0 - M);
+    term[2] = M * (un * un);
+    term[3] = pv * pv;
+    term[4] = S * yinv;
+    if (GRAD) {
+      const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
+      const double Gp = 2.0 * c_p * pv;
+      a.gbuf[pix] = make_double2(G, Gp);
+    }
+  }
+  if (UNI) {
+#pragma unroll
+    for (int i = 0; i < kUniBand; ++i) v[0][i] = v[0][i] < kFixOne ? v[0][i] : kFixOne;
+    sat_build<1>(T, band_tot, v);
+    unsigned bits = 0;
+    if (mine && mk != 0.0f) {
+#pragma unroll
+      for (int j = 0; j < kUniWindows; ++j) {
+        const unsigned long long box = sat_box(T, ox + kUniHalo, oy + kUniHalo, uni_radius(j));
+        if (box < kFixOne) {
+          bits |= 1u << j;
+          term[5] += uni_weight(j) * ((double)mk * ((double)(kFixOne - box) * kFixInv));
+        }
+      }
+    }
+    if (GRAD && mine) a.uflags[pix] = (uint8_t)bits;
+  }
   if (a.write_loss) {
 #pragma unroll
-    for (int t = 0; t < 5; ++t) {
-      const double v = wave_sum((double)a.w[t] * term[t]);
-      if (l == 0) s_loss[w][t] = v;
+    for (int t = 0; t < (UNI ? kLossTerms : kLossTerms - 1); ++t) {
+      const double s = wave_sum_dpp((double)a.w[t] * term[t]);
+      if (lane == 0) s_loss[w][t] = s;
     }
     __syncthreads();
-    if (tid < 5) a.block_loss[(int64_t)blk * 5 + tid] = ((s_loss[0][tid] + s_loss[1][tid]) + s_loss[2][tid]) + s_loss[3][tid];
+    if (tid < kLossTerms) {
+      double s = 0.0;
+      if (UNI || tid < kLossTerms - 1)
+        for (int q = 0; q < kPixWaves; ++q) s += s_loss[q][tid];
+      a.block_loss[(int64_t)blockIdx.x * kLossTerms + tid] = s;
+    }
   }
+}
+
+// k_unif_grad: for each window size j, the window sums of F_j = M 1(A_j < 1) (the pixels whose window_j
+// contains q are those in q's own window_j), weighted and added into dLoss/dS where S < 1.
+// A tile whose region has a binary mask (every M 0 or 1) counts the flags: the four counts, at most
+// kUniReg^2 < 2^16 each, travel as 16-bit fields of one 64-bit value through one table (a field's window
+// sum never carries into the next, so each count is exact).  Otherwise the four tables hold M in 2^-40
+// fixed point.
+constexpr int kUniField = 16;
+static_assert(kUniReg * kUniReg < (1 << kUniField) && kUniWindows * kUniField <= 64, "flag counts must fit");
+
+__global__ __launch_bounds__(kPixThreads) void k_unif_grad(KArgs a) {
+  __shared__ unsigned long long T[kUniWindows * kUniPitch * kUniPitch];
+  __shared__ unsigned long long band_tot[kUniWindows * kPixWaves * 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const PixTile u = pix_tile(konst(a.layouts), a.num_layouts, blockIdx.x);
+  const double cu = (double)a.w[5] * (a.dloss ? (double)a.dloss[kLossTerms * u.b + 5] : 1.0);
+  if (cu == 0.0) return;  // the same for every thread of the block
+  const int ox = tid % kPixTile, oy = tid / kPixTile;
+  const int px = u.x0 + ox, py = u.y0 + oy;
+  const int64_t pix = u.pix_off + (int64_t)py * u.W + px;
+  // S < 1 at the thread's own pixel (only there does O = min(S, 1) pass a gradient); its dLoss/dS
+  // is fetched now, with the other loads
+  const bool mine = px < u.W && py < u.H && a.acc[2 * pix] < kFixOne;
+  const double g0 = mine ? a.gbuf[pix].x : 0.0;
+  unsigned fl[kUniBand];
+  float mk[kUniBand];
+  bool binary = true;
+#pragma unroll
+  for (int i = 0; i < kUniBand; ++i) {
+    const int64_t q = uni_cell_pixel(u, lane, w * kUniBand + i);
+    fl[i] = 0u;
+    mk[i] = 0.0f;
+    if (q >= 0) {
+      fl[i] = a.uflags[q];
+      mk[i] = a.mask[q];
+    }
+    binary = binary && (fl[i] == 0u || mk[i] == 1.0f);
+  }
+  uni_zero_border<kUniWindows>(T);
+  double g = 0.0;
+  if (__syncthreads_and(binary)) {
+    unsigned long long v[1][kUniBand];
+#pragma unroll
+    for (int i = 0; i < kUniBand; ++i) {
+      unsigned long long x = 0ull;
+#pragma unroll
+      for (int j = 0; j < kUniWindows; ++j) x |= (unsigned long long)((fl[i] >> j) & 1u) << (kUniField * j);
+      v[0][i] = x;
+    }
+    sat_build<1>(T, band_tot, v);
+#pragma unroll
+    for (int j = 0; j < kUniWindows; ++j) {
+      const unsigned long long box = sat_box(T, ox + kUniHalo, oy + kUniHalo, uni_radius(j));
+      g += uni_weight(j) * (double)((box >> (kUniField * j)) & ((1ull << kUniField) - 1ull));
+    }
+  } else {
+    unsigned long long v[kUniWindows][kUniBand];
+#pragma unroll
+    for (int i = 0; i < kUniBand; ++i) {
+      const unsigned long long m = fl[i] ? (unsigned long long)llrint((double)mk[i] * kFixScale) : 0ull;
+#pragma unroll
+      for (int j = 0; j < kUniWindows; ++j) v[j][i] = ((fl[i] >> j) & 1u) ? m : 0ull;
+    }
+    sat_build<kUniWindows>(T, band_tot, v);
+#pragma unroll
+    for (int j = 0; j < kUniWindows; ++j)
+      g += uni_weight(j) *
+           (double)(long long)sat_box(T + j * kUniPitch * kUniPitch, ox + kUniHalo, oy + kUniHalo, uni_radius(j));
+    g *= kFixInv;
+  }
+  if (mine && g != 0.0) a.gbuf[pix].x = g0 - cu * g;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1232,27 +1469,27 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
 }
 
 __device__ void finalize_loss(const KArgs &a, int b) {
-  __shared__ double s_part[4][5];
+  __shared__ double s_part[4][kLossTerms];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   cptr<LayoutRec> LS = konst(a.layouts);
-  const int p0 = LS[b].pblk_off;
-  const int np = (int)(((int64_t)LS[b].W * LS[b].H + kPixelBlock - 1) / kPixelBlock);
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int p0 = LS[b].ptile_off;
+  const int np = ((LS[b].W + kPixTile - 1) / kPixTile) * ((LS[b].H + kPixTile - 1) / kPixTile);
+  double s[kLossTerms] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < np; j += 256) {
-    const double *bl = a.block_loss + (int64_t)(p0 + j) * 5;
+    const double *bl = a.block_loss + (int64_t)(p0 + j) * kLossTerms;
 #pragma unroll
-    for (int t = 0; t < 5; ++t) s[t] += bl[t];
+    for (int t = 0; t < kLossTerms; ++t) s[t] += bl[t];
   }
 #pragma unroll
-  for (int t = 0; t < 5; ++t) {
+  for (int t = 0; t < kLossTerms; ++t) {
     const double v = wave_sum(s[t]);
     if (lane == 0) s_part[wave][t] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 5) {
+  if (threadIdx.x < kLossTerms) {
     const int t = threadIdx.x;
     const double v = ((s_part[0][t] + s_part[1][t]) + s_part[2][t]) + s_part[3][t];
-    a.loss_out[5 * b + t] = (float)v;
+    a.loss_out[kLossTerms * b + t] = (float)v;
   }
 }
 
@@ -1373,11 +1610,25 @@ hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start, hip
 }
 
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
-  if (a.total_pblk <= 0) return hipSuccess;
-  if (grad)
-    hipLaunchKernelGGL(k_pixel<true>, dim3(a.total_pblk), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_pixel<false>, dim3(a.total_pblk), dim3(256), 0, st, a);
+  if (a.total_ptiles <= 0) return hipSuccess;
+  const dim3 g(a.total_ptiles), b(kPixThreads);
+  if (a.w[5] != 0.0f) {
+    if (grad)
+      hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, st, a);
+  } else {
+    if (grad)
+      hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_uniform_grad(const KArgs &a, hipStream_t st) {
+  if (a.w[5] == 0.0f || a.total_ptiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unif_grad, dim3(a.total_ptiles), dim3(kPixThreads), 0, st, a);
   return hipGetLastError();
 }
 

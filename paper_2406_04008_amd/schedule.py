@@ -20,6 +20,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
+from . import _lib
 from .collage import CollageScene
 from .scenes import Scene
 
@@ -29,7 +30,7 @@ class LevelRun:
     level: int
     steps: int
     tile: int
-    loss: Optional[np.ndarray] = None    # [B,5] weighted terms of the level's last epoch
+    loss: Optional[np.ndarray] = None    # [B,6] weighted terms of the level's last epoch
     params: Optional[np.ndarray] = None  # [N,4] parameters at the end of the level
     gpu_ms: float = 0.0                  # HIP-event time of the level's graph launch
 
@@ -78,7 +79,7 @@ class CoarseToFine:
         self.v = torch.zeros(N, 4, device=dev)
         self.step = torch.zeros(1, dtype=torch.int32, device=dev)
         self.grad = torch.zeros(N, 4, device=dev)
-        self.losses = [torch.zeros(B, 5, device=dev) for _ in self.levels]
+        self.losses = [torch.zeros(B, _lib.LOSS_TERMS, device=dev) for _ in self.levels]
         self.stream = torch.cuda.Stream(dev)
         self.graphs = None
         if use_graphs:

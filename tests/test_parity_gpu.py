@@ -2,6 +2,7 @@
 
 Every case prints its name before touching the GPU so that a failing run names it.
 """
+import dataclasses
 import math
 import sys
 
@@ -33,6 +34,11 @@ SCENES = {
     # open stroked polylines mixed with closed outlines, ragged canvases, some items off canvas
     "open": lambda: S.random_scene(6, [(71, 53), (40, 66)], [11, 8], kinds=("open", "poly", "open", "star"),
                                    radius=(3.0, 10.0), off_canvas=0.2),
+    # every loss term including the uniform one; canvases ragged against the 32-pixel window tiles,
+    # one smaller than a tile and empty (all windows empty), items partly off canvas
+    "uniform": lambda: dataclasses.replace(
+        S.random_scene(14, [(71, 53), (20, 9), (40, 97), (64, 64)], [9, 0, 7, 10], radius=(3.0, 8.0),
+                       off_canvas=0.2), w_uniform=0.6),
 }
 
 
@@ -71,7 +77,7 @@ def test_backward_parity_autograd(name, tile, oracles):
     cs = CollageScene(sc, tile=tile)
     p = cs.params_tensor().requires_grad_(True)
     rng = np.random.default_rng(1)
-    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 5))
+    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 6))
     loss = CollageLoss.apply(p, cs)
     (loss * torch.tensor(dl, dtype=torch.float32, device=loss.device)).sum().backward()
     g_ref = o.backward(sc.params, dloss=dl)
@@ -193,7 +199,7 @@ def test_graph_replay_matches_eager():
     cs = CollageScene(sc)
     p_g = cs.params_tensor()
     m_g, v_g, s_g = cs.new_state()
-    loss_g = torch.empty(1, 5, device="cuda")
+    loss_g = torch.empty(1, 6, device="cuda")
     grad_g = torch.empty(sc.num_shapes, 4, device="cuda")
     g = cs.graph(p_g, m_g, v_g, s_g, loss_g, grad_g, replays_per_launch=2)
     p_e = cs.params_tensor()
@@ -251,6 +257,80 @@ def test_open_items_vs_central_differences():
     for c in range(4):
         err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
         assert err.max() <= 1e-4, (c, err)
+
+
+def test_uniform_term_vs_central_differences():
+    """The uniform term alone (the other weights 0): GPU gradient against central differences."""
+    sc = dataclasses.replace(SCENES["uniform"](), w_overlap=0.0, w_contain=0.0, w_fill=0.0, w_pad=0.0,
+                             w_down=0.0, w_uniform=1.0)
+    _say("fd uniform")
+    cs = CollageScene(sc)
+    p = cs.params_tensor().requires_grad_(True)
+    CollageLoss.apply(p, cs).sum().backward()
+    o = Oracle(sc)
+    items = list(range(0, sc.num_shapes, 3))
+    fd = o.fd_gradient(sc.params, shapes=items)
+    g = _np(p.grad)
+    floor = 0.01 * np.abs(o.backward(sc.params)).max(0)
+    assert np.abs(fd[items]).max() > 0.0
+    for c in range(4):
+        err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
+        assert err.max() <= 1e-4, (c, err)
+
+
+@pytest.mark.parametrize("level,tile", [(512, 32), (1024, 16)])
+def test_uniform_term_metric_scene(level, tile):
+    """500 Bezier items with every term including the uniform one."""
+    sc = dataclasses.replace(S.config3(0), w_uniform=2e-3)
+    _say("config3 uniform level", level, "tile", tile)
+    o = Oracle(sc, level=level)
+    cs = CollageScene(sc, level=level, tile=tile)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    assert L[0, 5] > 0.0
+    check_image(_np(cov), S_, "S")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+
+
+def test_uniform_term_fractional_mask():
+    """Mask values strictly between 0 and 1 on the first layout (its tiles take the exact fixed-point
+    tables of the gradient pass) and binary masks on the others (packed flag counts), in one launch."""
+    sc = SCENES["uniform"]()
+    w, h, _, _ = sc.layout_arrays(None)
+    n0 = int(w[0]) * int(h[0])
+    m = sc.packed_mask(None).astype(np.float32).copy()
+    rng = np.random.default_rng(3)
+    m[:n0] *= rng.uniform(0.05, 1.0, n0).astype(np.float32)
+    assert np.any((m[:n0] > 0) & (m[:n0] < 1))
+    _say("uniform fractional mask")
+    o = Oracle(sc, mask=m.astype(np.float64))
+    cs = CollageScene(sc, mask=m)
+    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 6))
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+    g = cs.backward(cs.params_tensor(), torch.tensor(dl, dtype=torch.float32, device="cuda"))
+    check_grad(_np(g), o.backward(sc.params, dloss=dl.astype(np.float32).astype(np.float64)))
+
+
+def test_uniform_term_is_deterministic_and_forward_matches_fused():
+    sc = SCENES["uniform"]()
+    _say("uniform determinism")
+    cs = CollageScene(sc, tile=8)
+    p = cs.params_tensor()
+    runs = [cs.forward_backward(p) for _ in range(3)]
+    for r in runs[1:]:
+        for x, y in zip(r, runs[0]):
+            assert torch.equal(x, y)
+    _, _, loss_f = cs.forward(p)
+    assert torch.equal(loss_f, runs[0][2])
+    dl = torch.zeros(sc.num_layouts, 6, device="cuda")
+    dl[:, 5] = 1.0
+    g_u = cs.backward(p, dl)
+    o = Oracle(sc)
+    check_grad(_np(g_u), o.backward(sc.params, dloss=_np(dl).astype(np.float64)))
 
 
 @pytest.mark.parametrize("level,tile", [(256, 16), (2048, 32)])
