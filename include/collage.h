@@ -27,13 +27,21 @@
  *       [3] pad      w_pad     * sum_p relu(S_pad - 1)^2
  *       [4] down     w_down    * sum_p S (H - y_p)
  *       [5] uniform  w_uniform * sum_j (b_j / 5) sum_p M relu(1 - A_j(p))           (Sec. 4.2, eq. 7)
+ *       [6] wmse     w_wmse    * sum_p W(p) (M - min(S, 1))^2                        (Sec. 4.2, eq. 5)
+ *       [7] centre   w_centre  * sum_p S |p - c|, c = (W/2, H/2) the canvas centre   (Sec. 5, central force)
+ *       [8] objdown  w_objdown * sum_i (H - y_i), y_i = k t_y,i the item's origin   (Sec. 5, downward force
+ *                                                                 on the items themselves, object space)
  *     M is the container mask (1 inside), the complement of the paper's container image I_C.  For the
  *     uniform term, b_j = 5 + 6 j (j = 0..3) and A_j(p) is the sum of min(S, 1) over the b_j x b_j
  *     window centred on p, clipped to the canvas: it charges container pixels with no item nearby,
  *     the more the larger the empty window.  Its gradient with respect to S is
  *     -1(S(q) < 1) sum_j (b_j / 5) sum_{p: q in window_j(p)} M(p) 1(A_j(p) < 1) (relu'(0) = 0).  The
  *     window sums are exact integer sums of S in 2^-40 fixed point, so the A_j < 1 decisions depend
- *     only on the accumulated S.
+ *     only on the accumulated S.  In [6], W(p) = 1 M + 100 (1 - M): the penalty mask of eq. 5 (1 inside
+ *     the container, 100 outside) and 1 - min(S, 1) the black-and-white rendering of the items; its
+ *     gradient is -2 W (M - S) where S < 1.  With COLLAGE_FLAG_AREA_MEAN, terms [0]-[3] and [6] of a
+ *     layout are divided by its W * H (the 1 / (w h) of eqs. 5 and 6).  Terms with weight 0 cost no
+ *     reduction and are reported as 0.
  *   - All buffers passed to compute calls are DEVICE memory owned by the caller, float32 unless stated,
  *     contiguous.  Packed images hold the layouts one after another, layout b starting at pixel
  *     sum_{c<b} W_c * H_c.  Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream)
@@ -61,6 +69,9 @@ extern "C" {
 #define COLLAGE_ERR_WORKSPACE (-3)   /* workspace missing or smaller than collage_workspace_size() */
 #define COLLAGE_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
 #define COLLAGE_ERR_UNSUPPORTED (-5) /* unknown flag or tile size */
+
+/* collage_scene_desc.flags: divide the image-mismatch loss terms by the canvas area (eqs. 5, 6) */
+#define COLLAGE_FLAG_AREA_MEAN 1u
 
 
 typedef struct collage_scene collage_scene; /* opaque host handle */
@@ -97,6 +108,7 @@ typedef struct collage_scene_desc {
   float w_overlap, w_contain, w_fill, w_pad, w_down; /* loss weights, finite */
   float w_uniform;              /* weight of the uniform term, finite; 0 = the term is skipped (no
                                    launches) and reported as 0 */
+  float w_wmse, w_centre, w_objdown; /* weights of terms [6]-[8], finite */
   int32_t tile;                 /* screen tile edge in px: 8, 16 or 32; 0 = default (16) */
   int32_t code_capacity;        /* 64-pixel chunks of (tile, item) work whose nearest-edge codes (2 bytes
                                    per pixel) are kept between the coverage and adjoint passes; the
@@ -104,7 +116,7 @@ typedef struct collage_scene_desc {
                                    items per pixel on average, at least 65536 chunks); 0 = always
                                    rescan */
   int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
-  uint32_t flags;               /* reserved: must be 0 */
+  uint32_t flags;               /* 0 or COLLAGE_FLAG_AREA_MEAN; other bits are rejected */
 } collage_scene_desc;
 
 /* Validates `desc`, copies its host arrays and allocates the scene's small device tables.
@@ -123,7 +135,7 @@ int collage_scene_info(const collage_scene *scene, int64_t *num_pixels, int64_t 
  *   params  [N,4]        item parameters
  *   cov     [pixels]     S, written (may be NULL)
  *   cov_pad [pixels]     S_pad, written (may be NULL)
- *   loss    [B,6]        weighted loss terms, written
+ *   loss    [B,9]        weighted loss terms, written
  */
 int collage_forward(const collage_scene *scene, const float *params, float *cov, float *cov_pad, float *loss,
                     void *workspace, size_t workspace_bytes, void *stream);
@@ -132,11 +144,27 @@ int collage_forward(const collage_scene *scene, const float *params, float *cov,
  * Backward pass (the gradient used by eq. 4): d(sum_b sum_t dloss[b,t] * loss[b,t]) / d params.
  * Recomputes the coverage and every pixel's nearest edge from params (no per-pixel, per-item
  * intermediates are stored between calls, and no image from the forward pass is needed).
- *   dloss [B,6]  upstream gradient of each loss term
+ *   dloss [B,9]  upstream gradient of each loss term
  *   grad  [N,4]  overwritten
  */
 int collage_backward(const collage_scene *scene, const float *params, const float *dloss, float *grad,
                      void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Gradient with respect to the outline vertices (Sec. 3 "Vector Representation": the items' control
+ * points are fitted to their silhouettes by differentiable rendering), together with the parameter
+ * gradient of collage_backward.  Each pixel's signed distance moves with the two end points of its
+ * nearest edge (weights 1 - u and u of the nearest point); the sums go back through eq. 2
+ * (dv'/dv = k s R(theta)).  Term [8] does not depend on the vertices.
+ *   dloss      [B,9]  upstream gradient of each loss term
+ *   grad       [N,4]  overwritten, or NULL (then only the vertex gradient is computed)
+ *   grad_verts [V,2]  overwritten: dLoss/d(vertex) in the item frame, canonical px; NaN for the
+ *                     vertices of an item with a non-finite parameter
+ * The vertex sums are accumulated in 2^-32 fixed point (deterministic; a sum must stay below 2^31 in
+ * magnitude).
+ */
+int collage_backward_vertices(const collage_scene *scene, const float *params, const float *dloss, float *grad,
+                              float *grad_verts, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Forward and backward of the total loss sum_b sum_t loss[b,t] in one pass over the pixels
@@ -157,7 +185,7 @@ int collage_step(const collage_scene *scene, float *params, const float *grad, f
 /*
  * One optimization epoch of Fig. 2: forward, loss, backward and the Adam update of collage_step,
  * in kernel launches with fixed grids (safe to capture in a hipGraph and replay).
- * cov / cov_pad may be NULL.  loss [B,6] and grad [N,4] receive this epoch's values (before the update).
+ * cov / cov_pad may be NULL.  loss [B,9] and grad [N,4] receive this epoch's values (before the update).
  */
 int collage_iterate(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                     float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,

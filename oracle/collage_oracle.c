@@ -26,8 +26,17 @@
  *     and the uniform loss of Sec. 4.2 (eq. 7), read as: O = min(S, 1); for bandwidths
  *     b_j = 5 + 6 j (j < NUNI), A_j(p) = sum of O over the b_j x b_j window centred on p (clipped to
  *     the canvas);  L_unif = sum_j (b_j / b_0) sum_p M(p) relu(1 - A_j(p))  -- container pixels with
- *     no item within the window, larger windows weighted more.
- *     reported weighted: loss[b][term] = w_term * L_term (NTERMS terms per layout).
+ *     no item within the window, larger windows weighted more;
+ *     the weighted mean square error of Sec. 4.2 (eq. 5) between the black-and-white rendering
+ *     1 - O and the container image 1 - M, with penalty 1 inside the container and 100 outside:
+ *        L_wmse = sum_p W(p) (M - O)^2,  W = WMSE_IN M + WMSE_OUT (1 - M);
+ *     and the force terms of Sec. 5 ("Force Attraction"): a central force towards the canvas centre c,
+ *        L_centre = sum_p S |p - c|,
+ *     and a downward force on the items themselves (object space), with y_i = k t_y,i the item origin,
+ *        L_objdown = sum_i (H - y_i).
+ *     reported weighted: loss[b][term] = w_term * L_term (NTERMS terms per layout); with area_mean the
+ *     image-mismatch terms (overlap, contain, fill, pad, wmse) are divided by W * H, the 1 / (w h) of
+ *     eqs. 5 and 6.
  *   - The gradient of sum_b sum_term dloss[b][term] * loss[b][term] with respect to every item's
  *     (t_x, t_y, theta, s) (Sec. 4, eq. 4 needs dL/dt, dL/dr, dL/ds), by the chain rule through the
  *     two end points of each pixel's nearest edge and then through eq. 2.
@@ -44,7 +53,9 @@
 #include <omp.h>
 #endif
 
-#define NTERMS 6 /* loss terms per layout */
+#define NTERMS 9 /* loss terms per layout */
+#define WMSE_IN 1.0    /* eq. 5 penalty inside the container */
+#define WMSE_OUT 100.0 /* and outside */
 #define NUNI 4   /* window sizes of the uniform loss */
 
 static int uni_radius(int j) { return 2 + 3 * j; }                     /* window (2 r + 1) = 5 + 6 j */
@@ -62,11 +73,19 @@ typedef struct {
   const double *verts;      /* [V*2] local frame, canonical px */
   const double *mask;       /* packed masks, layout b at pixel offset sum_{c<b} W_c*H_c */
   double tau, r_cut, r_pad;
-  double w[6];              /* overlap, contain, fill, pad, down, uniform */
+  double w[9];              /* overlap, contain, fill, pad, down, uniform, wmse, centre, objdown */
   int32_t use_cutoff;       /* 1: hard zero below -r_cut (the definition); 0: no cut-off */
   int32_t use_bbox;         /* 1: skip pixels provably beyond the cut-off support (needs use_cutoff) */
   const double *stroke;     /* [N] stroke half-width, canonical px (> 0: open polyline), or NULL */
+  int32_t area_mean;        /* 1: overlap, contain, fill, pad and wmse are divided by W * H */
 } oracle_scene;
+
+/* 1 / (W H) for the image-mismatch terms when area_mean is set, else 1. */
+static double term_norm(const oracle_scene *sc, int b, int t) {
+  if (!sc->area_mean) return 1.0;
+  if (t == 0 || t == 1 || t == 2 || t == 3 || t == 6) return 1.0 / ((double)sc->width[b] * sc->height[b]);
+  return 1.0;
+}
 
 static int64_t pixel_offset(const oracle_scene *sc, int b) {
   int64_t off = 0;
@@ -368,10 +387,10 @@ static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, 
     const int W = sc->width[b], H = sc->height[b];
     const int64_t off = pixel_offset(sc, b);
     /* per-row partial sums, added in row order afterwards, so the result does not depend on threads */
-    double *rows = (double *)calloc((size_t)5 * (H > 0 ? H : 1), sizeof(double));
+    double *rows = (double *)calloc((size_t)7 * (H > 0 ? H : 1), sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < H; ++j) {
-      double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0;
+      double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0, lw = 0, lcen = 0;
       for (int i = 0; i < W; ++i) {
         const double px = i + 0.5, py = j + 0.5;
         double s = 0.0, spad = 0.0;
@@ -397,29 +416,44 @@ static void forward_impl(const oracle_scene *sc, const prepared *pr, double *S, 
         lf += M * un * un;
         lp += pv * pv;
         ld += s * (H - py);
+        const double O = s < 1.0 ? s : 1.0;
+        const double Wp = WMSE_IN * M + WMSE_OUT * (1.0 - M);
+        lw += Wp * (M - O) * (M - O);
+        const double cx = px - 0.5 * W, cy = py - 0.5 * H;
+        lcen += s * sqrt(cx * cx + cy * cy);
       }
-      rows[5 * j + 0] = lo;
-      rows[5 * j + 1] = lc;
-      rows[5 * j + 2] = lf;
-      rows[5 * j + 3] = lp;
-      rows[5 * j + 4] = ld;
+      rows[7 * j + 0] = lo;
+      rows[7 * j + 1] = lc;
+      rows[7 * j + 2] = lf;
+      rows[7 * j + 3] = lp;
+      rows[7 * j + 4] = ld;
+      rows[7 * j + 5] = lw;
+      rows[7 * j + 6] = lcen;
     }
-    double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0;
+    double lo = 0, lc = 0, lf = 0, lp = 0, ld = 0, lw = 0, lcen = 0;
     for (int j = 0; j < H; ++j) {
-      lo += rows[5 * j + 0];
-      lc += rows[5 * j + 1];
-      lf += rows[5 * j + 2];
-      lp += rows[5 * j + 3];
-      ld += rows[5 * j + 4];
+      lo += rows[7 * j + 0];
+      lc += rows[7 * j + 1];
+      lf += rows[7 * j + 2];
+      lp += rows[7 * j + 3];
+      ld += rows[7 * j + 4];
+      lw += rows[7 * j + 5];
+      lcen += rows[7 * j + 6];
     }
     free(rows);
     if (loss) {
-      loss[NTERMS * b + 0] = sc->w[0] * lo;
-      loss[NTERMS * b + 1] = sc->w[1] * lc;
-      loss[NTERMS * b + 2] = sc->w[2] * lf;
-      loss[NTERMS * b + 3] = sc->w[3] * lp;
+      /* object-space downward force: the item origins' heights above the bottom edge */
+      double lod = 0.0;
+      for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) lod += H - sc->scale[b] * pr->params[4 * q + 1];
+      loss[NTERMS * b + 0] = sc->w[0] * term_norm(sc, b, 0) * lo;
+      loss[NTERMS * b + 1] = sc->w[1] * term_norm(sc, b, 1) * lc;
+      loss[NTERMS * b + 2] = sc->w[2] * term_norm(sc, b, 2) * lf;
+      loss[NTERMS * b + 3] = sc->w[3] * term_norm(sc, b, 3) * lp;
       loss[NTERMS * b + 4] = sc->w[4] * ld;
       loss[NTERMS * b + 5] = sc->w[5] != 0.0 && S ? sc->w[5] * uniform_loss(sc, b, S + off) : 0.0;
+      loss[NTERMS * b + 6] = sc->w[6] * term_norm(sc, b, 6) * lw;
+      loss[NTERMS * b + 7] = sc->w[7] * lcen;
+      loss[NTERMS * b + 8] = sc->w[8] * lod;
     }
   }
 }
@@ -516,7 +550,21 @@ int oracle_signed_distance(const oracle_scene *sc, const double *params, int fir
  *     dv'/dt = k I,   dv'/dtheta = k s R'(theta) v,   dv'/ds = k R(theta) v.
  * A pixel centre lying exactly on the outline (|p - q| = 0) contributes nothing.
  */
+int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
+                         double *grad_verts);
+
 int oracle_backward(const oracle_scene *sc, const double *params, const double *dloss, double *grad) {
+  return oracle_backward_full(sc, params, dloss, grad, NULL);
+}
+
+/*
+ * As oracle_backward, and (grad_verts not NULL) the gradient with respect to every item's outline
+ * vertices in its own frame, [V*2] canonical px (Sec. 3 "Vector Representation": the outline control
+ * points are fitted by differentiable rendering): each pixel's dsd/dv' of the two end points of its
+ * nearest edge, mapped back through eq. 2, dv'/dv = k s R(theta):  dL/dv = omega (k s R)^T dsd/dv'.
+ */
+int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
+                         double *grad_verts) {
   if (!sc || !params || !dloss || !grad) return -1;
   if (sc->use_bbox && !sc->use_cutoff) return -1;
   prepared pr;
@@ -530,9 +578,13 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b], H = sc->height[b];
     const int64_t off = pixel_offset(sc, b);
-    const double c_ov = dloss[NTERMS * b + 0] * sc->w[0], c_c = dloss[NTERMS * b + 1] * sc->w[1];
-    const double c_f = dloss[NTERMS * b + 2] * sc->w[2], c_p = dloss[NTERMS * b + 3] * sc->w[3];
+    const double c_ov = dloss[NTERMS * b + 0] * sc->w[0] * term_norm(sc, b, 0);
+    const double c_c = dloss[NTERMS * b + 1] * sc->w[1] * term_norm(sc, b, 1);
+    const double c_f = dloss[NTERMS * b + 2] * sc->w[2] * term_norm(sc, b, 2);
+    const double c_p = dloss[NTERMS * b + 3] * sc->w[3] * term_norm(sc, b, 3);
     const double c_d = dloss[NTERMS * b + 4] * sc->w[4];
+    const double c_w = dloss[NTERMS * b + 6] * sc->w[6] * term_norm(sc, b, 6);
+    const double c_cen = dloss[NTERMS * b + 7] * sc->w[7];
     for (int j = 0; j < H; ++j)
       for (int i = 0; i < W; ++i) {
         const int64_t idx = off + (int64_t)j * W + i;
@@ -542,6 +594,10 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
         const double un = s < 1.0 ? 1.0 - s : 0.0;
         const double pv = sp > 1.0 ? sp - 1.0 : 0.0;
         G[idx] = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * M * un + c_d * (H - (j + 0.5));
+        /* d/dS of W (M - min(S, 1))^2 */
+        if (s < 1.0) G[idx] -= 2.0 * c_w * (WMSE_IN * M + WMSE_OUT * (1.0 - M)) * (M - s);
+        const double cx = i + 0.5 - 0.5 * W, cy = j + 0.5 - 0.5 * H;
+        G[idx] += c_cen * sqrt(cx * cx + cy * cy);
         Gp[idx] = 2.0 * c_p * pv;
       }
     uniform_grad(sc, b, S + off, dloss[NTERMS * b + 5] * sc->w[5], G + off);
@@ -554,6 +610,9 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
     for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) {
       const int n = sc->vert_off[q + 1] - sc->vert_off[q];
       double g[4] = {0, 0, 0, 0};
+      double *gv = grad_verts ? grad_verts + 2 * sc->vert_off[q] : NULL;
+      if (gv)
+        for (int m = 0; m < 2 * n; ++m) gv[m] = 0.0;
       if (n > 0) {
         const double *P = pr.P + 2 * sc->vert_off[q];
         const double th = params[4 * q + 2], s = params[4 * q + 3];
@@ -603,9 +662,16 @@ int oracle_backward(const oracle_scene *sc, const double *params, const double *
               /* dv'/ds = k R(theta) v */
               const double rsx = k * (c * lx - sn * ly), rsy = k * (sn * lx + c * ly);
               g[3] += omega * (dvx * rsx + dvy * rsy);
+              /* dv'/dv = k s R(theta) */
+              if (gv) {
+                gv[2 * vm[e] + 0] += omega * k * s * (c * dvx + sn * dvy);
+                gv[2 * vm[e] + 1] += omega * k * s * (-sn * dvx + c * dvy);
+              }
             }
           }
       }
+      /* object-space downward force: d(H - k t_y)/dt_y = -k */
+      g[1] -= dloss[NTERMS * b + 8] * sc->w[8] * k;
       for (int e = 0; e < 4; ++e) grad[4 * q + e] = g[e];
     }
   }

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "collage_oracle.c")
 
-NTERMS = 6  # loss terms per layout: overlap, contain, fill, pad, down, uniform
+NTERMS = 9  # loss terms per layout: overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -28,9 +28,10 @@ class _OracleScene(ctypes.Structure):
         ("width", _ip), ("height", _ip), ("scale", _dp), ("shape_off", _ip), ("vert_off", _ip),
         ("verts", _dp), ("mask", _dp),
         ("tau", ctypes.c_double), ("r_cut", ctypes.c_double), ("r_pad", ctypes.c_double),
-        ("w", ctypes.c_double * 6),
+        ("w", ctypes.c_double * 9),
         ("use_cutoff", ctypes.c_int32), ("use_bbox", ctypes.c_int32),
         ("stroke", _dp),
+        ("area_mean", ctypes.c_int32),
     ]
 
 
@@ -56,6 +57,7 @@ def lib():
         L.oracle_render.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.oracle_signed_distance.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_int, ctypes.c_int, _dp, _ip]
         L.oracle_backward.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, _dp]
+        L.oracle_backward_full.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, _dp, _dp]
         L.oracle_adam.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
         L.oracle_collage_lr.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_double, _dp]
@@ -99,6 +101,7 @@ class Oracle:
         s.use_cutoff, s.use_bbox = int(use_cutoff), int(use_bbox and use_cutoff)
         self.stroke = None if getattr(scene, "stroke", None) is None else _d(scene.stroke)
         s.stroke = _ptr(self.stroke) if self.stroke is not None and self.stroke.size else None
+        s.area_mean = int(bool(getattr(scene, "area_mean", False)))
         self._s = s
 
     @property
@@ -157,6 +160,35 @@ class Oracle:
         rc = lib().oracle_backward(ctypes.byref(self._s), _ptr(p), _ptr(dl), _ptr(g))
         assert rc == 0
         return g[: 4 * self.scene.num_shapes].reshape(-1, 4)
+
+    def backward_vertices(self, params, dloss=None):
+        """(grad [N,4], grad_verts [V,2]): the gradient with respect to the parameters and to every
+        outline vertex in its item's frame."""
+        p = _d(params).reshape(-1)
+        B = self.scene.num_layouts
+        dl = np.ones(NTERMS * B) if dloss is None else _d(dloss).reshape(-1)
+        if dl.size != NTERMS * B:
+            raise ValueError(f"dloss must have {NTERMS} entries per layout")
+        g = np.zeros(4 * max(self.scene.num_shapes, 1))
+        gv = np.zeros(2 * max(self.scene.num_verts, 1))
+        rc = lib().oracle_backward_full(ctypes.byref(self._s), _ptr(p), _ptr(dl), _ptr(g), _ptr(gv))
+        assert rc == 0
+        return g[: 4 * self.scene.num_shapes].reshape(-1, 4), gv[: 2 * self.scene.num_verts].reshape(-1, 2)
+
+    def fd_vertex_gradient(self, params, vertices, h=1e-4, dloss=None):
+        """Central differences of the total loss with respect to the listed vertices ([len, 2]), each
+        coordinate stepped by h canonical px in the item frame."""
+        out = np.zeros((len(vertices), 2))
+        for r, m in enumerate(vertices):
+            for c in range(2):
+                base = self.verts[2 * m + c]
+                self.verts[2 * m + c] = base + h
+                lp = self.loss(params, dloss)
+                self.verts[2 * m + c] = base - h
+                lm = self.loss(params, dloss)
+                self.verts[2 * m + c] = base
+                out[r, c] = (lp - lm) / (2 * h)
+        return out
 
     def learning_rates(self, lr_px=None):
         lr_px = self.scene.lr_px if lr_px is None else lr_px

@@ -20,7 +20,8 @@ ERR_WORKSPACE = -3
 ERR_HIP = -4
 ERR_UNSUPPORTED = -5
 FLAG_NONE = 0
-LOSS_TERMS = 6  # overlap, contain, fill, pad, down, uniform
+FLAG_AREA_MEAN = 1
+LOSS_TERMS = 9  # overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -36,6 +37,7 @@ class SceneDesc(ctypes.Structure):
         ("tau", ctypes.c_float), ("r_cut", ctypes.c_float), ("r_pad", ctypes.c_float),
         ("w_overlap", ctypes.c_float), ("w_contain", ctypes.c_float), ("w_fill", ctypes.c_float),
         ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float), ("w_uniform", ctypes.c_float),
+        ("w_wmse", ctypes.c_float), ("w_centre", ctypes.c_float), ("w_objdown", ctypes.c_float),
         ("tile", ctypes.c_int32), ("code_capacity", ctypes.c_int32), ("bin_chunk", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
     ]
@@ -50,6 +52,7 @@ SIGNATURES = [
     ("collage_forward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_forward_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("collage_backward_vertices", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_step", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _vp]),
     ("collage_iterate", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,

@@ -76,7 +76,10 @@ class CollageScene:
         d.stroke = self.stroke.data_ptr() if self.stroke is not None else None
         d.tau, d.r_cut, d.r_pad = scene.tau, scene.r_cut, scene.r_pad
         w = scene.weights()
-        d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down, d.w_uniform = w
+        (d.w_overlap, d.w_contain, d.w_fill, d.w_pad, d.w_down, d.w_uniform, d.w_wmse, d.w_centre,
+         d.w_objdown) = w
+        if getattr(scene, "area_mean", False):
+            flags |= _lib.FLAG_AREA_MEAN
         d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags
         self._desc = d
         h_ = ctypes.c_void_p()
@@ -128,6 +131,22 @@ class CollageScene:
                                        _stream(self.device))
         _lib.check(rc, "collage_backward")
         return grad
+
+    def backward_vertices(self, params: torch.Tensor, dloss: Optional[torch.Tensor] = None, want_grad: bool = True):
+        """(grad [N,4] or None, grad_verts [V,2]): the gradient of sum(dloss * loss) (dloss = 1 when None)
+        with respect to the parameters and to the outline vertices in their item frames.  The vertices
+        are read from `self.verts` on every call, so they can be optimized in place."""
+        _need(params, (self.N, 4), "params")
+        if dloss is None:
+            dloss = torch.ones(self.B, _lib.LOSS_TERMS, device=self.device)
+        _need(dloss, (self.B, _lib.LOSS_TERMS), "dloss")
+        grad = torch.empty(self.N, 4, device=self.device) if want_grad else None
+        grad_verts = torch.empty(self.scene.num_verts, 2, device=self.device)
+        ws, nb = self._ws()
+        rc = self.lib.collage_backward_vertices(self.handle, _ptr(params), _ptr(dloss), _ptr(grad), _ptr(grad_verts),
+                                                ws, nb, _stream(self.device))
+        _lib.check(rc, "collage_backward_vertices")
+        return grad, grad_verts
 
     def forward_backward(self, params: torch.Tensor, want_cov: bool = True):
         _need(params, (self.N, 4), "params")
@@ -278,7 +297,7 @@ class Timer:
 
 
 class CollageLoss(torch.autograd.Function):
-    """loss[B,6] = CollageLoss.apply(params[N,4], scene): the weighted loss terms of every layout.
+    """loss[B,9] = CollageLoss.apply(params[N,4], scene): the weighted loss terms of every layout.
 
     The backward recomputes the coverage and each pixel's nearest edge in the HIP adjoint kernel;
     only the parameters are saved between the passes."""

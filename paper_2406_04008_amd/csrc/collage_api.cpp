@@ -47,7 +47,7 @@ struct collage_scene {
   std::vector<int32_t> vert_off;
   const float *verts = nullptr, *rho = nullptr, *mask = nullptr, *stroke = nullptr;
   float tau = 0.5f, r_cut = 8.0f, r_pad = 0.0f;
-  float w[6] = {1, 1, 1, 0, 0, 0};
+  float w[kLossTerms] = {1, 1, 1, 0, 0, 0, 0, 0, 0};
   int64_t total_pixels = 0, total_tiles = 0, list_total = 0, total_ptiles = 0, total_rows = 0, row_list_total = 0;
   int32_t max_canvas = 0;
   // device tables owned by the scene
@@ -57,7 +57,7 @@ struct collage_scene {
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_islot = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
-         off_gbuf = 0, off_codes = 0, off_uflags = 0;
+         off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0;
   size_t ws_bytes = 0;
 };
 
@@ -106,7 +106,8 @@ int validate_desc(const collage_scene_desc *d) {
   if (!(d->tau > 0.0f) || !std::isfinite(d->tau)) return fail(COLLAGE_ERR_INVALID, "tau must be finite and > 0");
   if (!(d->r_cut >= 0.0f) || !std::isfinite(d->r_cut)) return fail(COLLAGE_ERR_INVALID, "r_cut must be finite and >= 0");
   if (!(d->r_pad >= 0.0f) || !std::isfinite(d->r_pad)) return fail(COLLAGE_ERR_INVALID, "r_pad must be finite and >= 0");
-  const float ws[6] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down, d->w_uniform};
+  const float ws[kLossTerms] = {d->w_overlap, d->w_contain, d->w_fill, d->w_pad, d->w_down,
+                                d->w_uniform, d->w_wmse, d->w_centre, d->w_objdown};
   for (float x : ws)
     if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32)
@@ -114,7 +115,7 @@ int validate_desc(const collage_scene_desc *d) {
   if (d->code_capacity < -1) return fail(COLLAGE_ERR_INVALID, "code_capacity must be -1 or >= 0");
   if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)
     return fail(COLLAGE_ERR_INVALID, "bin_chunk must be 0..%d", kMaxBinChunk);
-  if (d->flags != 0) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(uint32_t)COLLAGE_FLAG_AREA_MEAN) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
   return COLLAGE_OK;
 }
 
@@ -166,7 +167,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.r_pad = s->r_pad;
   a.inv_tau_d = 1.0 / (double)s->tau;
   a.pad_factor = std::exp(-(double)s->r_pad / (double)s->tau);
-  for (int i = 0; i < 6; ++i) a.w[i] = s->w[i];
+  for (int i = 0; i < kLossTerms; ++i) a.w[i] = s->w[i];
+  a.area_mean = (s->flags & COLLAGE_FLAG_AREA_MEAN) ? 1 : 0;
   return a;
 }
 
@@ -220,6 +222,9 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->w[3] = desc->w_pad;
   s->w[4] = desc->w_down;
   s->w[5] = desc->w_uniform;
+  s->w[6] = desc->w_wmse;
+  s->w[7] = desc->w_centre;
+  s->w[8] = desc->w_objdown;
   s->vert_off.assign(desc->vert_offset, desc->vert_offset + s->N + 1);
   s->layouts.resize(s->B);
   int64_t pix = 0, tiles = 0, list = 0, ptiles = 0, rows = 0, rlist = 0;
@@ -287,6 +292,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + sizeof(double) * kLossTerms * (size_t)ptiles);
   s->off_uflags = off;
   off = align256(off + (size_t)pix);
+  s->off_vacc = off;
+  off = align256(off + 2 * sizeof(unsigned long long) * (size_t)s->V);
   s->off_list = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
   s->off_islot = off;
@@ -398,6 +405,35 @@ int collage_backward(const collage_scene *s, const float *params, const float *d
   if (e == hipSuccess) e = launch_adjoint(a, st);
   if (e == hipSuccess) e = launch_finalize(a, true, false, false, st);
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward launch");
+}
+
+int collage_backward_vertices(const collage_scene *s, const float *params, const float *dloss, float *grad,
+                              float *grad_verts, void *ws, size_t ws_bytes, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (!dloss) return fail(COLLAGE_ERR_INVALID, "dloss is NULL");
+  if (s->N > 0 && (!params || (s->V > 0 && !grad_verts)))
+    return fail(COLLAGE_ERR_INVALID, "params or grad_verts is NULL");
+  int rc = check_ws(s, ws, ws_bytes);
+  if (rc) return rc;
+  if (s->N == 0) return COLLAGE_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KArgs a = base_args(s, ws);
+  a.params = params;
+  a.dloss = dloss;
+  a.grad_out = grad;
+  a.grad_verts_out = grad_verts;
+  a.vacc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + s->off_vacc);
+  a.keep_codes = 1;
+  hipError_t e = launch_transform(a, st);
+  if (e == hipSuccess) e = launch_bin(a, st);
+  if (e == hipSuccess) e = launch_scan(a, st);
+  if (e == hipSuccess) e = launch_cover(a, st);
+  if (e == hipSuccess) e = launch_pixel(a, true, st);
+  if (e == hipSuccess) e = launch_uniform_grad(a, st);
+  if (e == hipSuccess && grad) e = launch_adjoint(a, st);
+  if (e == hipSuccess && grad) e = launch_finalize(a, true, false, false, st);
+  if (e == hipSuccess) e = launch_vertex_grad(a, st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward_vertices launch");
 }
 
 int collage_forward_backward(const collage_scene *s, const float *params, float *cov, float *cov_pad, float *loss,

@@ -112,6 +112,9 @@ struct KArgs {
                             // piece of a unit that starts at the chunk, 0 for other chunks
   double *block_loss;       // per pixel tile: the kLossTerms weighted loss-term sums
   uint8_t *uflags;          // [pixels] bit j: M != 0 and A_j < 1 (the uniform term's active windows)
+  unsigned long long *vacc; // [V][2] outline-vertex adjoint sums, level frame, 2^-32 fixed point; null
+                            // unless vertex gradients are asked for (the transform kernel zeroes them)
+  float *grad_verts_out;    // [V,2] dLoss/d(vertex) in the item frame
   int32_t *step_inc;        // incremented once per epoch by the scan kernel when not null
   // images
   float *cov_out;
@@ -123,7 +126,8 @@ struct KArgs {
   float tau, inv_tau, r_cut, r_pad;
   double inv_tau_d;      // 1 / tau
   double pad_factor;     // e^(-r_pad / tau)
-  float w[6];            // overlap, contain, fill, pad, down, uniform
+  float w[9];            // overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
+  int32_t area_mean;     // 1: overlap, contain, fill, pad and wmse are divided by the layout's W * H
   // finalize / Adam
   float *loss_out;
   float *grad_out;
@@ -142,6 +146,9 @@ hipError_t launch_scan(const KArgs &a, hipStream_t st);
 hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st);
 hipError_t launch_adjoint(const KArgs &a, hipStream_t st);
+// dLoss/d(outline vertices) into a.grad_verts_out (needs a.vacc, zeroed by this call's transform, and
+// the codes and dLoss/dS of this call's coverage and per-pixel passes)
+hipError_t launch_vertex_grad(const KArgs &a, hipStream_t st);
 // the uniform term's share of dLoss/dS, added into gbuf after launch_pixel(grad = true) (nothing is
 // launched when its weight is 0)
 hipError_t launch_uniform_grad(const KArgs &a, hipStream_t st);
@@ -160,7 +167,9 @@ constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
 constexpr int64_t kRowBinTests = 1 << 21;  // box tests (tiles x items) above which the row pass is used
-constexpr int kLossTerms = 6;   // overlap, contain, fill, pad, down, uniform
+constexpr int kLossTerms = 9;   // overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
+constexpr double kWmseIn = 1.0;    // eq. 5 penalty inside the container
+constexpr double kWmseOut = 100.0; // and outside
 constexpr int kUniWindows = 4;  // window sizes 5 + 6 j of the uniform term
 constexpr int kUniHalo = 11;    // largest window radius (2 + 3 (kUniWindows - 1))
 constexpr int kPixTile = 32;    // pixel tile edge of the per-pixel and window passes

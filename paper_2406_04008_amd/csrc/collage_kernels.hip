@@ -160,6 +160,8 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
   const double s = finite ? (double)p.w : 1.0;
   const double cx = k * (double)p.x, cy = k * (double)p.y;
   const float2 *V = reinterpret_cast<const float2 *>(a.verts) + v0;
+  if (a.vacc)
+    for (int m = lane; m < 2 * n; m += 64) a.vacc[2 * v0 + m] = 0ull;
   // an open item has edges between consecutive vertices only (a single vertex: one point edge)
   const float wst = a.stroke ? a.stroke[sid] : 0.0f;
   const bool open = wst > 0.0f;
@@ -396,33 +398,27 @@ __device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double 
   alp = 1.0 / (1.0 + E * a.pad_factor);
 }
 
-// Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
-// translation terms applied by the finalize kernel.  omega = G dalpha/dsd + G_pad dalpha_pad/dsd.
-// For an open item (sw_ds != 0 or open) q.sd = sw - d, par is false (the gradient of -d), and the
-// stroke radius adds d sd / d s = sw_ds.
-__device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
-                                                 bool par, float orient, double G, double Gp, bool open,
-                                                 double sw_ds) {
-  // d alpha / d sd and d alpha_pad / d sd from one exponential: with E = e^-x (x = sd / tau),
-  // sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used (x >= -(r_cut + r_pad) / tau)
+// omega = G dalpha/dsd + G_pad dalpha_pad/dsd of one (pixel, item), from one exponential: with
+// E = e^-x (x = sd / tau), sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used
+// (x >= -(r_cut + r_pad) / tau).
+__device__ __forceinline__ double adjoint_omega(const KArgs &a, double sd, double G, double Gp) {
   double dal = 0.0, dalp = 0.0;
-  if (q.sd + (double)a.r_pad >= -(double)a.r_cut) {
-    const double E = exp(-q.sd * a.inv_tau_d), Ep = E * a.pad_factor;
+  if (sd + (double)a.r_pad >= -(double)a.r_cut) {
+    const double E = exp(-sd * a.inv_tau_d), Ep = E * a.pad_factor;
     const double r = 1.0 / (1.0 + E), rp = 1.0 / (1.0 + Ep);
-    if (q.sd >= -(double)a.r_cut) dal = E * r * r * a.inv_tau_d;
+    if (sd >= -(double)a.r_cut) dal = E * r * r * a.inv_tau_d;
     dalp = Ep * rp * rp * a.inv_tau_d;
   }
-  const double om = G * dal + Gp * dalp;
-  double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (om == 0.0) return t;
-  const double stroke_term = open ? om * sw_ds : 0.0;
-  t.w = stroke_term;
-  if (q.d == 0.0) return t;
-  double nx, ny;
+  return G * dal + Gp * dalp;
+}
+
+// n = grad_p sd of one (pixel, item) at a pixel off the outline (q.d > 0).  Nearest point inside the edge:
+// the unit edge normal, oriented (inside ? +1 : -1) times the side of the edge the pixel is on; within
+// 1e-4 px of the edge the float parity is not reliable, but the product of the two is the outline
+// orientation.  Nearest point at an end point: (p - q) / d, signed by the parity.
+__device__ __forceinline__ void adjoint_normal(const EdgeD &e, const PairD &q, bool par, float orient, bool open,
+                                               double &nx, double &ny) {
   if (q.u > 0.0 && q.u < 1.0) {
-    // nearest point inside the edge: grad sd is the unit edge normal, oriented (inside ? +1 : -1)
-    // times the side of the edge the pixel is on; within 1e-4 px of the edge the float parity is
-    // not reliable, but the product of the two is the outline orientation
     const double il = sqrt(e.inv_ee);
     double sg = (double)orient;
     if (q.d >= 1e-4 || open) {
@@ -436,6 +432,23 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
     nx = q.qx * id;
     ny = q.qy * id;
   }
+}
+
+// Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
+// translation terms applied by the finalize kernel.
+// For an open item (sw_ds != 0 or open) q.sd = sw - d, par is false (the gradient of -d), and the
+// stroke radius adds d sd / d s = sw_ds.
+__device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
+                                                 bool par, float orient, double G, double Gp, bool open,
+                                                 double sw_ds) {
+  const double om = adjoint_omega(a, q.sd, G, Gp);
+  double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (om == 0.0) return t;
+  const double stroke_term = open ? om * sw_ds : 0.0;
+  t.w = stroke_term;
+  if (q.d == 0.0) return t;
+  double nx, ny;
+  adjoint_normal(e, q, par, orient, open, nx, ny);
   t.x = om * nx;
   t.y = om * ny;
   t.z = om * (nx * ry - ny * rx);
@@ -1072,14 +1085,16 @@ __device__ __forceinline__ unsigned long long sat_box(const unsigned long long *
 
 // k_pixel: S, S_pad, the loss terms (summed per tile) and dLoss/dS, dLoss/dS_pad of the per-pixel
 // terms.  UNI (uniform weight != 0): also the A_j of the tile's pixels, the uniform term, and for the
-// gradient the bits M != 0 and A_j < 1 that k_unif_grad needs.
+// gradient the bits M != 0 and A_j < 1 that k_unif_grad needs.  The first tile of each layout also adds
+// the object-space downward force over the layout's items (their transforms are final for this epoch).
 template <bool GRAD, bool UNI>
 __global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
   __shared__ double s_loss[kPixWaves][kLossTerms];
   __shared__ unsigned long long T[UNI ? kUniPitch * kUniPitch : 1];
   __shared__ unsigned long long band_tot[UNI ? kPixWaves * 64 : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const PixTile u = pix_tile(konst(a.layouts), a.num_layouts, blockIdx.x);
+  cptr<LayoutRec> LS = konst(a.layouts);
+  const PixTile u = pix_tile(LS, a.num_layouts, blockIdx.x);
   const int ox = tid % kPixTile, oy = tid / kPixTile;
   const int px = u.x0 + ox, py = u.y0 + oy;
   const bool mine = px < u.W && py < u.H;
@@ -1100,7 +1115,13 @@ __global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
       v[0][i] = q >= 0 ? a.acc[2 * q] : 0ull;
     }
   }
-  double c_ov = a.w[0], c_c = a.w[1], c_f = a.w[2], c_p = a.w[3], c_d = a.w[4];
+  // weights, with the 1 / (W H) of the image-mismatch terms when asked for
+  const double nu = a.area_mean ? 1.0 / ((double)u.W * (double)u.H) : 1.0;
+  double wt[kLossTerms];
+#pragma unroll
+  for (int t = 0; t < kLossTerms; ++t)
+    wt[t] = (double)a.w[t] * ((t <= 3 || t == 6) ? nu : 1.0);
+  double c_ov = wt[0], c_c = wt[1], c_f = wt[2], c_p = wt[3], c_d = wt[4], c_w = wt[6], c_cen = wt[7];
   if (GRAD && a.dloss) {
     const float *dl = a.dloss + kLossTerms * u.b;
     c_ov *= (double)dl[0];
@@ -1108,21 +1129,32 @@ __global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
     c_f *= (double)dl[2];
     c_p *= (double)dl[3];
     c_d *= (double)dl[4];
+    c_w *= (double)dl[6];
+    c_cen *= (double)dl[7];
   }
-  double term[kLossTerms] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double term[kLossTerms];
+#pragma unroll
+  for (int t = 0; t < kLossTerms; ++t) term[t] = 0.0;
   if (mine) {
     const double S = (double)s0 * kFixInv, Sp = (double)s1 * kFixInv, M = (double)mk;
     if (a.cov_out) a.cov_out[pix] = (float)S;
     if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
     const double yinv = (double)u.H - (py + 0.5);
     const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
+    const double O = fmin(S, 1.0), Wp = kWmseIn * M + kWmseOut * (1.0 - M);
+    const double cx = (px + 0.5) - 0.5 * u.W, cy = (py + 0.5) - 0.5 * u.H;
+    const double dist = sqrt(cx * cx + cy * cy);
     term[0] = ov * ov;
     term[1] = S * (1.0 - M);
     term[2] = M * (un * un);
     term[3] = pv * pv;
     term[4] = S * yinv;
+    term[6] = Wp * ((M - O) * (M - O));
+    term[7] = S * dist;
     if (GRAD) {
-      const double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
+      double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
+      if (S < 1.0) G -= 2.0 * c_w * (Wp * (M - S));
+      G += c_cen * dist;
       const double Gp = 2.0 * c_p * pv;
       a.gbuf[pix] = make_double2(G, Gp);
     }
@@ -1145,16 +1177,20 @@ __global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
     if (GRAD && mine) a.uflags[pix] = (uint8_t)bits;
   }
   if (a.write_loss) {
+    if (a.w[8] != 0.0f && blockIdx.x == LS[u.b].ptile_off) {
+      cptr<ShapeRec> SR = konst(a.shapes);
+      for (int q = LS[u.b].shape_begin + tid; q < LS[u.b].shape_end; q += kPixThreads) term[8] += (double)u.H - SR[q].cy;
+    }
 #pragma unroll
-    for (int t = 0; t < (UNI ? kLossTerms : kLossTerms - 1); ++t) {
-      const double s = wave_sum_dpp((double)a.w[t] * term[t]);
+    for (int t = 0; t < kLossTerms; ++t) {
+      // a term with weight 0 is 0: its reduction is skipped (the branch is the same for the whole grid)
+      const double s = a.w[t] != 0.0f ? wave_sum_dpp(wt[t] * term[t]) : 0.0;
       if (lane == 0) s_loss[w][t] = s;
     }
     __syncthreads();
     if (tid < kLossTerms) {
       double s = 0.0;
-      if (UNI || tid < kLossTerms - 1)
-        for (int q = 0; q < kPixWaves; ++q) s += s_loss[q][tid];
+      for (int q = 0; q < kPixWaves; ++q) s += s_loss[q][tid];
       a.block_loss[(int64_t)blockIdx.x * kLossTerms + tid] = s;
     }
   }
@@ -1342,6 +1378,99 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// Outline (control-point) gradients (Sec. 3 "Vector Representation": the control points are fitted by
+// differentiable rendering).  k_vgrad walks the adjoint's units; per pixel the nearest point
+// q' = a' + u (b' - a') of the nearest edge moves with its two end points, d sd / d a' = -n (1 - u) and
+// d sd / d b' = -n u, and omega times those is added into the end points' accumulators (level frame,
+// 2^-32 fixed point, so the sums do not depend on the order of the atomics).  k_vfinal maps each vertex
+// sum back through eq. 2 (dv'/dv = k s R(theta)).
+// ------------------------------------------------------------------------------------------------
+constexpr double kVertFix = 4294967296.0;  // 2^32
+
+__device__ __forceinline__ void vert_add(unsigned long long *acc, double x) {
+  if (x != 0.0) atomicAdd(acc, (unsigned long long)llrint(x * kVertFix));
+}
+
+template <int T>
+__global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
+  __shared__ float4 s_stage[kPersistWaves][kStageSlots];
+  const int lane = threadIdx.x & 63;
+  float4 *S = s_stage[threadIdx.x >> 6];
+  cptr<ShapeRec> SR = konst(a.shapes);
+  const int gw = global_wave();
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  Walk wk;
+  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T); ok; ok = walk_next(a, wk, T)) {
+    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
+    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    const long long q = walk_chunk0(wk);
+    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
+    const int nv = a.vert_off[item + 1] - a.vert_off[item];
+    const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
+    const double cx = SR[item].cx, cy = SR[item].cy;
+    const bool open = SR[item].open != 0;
+    const double sw = SR[item].sw;
+    const bool staged = ec <= kStageEdges;
+    if (staged && q + wk.jhi > a.code_cap) stage_edges(a.edges + eo, ec, S, lane);
+    for (int j = wk.jlo; j < wk.jhi; ++j) {
+      int pxi, pyi;
+      bool in;
+      chunk_pixel(r, j, lane, pxi, pyi, in);
+      const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
+      int bi = 0;
+      bool par = false;
+      if (q + j < a.code_cap) {
+        const unsigned code = a.codes[(q + j) * 64 + lane];
+        bi = (int)(code & 0x7fffu);
+        par = (code & 0x8000u) != 0u;
+      } else {
+        scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+        bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry).e;
+      }
+      if (in) {
+        const double2 g = a.gbuf[wk.pix_off + (int64_t)pyi * wk.W + pxi];
+        const EdgeD e = a.edges_d[eo + bi];
+        if (open) par = false;
+        PairD pr = pair_eval(e, rx, ry, par);
+        if (open) pr.sd = sw - pr.d;
+        const double om = adjoint_omega(a, pr.sd, g.x, g.y);
+        if (om != 0.0 && pr.d != 0.0) {
+          double nx, ny;
+          adjoint_normal(e, pr, par, orient, open, nx, ny);
+          const int ib = open ? min(bi + 1, nv - 1) : (bi + 1 == nv ? 0 : bi + 1);
+          const double fa = -om * (1.0 - pr.u), fb = -om * pr.u;
+          vert_add(&a.vacc[2 * (eo + bi)], fa * nx);
+          vert_add(&a.vacc[2 * (eo + bi) + 1], fa * ny);
+          vert_add(&a.vacc[2 * (eo + ib)], fb * nx);
+          vert_add(&a.vacc[2 * (eo + ib) + 1], fb * ny);
+        }
+      }
+    }
+  }
+}
+
+// One wave per item: dL/dv = (k s R(theta))^T dL/dv' for each of its vertices (NaN for an item with a
+// non-finite parameter).
+__global__ __launch_bounds__(256) void k_vfinal(KArgs a) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * 4 + wave;
+  if (sid >= a.num_shapes) return;
+  const int v0 = a.vert_off[sid], n = a.vert_off[sid + 1] - v0;
+  const float4 p = reinterpret_cast<const float4 *>(a.params)[sid];
+  const bool bad = konst(a.shapes)[sid].bad != 0;
+  const double ks = (double)konst(a.shapes)[sid].k * (double)p.w;
+  double sn = 0.0, c = 1.0;
+  if (!bad) sincos((double)p.z, &sn, &c);
+  for (int m = lane; m < n; m += 64) {
+    const double gx = (double)(long long)a.vacc[2 * (v0 + m)] / kVertFix;
+    const double gy = (double)(long long)a.vacc[2 * (v0 + m) + 1] / kVertFix;
+    float2 out = make_float2((float)(ks * (c * gx + sn * gy)), (float)(ks * (-sn * gx + c * gy)));
+    if (bad) out = make_float2(NAN, NAN);
+    reinterpret_cast<float2 *>(a.grad_verts_out)[v0 + m] = out;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
 // k_finalize: per-item gradient (fixed tile order) + optional Adam; per-layout loss.
 // ------------------------------------------------------------------------------------------------
 // The parameters, moments and rim radius an Adam step of item sid reads (loaded ahead of the gradient).
@@ -1453,7 +1582,9 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
   acc.w = wave_sum(acc.w);
   float4 pn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (lane == 0) {
-    float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * acc.y), (float)acc.z, (float)acc.w);
+    // the object-space downward force adds d(H - k t_y)/dt_y = -k per unit of its weight
+    const double c_od = (double)a.w[8] * (a.dloss ? (double)a.dloss[kLossTerms * b + 8] : 1.0);
+    float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * (acc.y + c_od)), (float)acc.z, (float)acc.w);
     if (SR[sid].bad != 0) g = make_float4(NAN, NAN, NAN, NAN);
     if (a.grad_out) reinterpret_cast<float4 *>(a.grad_out)[sid] = g;
     if (do_adam) pn = adam_update(a, sid, g, k, ain);
@@ -1474,7 +1605,9 @@ __device__ void finalize_loss(const KArgs &a, int b) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int p0 = LS[b].ptile_off;
   const int np = ((LS[b].W + kPixTile - 1) / kPixTile) * ((LS[b].H + kPixTile - 1) / kPixTile);
-  double s[kLossTerms] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double s[kLossTerms];
+#pragma unroll
+  for (int t = 0; t < kLossTerms; ++t) s[t] = 0.0;
   for (int j = threadIdx.x; j < np; j += 256) {
     const double *bl = a.block_loss + (int64_t)(p0 + j) * kLossTerms;
 #pragma unroll
@@ -1629,6 +1762,12 @@ hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
 hipError_t launch_uniform_grad(const KArgs &a, hipStream_t st) {
   if (a.w[5] == 0.0f || a.total_ptiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unif_grad, dim3(a.total_ptiles), dim3(kPixThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_grad(const KArgs &a, hipStream_t st) {
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_vgrad<T>, dim3(a.adjoint_grid), dim3(256), 0, st, a));
+  if (a.num_shapes > 0) hipLaunchKernelGGL(k_vfinal, dim3((a.num_shapes + 3) / 4), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -74,6 +74,10 @@ class Scene:
     w_pad: float = 0.0
     w_down: float = 0.0
     w_uniform: float = 0.0  # uniform (dilation) term, off unless a scene sets it
+    w_wmse: float = 0.0     # weighted mean square error containment (penalty 1 inside, 100 outside)
+    w_centre: float = 0.0   # central force towards the canvas centre (image space)
+    w_objdown: float = 0.0  # downward force on the item origins (object space)
+    area_mean: bool = False  # overlap, contain, fill, pad and wmse divided by the canvas area
     steps_per_level: int = 300
     lr_px: float = 0.5
     seed: int = 0
@@ -121,7 +125,8 @@ class Scene:
 
     def weights(self):
         """Loss weights in term order: overlap, contain, fill, pad, down, uniform."""
-        return (self.w_overlap, self.w_contain, self.w_fill, self.w_pad, self.w_down, self.w_uniform)
+        return (self.w_overlap, self.w_contain, self.w_fill, self.w_pad, self.w_down, self.w_uniform, self.w_wmse,
+                self.w_centre, self.w_objdown)
 
     def signature(self) -> str:
         h = hashlib.sha1()
@@ -417,6 +422,13 @@ def config5(seed: int = 0, num_shapes: int = 2000) -> Scene:
     return assemble("config5", outlines, params, [lay], [256, 512, 1024, 2048], 2048,
                     stroke=np.full(num_shapes, 1.5), tau=0.5, r_cut=8.0, r_pad=2.0, w_overlap=1.0,
                     w_contain=1.0, w_fill=1.0, w_pad=1.0, w_down=1e-3, steps_per_level=300, seed=seed)
+
+
+def paper_loss_preset(scene: Scene) -> Scene:
+    """The weights of Sec. 4.2 (eq. 8): containment alpha = 3e3 on the WMSE of eq. 5, overlap beta = 8e4,
+    uniform gamma = 5e-4, with the 1 / (w h) of eqs. 5 and 6; every other term off."""
+    return dataclasses.replace(scene, w_overlap=8e4, w_contain=0.0, w_fill=0.0, w_pad=0.0, w_down=0.0,
+                               w_uniform=5e-4, w_wmse=3e3, w_centre=0.0, w_objdown=0.0, area_mean=True)
 
 
 def random_scene(seed: int, sizes: Sequence[tuple], shapes_per_layout: Sequence[int], kinds=("poly", "star", "bezier"),

@@ -30,7 +30,7 @@ class LevelRun:
     level: int
     steps: int
     tile: int
-    loss: Optional[np.ndarray] = None    # [B,6] weighted terms of the level's last epoch
+    loss: Optional[np.ndarray] = None    # [B,9] weighted terms of the level's last epoch
     params: Optional[np.ndarray] = None  # [N,4] parameters at the end of the level
     gpu_ms: float = 0.0                  # HIP-event time of the level's graph launch
 

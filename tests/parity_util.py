@@ -3,6 +3,7 @@
   images  (S, S_pad, per-item alpha): |gpu - ref| <= 1e-5 absolute
   loss    each term: |gpu - ref| <= 1e-5 |ref| (+1e-9 for exact zeros)
   grads   |g - g_ref| <= 1e-4 max(|g_ref|, 0.01 max_items |g_ref| of that component)
+  vertex grads  the same, over vertices and the two components
 """
 import numpy as np
 
@@ -52,3 +53,17 @@ def check_grad(gpu, ref, what="grad", rtol=GRAD_RTOL):
         raise AssertionError(f"{what}: relative error {e:.3e} > {rtol} at item {i} component {c}: "
                              f"gpu {g[i, c]!r} ref {r[i, c]!r} floor {floor[c]!r}")
     return e
+
+
+def check_vgrad(gpu, ref, what="vertex grad", rtol=GRAD_RTOL):
+    g = np.asarray(gpu, np.float64).reshape(-1, 2)
+    r = np.asarray(ref, np.float64).reshape(-1, 2)
+    if r.size == 0:
+        return 0.0
+    floor = 0.01 * np.abs(r).max(0)
+    denom = np.maximum(np.abs(r), floor[None, :])
+    denom = np.where(denom > 0, denom, 1.0)
+    rel = np.abs(g - r) / denom
+    i, c = np.unravel_index(int(np.argmax(rel)), rel.shape)
+    assert rel[i, c] <= rtol, f"{what}: relative error {rel[i, c]:.3e} at vertex {i} component {c}: gpu {g[i, c]!r} ref {r[i, c]!r}"
+    return float(rel.max())

@@ -203,7 +203,7 @@ def test_P3_scale_derivative_is_twice_area_over_s():
     area = 0.5 * 128 * 81.0 * math.sin(2 * math.pi / 128)
     s = 1.3
     sc = S.single_shape_scene(P, 48, 48, (24.21, 23.67), 0.2, s, w_overlap=0, w_contain=1, w_fill=0)
-    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0])
+    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0, 0, 0, 0])
     assert abs(g[0, 3] - 2 * area * s) / (2 * area * s) < 1e-3  # d(s^2 A)/ds
     # translation and rotation leave the total coverage unchanged
     assert abs(g[0, 0]) < 2e-3 * area and abs(g[0, 1]) < 2e-3 * area and abs(g[0, 2]) < 2e-3 * area
@@ -217,7 +217,7 @@ def test_P4_gravity_identity():
         sc = S.single_shape_scene(P, 48, 48, c, 0.2, 1.0, w_overlap=0, w_contain=1, w_fill=0, w_down=1.0)
         o = Oracle(sc)
         mass = o.forward(sc.params)[2][0, 1]
-        g = o.backward(sc.params, dloss=[0, 0, 0, 0, 1, 0])[0]
+        g = o.backward(sc.params, dloss=[0, 0, 0, 0, 1, 0, 0, 0, 0])[0]
         return np.array([mass, g[0], g[1]])
 
     mass, gx, gy = _offset_average(f, (23.9, 20.3))
@@ -392,7 +392,7 @@ def test_open_P3_scale_derivative():
     L, w, s = 14.6, 4.0, 1.3
     area = 2 * w * L + math.pi * w * w
     sc = _stadium(L, w, (24.21, 23.67), 0.2, s, size=64)
-    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0])
+    g = Oracle(sc).backward(sc.params, dloss=[0, 1, 0, 0, 0, 0, 0, 0, 0])
     assert abs(g[0, 3] - 2 * area * s) / (2 * area * s) < 2e-3, (g[0, 3], 2 * area * s)
     assert abs(g[0, 0]) < 2e-3 * area and abs(g[0, 1]) < 2e-3 * area and abs(g[0, 2]) < 2e-3 * area
 
@@ -437,3 +437,146 @@ def test_uniform_term_backward_vs_central_differences():
     sc = dataclasses.replace(S.random_scene(9, [(52, 44)], [5], radius=(3.0, 6.0)), w_uniform=3.0,
                              w_overlap=0.2, w_contain=0.2, w_fill=0.2)
     _fd_check(sc)
+
+
+# --------------------------------------------------------------------------------------------------
+# The paper's containment loss (eq. 5), the 1 / (w h) of eqs. 5-6, and the force variants of Sec. 5
+# --------------------------------------------------------------------------------------------------
+def test_wmse_closed_forms():
+    """eq. 5 at its two extremes.  No items: the rendering is white (O = 0) and the container black, so
+    the sum is the container's pixel count (penalty 1 inside).  One item far larger than the canvas
+    covering it (S = 1 at every pixel): the pixels outside the container, at penalty 100."""
+    W, H = 37, 29
+    sc = S.multi_shape_scene([S.rectangle(2.0, 2.0)], np.array([[-500.0, -500.0, 0.0, 1.0]]), W, H, mask="disk",
+                             w_overlap=0, w_contain=0, w_fill=0, w_wmse=1.0)
+    M = sc.packed_mask(None).astype(np.float64)
+    n_in = M.sum()
+    assert 0 < n_in < W * H
+    L = Oracle(sc).forward(sc.params)[2]
+    assert abs(L[0, 6] - n_in) < 1e-9 * n_in
+    big = dataclasses.replace(sc, params=np.array([[18.0, 14.0, 0.0, 1.0]], np.float32),
+                              verts=S.rectangle(200.0, 200.0).astype(np.float32))
+    Sb, _, Lb = Oracle(big).forward(big.params)
+    assert np.all(Sb == 1.0)
+    assert abs(Lb[0, 6] - 100.0 * (W * H - n_in)) < 1e-9 * Lb[0, 6]
+    # the 1 / (w h) of eq. 5
+    Lm = Oracle(dataclasses.replace(big, area_mean=True)).forward(big.params)[2]
+    assert abs(Lm[0, 6] - Lb[0, 6] / (W * H)) < 1e-12 * Lb[0, 6]
+
+
+def test_area_mean_scales_exactly_the_image_mismatch_terms():
+    """With area_mean, overlap, contain, fill, pad and wmse (loss and gradient) are divided by each
+    layout's own pixel count; down, uniform, centre and objdown are unchanged."""
+    sc = dataclasses.replace(S.random_scene(4, [(41, 33), (26, 30)], [6, 4], radius=(3.0, 7.0)), w_uniform=0.3,
+                             w_wmse=2.0, w_centre=0.01, w_objdown=0.5)
+    o, om = Oracle(sc), Oracle(dataclasses.replace(sc, area_mean=True))
+    L, Lm = o.forward(sc.params)[2], om.forward(sc.params)[2]
+    areas = np.array([41 * 33, 26 * 30], np.float64)
+    for t in range(9):
+        f = 1.0 / areas if t in (0, 1, 2, 3, 6) else np.ones(2)
+        assert np.all(np.abs(Lm[:, t] - L[:, t] * f) <= 1e-12 * np.abs(L[:, t]) + 1e-300), t
+    for t in (1, 6, 7):
+        dl = np.zeros((2, 9))
+        dl[:, t] = 1.0
+        g, gm = o.backward(sc.params, dloss=dl), om.backward(sc.params, dloss=dl)
+        f = np.repeat(1.0 / areas if t != 7 else np.ones(2), [6, 4])[:, None]
+        assert np.allclose(gm, g * f, rtol=1e-12, atol=0.0), t
+
+
+def test_centre_force_against_quadrature():
+    """sum_p S |p - c| (c the canvas centre) for a fine disk whose centre is 11.3 px from c, against the
+    2-D integral in polar coordinates about the disk centre; sub-pixel offsets averaged."""
+    r, D, side = 8.0, 11.3, 64
+    P, _, r_eff = _fine_circle(r)
+    c = side / 2.0
+    upper = r_eff + R_CUT + 5.0
+
+    def f(pos):
+        sc = S.multi_shape_scene([P], np.array([[pos[0], pos[1], 0.0, 1.0]]), side, side, mask="none",
+                                 w_overlap=0, w_contain=0, w_fill=0, w_centre=1.0)
+        return Oracle(sc).forward(sc.params)[2][0]
+
+    base = (c + D - 0.5, c - 0.5)
+    L = _offset_average(f, base)
+
+    def ring(rho):  # int_0^{2 pi} |rho (cos phi, sin phi) + (D, 0)| d phi
+        v, _ = integrate.quad(lambda ph: math.hypot(D + rho * math.cos(ph), rho * math.sin(ph)), 0.0, 2 * math.pi,
+                              limit=200, epsabs=1e-11, epsrel=1e-11)
+        return v
+
+    pts = sorted({0.0, max(r_eff - 6, 0.0), r_eff, r_eff + 2.0, r_eff + R_CUT, upper})
+    ref = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        v, _ = integrate.quad(lambda rho: _alpha(r_eff - rho) * rho * ring(rho), a, b, limit=200, epsabs=1e-9,
+                              epsrel=1e-10)
+        ref += v
+    # the offset average moves the disk by up to half a pixel about its mean centre; L is smooth in the
+    # position, so that leaves a second-order bias well below the bound
+    assert abs(L[7] - ref) < 2e-3 * ref, (L[7], ref)
+    assert L[0] == 0.0 and L[6] == 0.0 and L[8] == 0.0
+
+
+def test_object_space_downward_force():
+    """sum_i (H - k t_y,i) exactly, and its gradient -k w on t_y only, at a level with k != 1."""
+    sc = dataclasses.replace(S.config4(2, num_layouts=3), w_overlap=0.0, w_contain=0.0, w_fill=0.0, w_pad=0.0,
+                             w_down=0.0, w_objdown=0.7)
+    level = sc.levels[0]
+    o = Oracle(sc, level=level)
+    w, h, k, off = sc.layout_arrays(level)
+    assert k[0] != 1.0
+    L = o.forward(sc.params)[2]
+    p = sc.params.astype(np.float64)
+    for b in range(sc.num_layouts):
+        ref = 0.7 * sum(float(h[b]) - float(k[b]) * p[q, 1] for q in range(off[b], off[b + 1]))
+        assert abs(L[b, 8] - ref) < 1e-12 * abs(ref)
+    g = o.backward(sc.params)
+    for b in range(sc.num_layouts):
+        assert np.all(g[off[b]:off[b + 1], 1] == -0.7 * float(k[b]))
+    assert np.all(g[:, [0, 2, 3]] == 0.0)
+
+
+def test_new_terms_backward_vs_central_differences():
+    sc = dataclasses.replace(S.random_scene(21, [(52, 44)], [5], radius=(3.0, 6.0)), w_overlap=0.5, w_contain=0.0,
+                             w_fill=0.0, w_pad=0.0, w_down=0.0, w_wmse=1.0, w_centre=0.05, w_objdown=0.3,
+                             area_mean=True)
+    _fd_check(sc)
+
+
+def test_paper_preset():
+    sc = S.paper_loss_preset(S.config1())
+    assert sc.weights() == (8e4, 0.0, 0.0, 0.0, 0.0, 5e-4, 3e3, 0.0, 0.0) and sc.area_mean
+
+
+# --------------------------------------------------------------------------------------------------
+# Outline (control-point) gradients: dL / d(vertex in the item frame)
+# --------------------------------------------------------------------------------------------------
+def test_vertex_gradient_vs_central_differences():
+    """Closed and open items, vertices at corners and mid-outline, every loss term on."""
+    sc = dataclasses.replace(S.random_scene(12, [(56, 48)], [7], kinds=("open", "star", "poly", "bezier"),
+                                            radius=(4.0, 9.0)), w_uniform=0.5, w_wmse=0.5, w_centre=0.01)
+    o = Oracle(sc)
+    _, gv = o.backward_vertices(sc.params)
+    rng = np.random.default_rng(5)
+    verts = sorted(rng.choice(sc.num_verts, 14, replace=False).tolist())
+    fd = o.fd_vertex_gradient(sc.params, verts)
+    floor = 0.01 * np.abs(gv).max()
+    err = np.abs(gv[verts] - fd)
+    assert np.all(err <= 1e-4 * np.maximum(np.abs(fd), floor)), (err.max(), fd)
+
+
+def test_vertex_gradient_sums_to_the_parameter_gradient():
+    """v' = k (R s v + t): dL/dt = R sum_m g_m / s, dL/dtheta = sum_m v_m x g_m and, for a closed item,
+    dL/ds = sum_m v_m . g_m / s, with g_m = dL/dv_m."""
+    sc = S.config1()
+    o = Oracle(sc)
+    g, gv = o.backward_vertices(sc.params)
+    V = sc.verts.astype(np.float64)
+    for q in range(sc.num_shapes):
+        a, b = sc.vert_off[q], sc.vert_off[q + 1]
+        th, s = float(sc.params[q, 2]), float(sc.params[q, 3])
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+        gm, vm = gv[a:b], V[a:b]
+        scale = np.abs(g[q]).max()
+        assert np.allclose(R @ gm.sum(0) / s, g[q, :2], rtol=0, atol=1e-9 * scale)
+        assert abs((vm[:, 0] * gm[:, 1] - vm[:, 1] * gm[:, 0]).sum() - g[q, 2]) <= 1e-9 * scale
+        assert abs((vm * gm).sum() / s - g[q, 3]) <= 1e-9 * scale

@@ -11,9 +11,10 @@ import pytest
 import torch
 
 from oracle.oracle import Oracle
+from paper_2406_04008_amd import _lib
 from paper_2406_04008_amd import scenes as S
 from paper_2406_04008_amd.collage import CollageLoss, CollageScene
-from tests.parity_util import check_grad, check_image, check_loss, grad_error
+from tests.parity_util import check_grad, check_image, check_loss, check_vgrad, grad_error
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +40,10 @@ SCENES = {
     "uniform": lambda: dataclasses.replace(
         S.random_scene(14, [(71, 53), (20, 9), (40, 97), (64, 64)], [9, 0, 7, 10], radius=(3.0, 8.0),
                        off_canvas=0.2), w_uniform=0.6),
+    # the containment of eq. 5, the central and the object-space downward forces, normalized by area
+    "forces": lambda: dataclasses.replace(
+        S.random_scene(17, [(61, 47), (33, 70), (18, 18)], [8, 6, 0], radius=(3.0, 8.0), off_canvas=0.2),
+        w_contain=0.0, w_fill=0.0, w_wmse=2.0, w_centre=3e-3, w_objdown=0.25, area_mean=True),
 }
 
 
@@ -77,7 +82,7 @@ def test_backward_parity_autograd(name, tile, oracles):
     cs = CollageScene(sc, tile=tile)
     p = cs.params_tensor().requires_grad_(True)
     rng = np.random.default_rng(1)
-    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 6))
+    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, _lib.LOSS_TERMS))
     loss = CollageLoss.apply(p, cs)
     (loss * torch.tensor(dl, dtype=torch.float32, device=loss.device)).sum().backward()
     g_ref = o.backward(sc.params, dloss=dl)
@@ -199,7 +204,7 @@ def test_graph_replay_matches_eager():
     cs = CollageScene(sc)
     p_g = cs.params_tensor()
     m_g, v_g, s_g = cs.new_state()
-    loss_g = torch.empty(1, 6, device="cuda")
+    loss_g = torch.empty(1, _lib.LOSS_TERMS, device="cuda")
     grad_g = torch.empty(sc.num_shapes, 4, device="cuda")
     g = cs.graph(p_g, m_g, v_g, s_g, loss_g, grad_g, replays_per_launch=2)
     p_e = cs.params_tensor()
@@ -293,6 +298,87 @@ def test_uniform_term_metric_scene(level, tile):
     check_grad(_np(grad), o.backward(sc.params))
 
 
+@pytest.mark.parametrize("level,tile", [(512, 32), (256, 16)])
+def test_paper_loss_preset_metric_scene(level, tile):
+    """The weights of eq. 8 (WMSE containment, overlap, uniform; 1 / (w h)) on the 500-item scene."""
+    sc = S.paper_loss_preset(S.config3(0))
+    _say("config3 paper preset level", level, "tile", tile)
+    o = Oracle(sc, level=level)
+    cs = CollageScene(sc, level=level, tile=tile)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    assert L[0, 6] > 0.0 and L[0, 5] > 0.0 and L[0, 0] > 0.0
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+
+
+def test_force_terms_vs_central_differences():
+    sc = SCENES["forces"]()
+    _say("fd forces")
+    cs = CollageScene(sc)
+    p = cs.params_tensor().requires_grad_(True)
+    CollageLoss.apply(p, cs).sum().backward()
+    o = Oracle(sc)
+    items = list(range(0, sc.num_shapes, 2))
+    fd = o.fd_gradient(sc.params, shapes=items)
+    g = _np(p.grad)
+    floor = 0.01 * np.abs(o.backward(sc.params)).max(0)
+    for c in range(4):
+        err = np.abs(g[items, c] - fd[items, c]) / np.maximum(np.abs(fd[items, c]), floor[c])
+        assert err.max() <= 1e-4, (c, err)
+
+
+@pytest.mark.parametrize("code_capacity", [-1, 0])
+@pytest.mark.parametrize("tile", [16, 8, 32])
+@pytest.mark.parametrize("name", list(SCENES))
+def test_vertex_gradient_parity(name, tile, code_capacity, oracles):
+    """dLoss/d(outline vertex) and the parameter gradient of the same call, with a random dloss."""
+    sc, o = oracles(name)
+    _say("vertex grad", name, "tile", tile, "cache", code_capacity)
+    cs = CollageScene(sc, tile=tile, code_capacity=code_capacity)
+    dl = np.random.default_rng(7).uniform(0.5, 2.0, (sc.num_layouts, _lib.LOSS_TERMS))
+    g, gv = cs.backward_vertices(cs.params_tensor(), torch.tensor(dl, dtype=torch.float32, device="cuda"))
+    g_ref, gv_ref = o.backward_vertices(sc.params, dloss=dl.astype(np.float32).astype(np.float64))
+    check_grad(_np(g), g_ref)
+    check_vgrad(_np(gv), gv_ref)
+    _, gv2 = cs.backward_vertices(cs.params_tensor(), torch.tensor(dl, dtype=torch.float32, device="cuda"),
+                                  want_grad=False)
+    assert torch.equal(gv, gv2)
+
+
+def test_vertex_gradient_metric_scene():
+    sc = S.config3(0)
+    _say("vertex grad config3 512")
+    o = Oracle(sc, level=512)
+    cs = CollageScene(sc, level=512, tile=32)
+    g, gv = cs.backward_vertices(cs.params_tensor())
+    g_ref, gv_ref = o.backward_vertices(sc.params)
+    check_grad(_np(g), g_ref)
+    check_vgrad(_np(gv), gv_ref)
+
+
+def test_outline_fitting_to_a_silhouette():
+    """Gradient descent (Adam) on the vertices of one circle outline towards a rectangular silhouette
+    (the container mask as the target image): the mismatch falls by well over half."""
+    sc = S.multi_shape_scene([S.regular_polygon(48, 9.0)], np.array([[32.0, 32.0, 0.0, 1.0]]), 64, 64, mask="none",
+                             w_overlap=0.0, w_contain=1.0, w_fill=1.0)
+    lay = dataclasses.replace(sc.layouts[0], rects=np.array([[32.0, 32.0, 16.0, 7.0, 0.3]]), full=False)
+    sc = dataclasses.replace(sc, layouts=[lay])
+    _say("outline fit")
+    cs = CollageScene(sc)
+    p = cs.params_tensor()
+    verts = cs.verts
+    opt = torch.optim.Adam([verts], lr=0.15)
+    losses = []
+    for _ in range(150):
+        _, _, loss = cs.forward(p, want_cov=False)
+        losses.append(float(loss.sum()))
+        _, gv = cs.backward_vertices(p, want_grad=False)
+        verts.grad = gv
+        opt.step()
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.4 * losses[0], (losses[0], losses[-1])
+
+
 def test_uniform_term_fractional_mask():
     """Mask values strictly between 0 and 1 on the first layout (its tiles take the exact fixed-point
     tables of the gradient pass) and binary masks on the others (packed flag counts), in one launch."""
@@ -306,7 +392,7 @@ def test_uniform_term_fractional_mask():
     _say("uniform fractional mask")
     o = Oracle(sc, mask=m.astype(np.float64))
     cs = CollageScene(sc, mask=m)
-    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, 6))
+    dl = rng.uniform(0.5, 2.0, (sc.num_layouts, _lib.LOSS_TERMS))
     cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
     S_, Sp, L = o.forward(sc.params)
     check_loss(_np(loss), L)
@@ -326,7 +412,7 @@ def test_uniform_term_is_deterministic_and_forward_matches_fused():
             assert torch.equal(x, y)
     _, _, loss_f = cs.forward(p)
     assert torch.equal(loss_f, runs[0][2])
-    dl = torch.zeros(sc.num_layouts, 6, device="cuda")
+    dl = torch.zeros(sc.num_layouts, _lib.LOSS_TERMS, device="cuda")
     dl[:, 5] = 1.0
     g_u = cs.backward(p, dl)
     o = Oracle(sc)
