@@ -50,12 +50,6 @@ __device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
   return make_int4(q[0], q[1], q[2], q[3]);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // v moved between lanes by the DPP control CTRL (rows outside ROW_MASK and lanes whose source is out of
 // the row read 0); the two 32-bit halves move separately.
 template <int CTRL, int ROW_MASK>
@@ -92,6 +86,9 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   const int hi = __builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)bits >> 32), 63);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
+
+// The sum over a wave's 64 lanes (every lane active), broadcast to all of them.
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
@@ -1088,23 +1085,32 @@ __device__ __forceinline__ unsigned long long sat_box(const unsigned long long *
 // gradient the bits M != 0 and A_j < 1 that k_unif_grad needs.  The first tile of each layout also adds
 // the object-space downward force over the layout's items (their transforms are final for this epoch).
 template <bool GRAD, bool UNI>
-__global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
-  __shared__ double s_loss[kPixWaves][kLossTerms];
+__global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
+  // without the uniform term a workgroup of 256 threads takes the tile, four pixels per thread with
+  // all their loads in flight together; the window pass needs one thread per pixel (16 waves)
+  constexpr int NT = UNI ? kPixThreads : 256, PX = kPixTile * kPixTile / NT, NW = NT / 64;
+  __shared__ double s_loss[NW][kLossTerms];
   __shared__ unsigned long long T[UNI ? kUniPitch * kUniPitch : 1];
   __shared__ unsigned long long band_tot[UNI ? kPixWaves * 64 : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   cptr<LayoutRec> LS = konst(a.layouts);
   const PixTile u = pix_tile(LS, a.num_layouts, blockIdx.x);
-  const int ox = tid % kPixTile, oy = tid / kPixTile;
-  const int px = u.x0 + ox, py = u.y0 + oy;
-  const bool mine = px < u.W && py < u.H;
-  const int64_t pix = u.pix_off + (int64_t)py * u.W + px;
-  unsigned long long s0 = 0ull, s1 = 0ull;
-  float mk = 0.0f;
-  if (mine) {
-    s0 = a.acc[2 * pix];
-    s1 = a.acc[2 * pix + 1];
-    mk = a.mask[pix];
+  bool mine[PX];
+  int64_t pix[PX];
+  unsigned long long s0[PX], s1[PX];
+  float mk[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int i = tid + NT * k, px = u.x0 + i % kPixTile, py = u.y0 + i / kPixTile;
+    mine[k] = px < u.W && py < u.H;
+    pix[k] = u.pix_off + (int64_t)py * u.W + px;
+    s0[k] = s1[k] = 0ull;
+    mk[k] = 0.0f;
+    if (mine[k]) {
+      s0[k] = a.acc[2 * pix[k]];
+      s1[k] = a.acc[2 * pix[k] + 1];
+      mk[k] = a.mask[pix[k]];
+    }
   }
   unsigned long long v[1][kUniBand];
   if (UNI) {
@@ -1135,62 +1141,66 @@ __global__ __launch_bounds__(kPixThreads) void k_pixel(KArgs a) {
   double term[kLossTerms];
 #pragma unroll
   for (int t = 0; t < kLossTerms; ++t) term[t] = 0.0;
-  if (mine) {
-    const double S = (double)s0 * kFixInv, Sp = (double)s1 * kFixInv, M = (double)mk;
-    if (a.cov_out) a.cov_out[pix] = (float)S;
-    if (a.cov_pad_out) a.cov_pad_out[pix] = (float)Sp;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    if (!mine[k]) continue;
+    const int i = tid + NT * k, px = u.x0 + i % kPixTile, py = u.y0 + i / kPixTile;
+    const double S = (double)s0[k] * kFixInv, Sp = (double)s1[k] * kFixInv, M = (double)mk[k];
+    if (a.cov_out) a.cov_out[pix[k]] = (float)S;
+    if (a.cov_pad_out) a.cov_pad_out[pix[k]] = (float)Sp;
     const double yinv = (double)u.H - (py + 0.5);
     const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
     const double O = fmin(S, 1.0), Wp = kWmseIn * M + kWmseOut * (1.0 - M);
     const double cx = (px + 0.5) - 0.5 * u.W, cy = (py + 0.5) - 0.5 * u.H;
     const double dist = sqrt(cx * cx + cy * cy);
-    term[0] = ov * ov;
-    term[1] = S * (1.0 - M);
-    term[2] = M * (un * un);
-    term[3] = pv * pv;
-    term[4] = S * yinv;
-    term[6] = Wp * ((M - O) * (M - O));
-    term[7] = S * dist;
+    term[0] += ov * ov;
+    term[1] += S * (1.0 - M);
+    term[2] += M * (un * un);
+    term[3] += pv * pv;
+    term[4] += S * yinv;
+    term[6] += Wp * ((M - O) * (M - O));
+    term[7] += S * dist;
     if (GRAD) {
       double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
       if (S < 1.0) G -= 2.0 * c_w * (Wp * (M - S));
       G += c_cen * dist;
       const double Gp = 2.0 * c_p * pv;
-      a.gbuf[pix] = make_double2(G, Gp);
+      a.gbuf[pix[k]] = make_double2(G, Gp);
     }
   }
   if (UNI) {
 #pragma unroll
     for (int i = 0; i < kUniBand; ++i) v[0][i] = v[0][i] < kFixOne ? v[0][i] : kFixOne;
     sat_build<1>(T, band_tot, v);
+    const int ox = tid % kPixTile, oy = tid / kPixTile;
     unsigned bits = 0;
-    if (mine && mk != 0.0f) {
+    if (mine[0] && mk[0] != 0.0f) {
 #pragma unroll
       for (int j = 0; j < kUniWindows; ++j) {
         const unsigned long long box = sat_box(T, ox + kUniHalo, oy + kUniHalo, uni_radius(j));
         if (box < kFixOne) {
           bits |= 1u << j;
-          term[5] += uni_weight(j) * ((double)mk * ((double)(kFixOne - box) * kFixInv));
+          term[5] += uni_weight(j) * ((double)mk[0] * ((double)(kFixOne - box) * kFixInv));
         }
       }
     }
-    if (GRAD && mine) a.uflags[pix] = (uint8_t)bits;
+    if (GRAD && mine[0]) a.uflags[pix[0]] = (uint8_t)bits;
   }
   if (a.write_loss) {
     if (a.w[8] != 0.0f && blockIdx.x == LS[u.b].ptile_off) {
       cptr<ShapeRec> SR = konst(a.shapes);
-      for (int q = LS[u.b].shape_begin + tid; q < LS[u.b].shape_end; q += kPixThreads) term[8] += (double)u.H - SR[q].cy;
+      for (int q = LS[u.b].shape_begin + tid; q < LS[u.b].shape_end; q += NT) term[8] += (double)u.H - SR[q].cy;
     }
 #pragma unroll
     for (int t = 0; t < kLossTerms; ++t) {
       // a term with weight 0 is 0: its reduction is skipped (the branch is the same for the whole grid)
-      const double s = a.w[t] != 0.0f ? wave_sum_dpp(wt[t] * term[t]) : 0.0;
+      const double s = a.w[t] != 0.0f ? wave_sum(wt[t] * term[t]) : 0.0;
       if (lane == 0) s_loss[w][t] = s;
     }
     __syncthreads();
     if (tid < kLossTerms) {
       double s = 0.0;
-      for (int q = 0; q < kPixWaves; ++q) s += s_loss[q][tid];
+      for (int q = 0; q < NW; ++q) s += s_loss[q][tid];
       a.block_loss[(int64_t)blockIdx.x * kLossTerms + tid] = s;
     }
   }
@@ -1744,17 +1754,17 @@ hipError_t launch_cover(const KArgs &a, hipStream_t st, hipEvent_t ev_start, hip
 
 hipError_t launch_pixel(const KArgs &a, bool grad, hipStream_t st) {
   if (a.total_ptiles <= 0) return hipSuccess;
-  const dim3 g(a.total_ptiles), b(kPixThreads);
+  const dim3 g(a.total_ptiles), b_uni(kPixThreads), b_plain(256);
   if (a.w[5] != 0.0f) {
     if (grad)
-      hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_pixel<true, true>), g, b_uni, 0, st, a);
     else
-      hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_pixel<false, true>), g, b_uni, 0, st, a);
   } else {
     if (grad)
-      hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_pixel<true, false>), g, b_plain, 0, st, a);
     else
-      hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_pixel<false, false>), g, b_plain, 0, st, a);
   }
   return hipGetLastError();
 }
