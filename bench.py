@@ -220,6 +220,59 @@ def uniform_term(sc, level, cfg, steps, weight=2e-3):
     return out
 
 
+def paper_preset(sc, level, cfg, steps):
+    """Epochs per second with the loss weights of eq. 8 (WMSE containment, overlap, uniform; 1 / (w h)),
+    same scene, level and launch configuration, from the seed-0 layout after a warm-up."""
+    import torch
+
+    from paper_2406_04008_amd import scenes
+    from paper_2406_04008_amd.collage import CollageScene
+
+    cs = CollageScene(scenes.paper_loss_preset(sc), level=level, **cfg.scene_kwargs())
+    stream = torch.cuda.Stream()
+    for timed in (False, True):
+        p = cs.params_tensor()
+        m, v, st = cs.new_state()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            loss, _ = cs.iterate_n(p, m, v, st, steps if timed else 20, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+    assert np.all(np.isfinite(p.cpu().numpy())), "non-finite parameters"
+    return {"steps": steps, "tile": cfg.tile, "it_per_s": steps / (e0.elapsed_time(e1) / 1e3),
+            "final_loss": [float(x) for x in loss.sum(0).cpu().numpy()]}
+
+
+def vertex_grad(sc, level, cfg, reps=50):
+    """collage_backward_vertices (parameter and outline-vertex gradients) against collage_backward, same
+    parameters, HIP events around `reps` calls of each."""
+    import torch
+
+    from paper_2406_04008_amd import _lib
+    from paper_2406_04008_amd.collage import CollageScene
+
+    cs = CollageScene(sc, level=level, **cfg.scene_kwargs())
+    p = cs.params_tensor()
+    dl = torch.ones(cs.B, _lib.LOSS_TERMS, device="cuda")
+    out = {"reps": reps, "tile": cfg.tile, "vertices": int(sc.num_verts)}
+    for name, fn in (("backward", lambda: cs.backward(p, dl)), ("backward_vertices", lambda: cs.backward_vertices(p, dl))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = e0.elapsed_time(e1) / reps
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,9 +283,9 @@ def main():
     ap.add_argument("--code-capacity", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip every extra measurement (schedules, batched-vs-loop, uniform term)")
-    ap.add_argument("--extras", default="c2f,open,batched,uniform",
-                    help="comma-separated extra measurements: c2f, open, batched, uniform")
+                    help="skip every extra measurement (schedules, batched-vs-loop, uniform term, preset, vertices)")
+    ap.add_argument("--extras", default="c2f,open,batched,uniform,preset,vertex",
+                    help="comma-separated extra measurements: c2f, open, batched, uniform, preset, vertex")
     ap.add_argument("--batched-steps", type=int, default=30)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed region, copy 256 MiB device to device (reference for HBM counters)")
@@ -386,6 +439,10 @@ def main():
         out["batched"] = batched_vs_loop(args.batched_steps)
     if "uniform" in extras:
         out["uniform_term"] = uniform_term(sc, args.level, cfg, args.steps)
+    if "preset" in extras:
+        out["paper_preset"] = paper_preset(sc, args.level, cfg, args.steps)
+    if "vertex" in extras:
+        out["vertex_grad"] = vertex_grad(sc, args.level, cfg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.level)
     print(json.dumps(out), flush=True)

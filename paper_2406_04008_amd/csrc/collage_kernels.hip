@@ -17,10 +17,16 @@
 //                them to S and S_pad as 2^-40 fixed point with 64-bit integer atomics (exact, so the
 //                result does not depend on the order of the work).  Backward calls keep a 2-byte
 //                nearest-edge code per (chunk, lane).
-//   k_pixel      S, S_pad, the five loss terms (summed per pixel block in a fixed order) and
-//                dLoss/dS, dLoss/dS_pad per pixel.
+//   k_pixel      one workgroup per 32 x 32 pixel tile: S, S_pad, the loss terms (summed per tile in a
+//                fixed order) and dLoss/dS, dLoss/dS_pad per pixel; with the uniform term on, also the
+//                tile's window occupancies from a summed-area table of the tile and its halo.
+//   k_unif_grad  (uniform term on) the same tiles: the term's share of dLoss/dS from window sums of
+//                the pixels' active-window bits.
 //   k_adjoint    persistent waves again: per chunk, the gradient terms of its pixels (double), one
 //                partial per piece of a unit.
+//   k_vgrad,     (outline-vertex gradients only) the adjoint's walk once more, adding each pixel's
+//   k_vfinal     d sd / d(end points of its nearest edge) into per-vertex fixed-point sums, then back
+//                through eq. 2 per vertex.
 //   k_finalize   one wave per item sums its units' partials in a fixed order (gradient, then the
 //                optional Adam update and the next epoch's transform); one workgroup per layout sums
 //                the loss blocks in a fixed order.
@@ -1401,11 +1407,15 @@ __device__ __forceinline__ void vert_add(unsigned long long *acc, double x) {
   if (x != 0.0) atomicAdd(acc, (unsigned long long)llrint(x * kVertFix));
 }
 
+constexpr int kVertLds = 128;  // items with up to this many vertices gather a unit piece's sums in LDS
+
 template <int T>
 __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
+  __shared__ unsigned long long s_vacc[kPersistWaves][2 * kVertLds];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
+  unsigned long long *L = s_vacc[threadIdx.x >> 6];
   cptr<ShapeRec> SR = konst(a.shapes);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -1421,6 +1431,12 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
     const bool open = SR[item].open != 0;
     const double sw = SR[item].sw;
     const bool staged = ec <= kStageEdges;
+    // small items: the piece's vertex sums gather in the wave's LDS (64-bit integer atomics, so the
+    // order does not matter), then one global atomic per vertex and component; large items add directly
+    const bool gather = nv <= kVertLds;
+    unsigned long long *acc = gather ? L : a.vacc + 2 * eo;
+    if (gather)
+      for (int m = lane; m < 2 * nv; m += 64) L[m] = 0ull;
     if (staged && q + wk.jhi > a.code_cap) stage_edges(a.edges + eo, ec, S, lane);
     for (int j = wk.jlo; j < wk.jhi; ++j) {
       int pxi, pyi;
@@ -1449,12 +1465,20 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
           adjoint_normal(e, pr, par, orient, open, nx, ny);
           const int ib = open ? min(bi + 1, nv - 1) : (bi + 1 == nv ? 0 : bi + 1);
           const double fa = -om * (1.0 - pr.u), fb = -om * pr.u;
-          vert_add(&a.vacc[2 * (eo + bi)], fa * nx);
-          vert_add(&a.vacc[2 * (eo + bi) + 1], fa * ny);
-          vert_add(&a.vacc[2 * (eo + ib)], fb * nx);
-          vert_add(&a.vacc[2 * (eo + ib) + 1], fb * ny);
+          vert_add(&acc[2 * bi], fa * nx);
+          vert_add(&acc[2 * bi + 1], fa * ny);
+          vert_add(&acc[2 * ib], fb * nx);
+          vert_add(&acc[2 * ib + 1], fb * ny);
         }
       }
+    }
+    if (gather) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int m = lane; m < 2 * nv; m += 64) {
+        const unsigned long long x = L[m];
+        if (x != 0ull) atomicAdd(&a.vacc[2 * eo + m], x);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
