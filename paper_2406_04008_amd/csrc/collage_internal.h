@@ -62,7 +62,7 @@ struct alignas(16) EdgeD {
 // Work counters at the start of the workspace (zeroed by the transform kernel of every call).
 enum Counter { CNT_UNITS = 0, CNT_WORDS = 8 };
 constexpr int kPersistWaves = 4;      // waves per workgroup of the persistent kernels
-constexpr int kCoverBlocksPerCU = 5;  // resident workgroups per CU: coverage kernel (LDS and VGPR bound)
+constexpr int kCoverBlocksPerCU = 6;  // resident workgroups per CU: coverage kernel (LDS and VGPR bound)
 constexpr int kAdjointBlocksPerCU = 4;  // and adjoint kernel (VGPR bound)
 
 // Kernel arguments (one struct, passed by value).
