@@ -834,31 +834,46 @@ __device__ __forceinline__ void stage_edges(const EdgeRec *E, int ne, float4 *ds
 
 struct ScanState {
   float best;               // smallest squared distance so far
-  int idx;                  // its edge (lowest index among equal distances)
+  int grp;                  // first edge of the earliest group of four edges that holds it
   unsigned long long par;   // lanes with an odd number of crossings so far
   unsigned long long up;    // lanes whose ordinate test holds for the current vertex
 };
 
 __device__ __forceinline__ void scan_start(ScanState &st, const float4 *S, float ry) {
   st.best = INFINITY;
-  st.idx = 0;
+  st.grp = 0;
   st.par = 0ull;
   st.up = __ballot(S[0].y > ry);  // a_y of the item's first edge
 }
 
-// r0 = (a_x, a_y, e_x / |e|^2, e_y / |e|^2), r1 = (e_x, e_y, b_y, e_x / e_y).
-__device__ __forceinline__ void scan_edge(const float4 r0, const float4 r1, int e, float rx, float ry, ScanState &st) {
+// Squared distance (float) from (rx, ry) to the edge of records r0 = (a_x, a_y, e_x / |e|^2, e_y / |e|^2),
+// r1 = (e_x, e_y, b_y, e_x / e_y).  The scan and the re-decision of the nearest edge both use this one
+// sequence, so they produce the same bits.
+__device__ __forceinline__ float edge_d2(const float4 r0, const float4 r1, float rx, float ry) {
   const float wx = rx - r0.x, wy = ry - r0.y;
   const float t = fmaf(wx, r0.z, wy * r0.w);
   const float u = __builtin_amdgcn_fmed3f(t, 0.0f, 1.0f);
   const float qx = fmaf(-u, r1.x, wx), qy = fmaf(-u, r1.y, wy);
-  const float d2 = fmaf(qx, qx, qy * qy);
-  st.idx = d2 < st.best ? e : st.idx;  // strict: the lowest index wins ties
-  st.best = fminf(st.best, d2);
+  return fmaf(qx, qx, qy * qy);
+}
+
+// One edge of the scan: its squared distance, and its crossing of the ray from the pixel towards +x
+// folded into the parity mask (half-open rule on the vertex ordinates, shared with the next edge).
+__device__ __forceinline__ float scan_edge(const float4 r0, const float4 r1, float rx, float ry, ScanState &st) {
+  const float d2 = edge_d2(r0, r1, rx, ry);
   const unsigned long long up_b = __ballot(r1.z > ry);
-  const unsigned long long left = __ballot(wx < wy * r1.w);
+  const unsigned long long left = __ballot(rx - r0.x < (ry - r0.y) * r1.w);
   st.par ^= (st.up ^ up_b) & left;
   st.up = up_b;
+  return d2;
+}
+
+// The minimum of a group of four edges (first edge e) enters the running minimum; strict comparison,
+// so the earliest group holding the minimum is kept.
+__device__ __forceinline__ void scan_group(float d0, float d1, float d2, float d3, int e, ScanState &st) {
+  const float g = fminf(fminf(d0, d1), fminf(d2, d3));
+  st.grp = g < st.best ? e : st.grp;
+  st.best = fminf(st.best, g);
 }
 
 // Edges [0, ne) of the staged slice S, numbered from ebase.  Each step loads four records' worth of
@@ -869,18 +884,30 @@ __device__ __forceinline__ void scan_lds(const float4 *S, int ne, int ebase, flo
   for (; e + 4 <= ne; e += 4) {
     const float4 *R = S + 2 * e;
     const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
-    scan_edge(r0, r1, ebase + e, rx, ry, st);
-    scan_edge(r2, r3, ebase + e + 1, rx, ry, st);
-    scan_edge(r4, r5, ebase + e + 2, rx, ry, st);
-    scan_edge(r6, r7, ebase + e + 3, rx, ry, st);
+    const float d0 = scan_edge(r0, r1, rx, ry, st);
+    const float d1 = scan_edge(r2, r3, rx, ry, st);
+    const float d2 = scan_edge(r4, r5, rx, ry, st);
+    const float d3 = scan_edge(r6, r7, rx, ry, st);
+    scan_group(d0, d1, d2, d3, ebase + e, st);
   }
   if (e < ne) {
     const float4 *R = S + 2 * e;
     const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
-    scan_edge(r0, r1, ebase + e, rx, ry, st);
-    if (e + 1 < ne) scan_edge(r2, r3, ebase + e + 1, rx, ry, st);
-    if (e + 2 < ne) scan_edge(r4, r5, ebase + e + 2, rx, ry, st);
+    const float d0 = scan_edge(r0, r1, rx, ry, st);
+    const float d1 = e + 1 < ne ? scan_edge(r2, r3, rx, ry, st) : INFINITY;
+    const float d2 = e + 2 < ne ? scan_edge(r4, r5, rx, ry, st) : INFINITY;
+    scan_group(d0, d1, d2, INFINITY, ebase + e, st);
   }
+}
+
+// The nearest edge within the winning group: the first of its edges (at most four, up to ec) whose
+// recomputed squared distance equals the scan's minimum, i.e. the first edge of the whole outline that
+// attains it.  R holds the item's records from edge 0 (LDS stage or global).
+__device__ __forceinline__ int scan_resolve(const float4 *R, int grp, int ec, float rx, float ry, float best) {
+  int bi = grp;
+  for (int j = min(grp + 3, ec - 1); j >= grp; --j)
+    if (edge_d2(R[2 * j], R[2 * j + 1], rx, ry) == best) bi = j;
+  return bi;
 }
 
 // Nearest edge and inside flag of the lane's pixel over all ec edges of the item at E.  When the item
@@ -891,6 +918,7 @@ __device__ __forceinline__ void scan_item(const EdgeRec *E, int ec, bool staged,
   if (staged) {
     scan_start(st, S, ry);
     scan_lds(S, ec, 0, rx, ry, st);
+    bi = scan_resolve(S, st.grp, ec, rx, ry, st.best);
   } else {
     for (int e0 = 0; e0 < ec; e0 += kStageEdges) {
       const int ne = min(kStageEdges, ec - e0);
@@ -898,8 +926,8 @@ __device__ __forceinline__ void scan_item(const EdgeRec *E, int ec, bool staged,
       if (e0 == 0) scan_start(st, S, ry);
       scan_lds(S, ne, e0, rx, ry, st);
     }
+    bi = scan_resolve(reinterpret_cast<const float4 *>(E), st.grp, ec, rx, ry, st.best);
   }
-  bi = st.idx;
   par = ((st.par >> lane) & 1ull) != 0ull;
 }
 
