@@ -833,14 +833,14 @@ __device__ __forceinline__ void stage_edges(const EdgeRec *E, int ne, float4 *ds
 }
 
 struct ScanState {
-  float best;               // smallest squared distance so far
+  unsigned best;            // bits of the smallest squared distance so far (see scan_group)
   int grp;                  // first edge of the earliest group of four edges that holds it
   unsigned long long par;   // lanes with an odd number of crossings so far
   unsigned long long up;    // lanes whose ordinate test holds for the current vertex
 };
 
 __device__ __forceinline__ void scan_start(ScanState &st, const float4 *S, float ry) {
-  st.best = INFINITY;
+  st.best = __float_as_uint(INFINITY);
   st.grp = 0;
   st.par = 0ull;
   st.up = __ballot(S[0].y > ry);  // a_y of the item's first edge
@@ -869,11 +869,13 @@ __device__ __forceinline__ float scan_edge(const float4 r0, const float4 r1, flo
 }
 
 // The minimum of a group of four edges (first edge e) enters the running minimum; strict comparison,
-// so the earliest group holding the minimum is kept.
+// so the earliest group holding the minimum is kept.  Squared distances are never negative, so their
+// bit patterns order as unsigned integers (NaN above +inf: never chosen, as with fminf), which needs
+// no canonicalization of the running value.
 __device__ __forceinline__ void scan_group(float d0, float d1, float d2, float d3, int e, ScanState &st) {
-  const float g = fminf(fminf(d0, d1), fminf(d2, d3));
+  const unsigned g = min(min(__float_as_uint(d0), __float_as_uint(d1)), min(__float_as_uint(d2), __float_as_uint(d3)));
   st.grp = g < st.best ? e : st.grp;
-  st.best = fminf(st.best, g);
+  st.best = min(st.best, g);
 }
 
 // Edges [0, ne) of the staged slice S, numbered from ebase.  Each step loads four records' worth of
@@ -903,10 +905,10 @@ __device__ __forceinline__ void scan_lds(const float4 *S, int ne, int ebase, flo
 // The nearest edge within the winning group: the first of its edges (at most four, up to ec) whose
 // recomputed squared distance equals the scan's minimum, i.e. the first edge of the whole outline that
 // attains it.  R holds the item's records from edge 0 (LDS stage or global).
-__device__ __forceinline__ int scan_resolve(const float4 *R, int grp, int ec, float rx, float ry, float best) {
+__device__ __forceinline__ int scan_resolve(const float4 *R, int grp, int ec, float rx, float ry, unsigned best) {
   int bi = grp;
   for (int j = min(grp + 3, ec - 1); j >= grp; --j)
-    if (edge_d2(R[2 * j], R[2 * j + 1], rx, ry) == best) bi = j;
+    if (__float_as_uint(edge_d2(R[2 * j], R[2 * j + 1], rx, ry)) == best) bi = j;
   return bi;
 }
 
