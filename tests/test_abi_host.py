@@ -58,6 +58,9 @@ def _desc(B=1, N=1, V=4, w=(16,), h=(16,), k=(1.0,), shapes=(0, 1), voff=(0, 4))
     (lambda d: setattr(d, "w_uniform", float("nan")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "tile", 12), _lib.ERR_UNSUPPORTED),
     (lambda d: setattr(d, "flags", 0x80), _lib.ERR_UNSUPPORTED),
+    (lambda d: setattr(d, "flags", 0x3), _lib.ERR_UNSUPPORTED),
+    (lambda d: setattr(d, "w_wmse", float("inf")), _lib.ERR_INVALID),
+    (lambda d: setattr(d, "w_objdown", float("nan")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "code_capacity", -2), _lib.ERR_INVALID),
     (lambda d: setattr(d, "bin_chunk", 1025), _lib.ERR_INVALID),
     (lambda d: setattr(d, "num_shapes", 2), _lib.ERR_SIZE),
@@ -98,6 +101,8 @@ def test_null_scene_calls_fail_cleanly():
     assert lib.collage_workspace_size(None, ctypes.byref(nb)) == _lib.ERR_INVALID
     assert lib.collage_forward(None, None, None, None, None, None, 0, None) == _lib.ERR_INVALID
     assert lib.collage_backward(None, None, None, None, None, 0, None) == _lib.ERR_INVALID
+    assert lib.collage_backward_vertices(None, None, None, None, None, None, 0, None) == _lib.ERR_INVALID
+    assert lib.collage_forward_backward(None, None, None, None, None, None, None, 0, None) == _lib.ERR_INVALID
     assert lib.collage_graph_launch(None, 1, None) == _lib.ERR_INVALID
     assert lib.collage_adam_reset(None, None, None, None, None) == _lib.ERR_INVALID
     out_g = ctypes.c_void_p()
