@@ -101,7 +101,7 @@ struct KArgs {
   int32_t *row_count;    // [rows] items whose support box meets the row band
   int32_t *row_list;     // per layout [tile rows][items]: those items, in item order
   int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
-                         // chunks of the tile's earlier units, 0)
+                         // chunks of the tile's earlier units, coverage cost of the tile's earlier units)
   int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units
   long long *tile_pre;   // [2][tiles + 1] exclusive prefix sums of the tile costs and of the tile chunks
   uint16_t *codes;       // [code_cap * 64] per chunk and lane: nearest edge (15 bits) | inside << 15

@@ -515,7 +515,7 @@ struct Walk {
   int64_t pix_off, list_base;
   long long p, end;        // cost prefix of the current unit (in this pass); end of the wave's range
   long long q0;            // first chunk of the tile
-  int4 aux;                // (chunks, cost per chunk, chunks of the tile's earlier units, 0) of the unit
+  int4 aux;                // (chunks, cost per chunk, chunks and cost of the tile's earlier units) of the unit
   int jlo, jhi;            // the wave's chunks [jlo, jhi) of the current unit
   bool adj;
 };
@@ -567,29 +567,48 @@ __device__ __forceinline__ void walk_range(Walk &w, long long b0) {
   w.jhi = hi < (long long)w.aux.x ? (int)hi : w.aux.x;
 }
 
+// The last index i in [0, n) with val(i) <= x, for a nondecreasing val with val(0) <= x, found by the
+// whole wave: each round loads 64 evenly spaced candidates of the remaining range at once (one vector
+// load instead of a chain of dependent ones) and keeps the segment after the last candidate <= x.
+template <class F>
+__device__ __forceinline__ int wave_last_le(int n, long long x, F val) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, len = n;
+  while (len > 1) {
+    const int step = (len + 63) >> 6;
+    const int i = lo + lane * step;
+    const bool ok = i < lo + len && val(i) <= x;
+    const int k = 63 - __clzll(__ballot(ok));  // lane 0 (i = lo) always qualifies
+    const int end = lo + len;
+    lo += k * step;
+    len = min(step, end - lo);
+  }
+  return uniform(lo);
+}
+
 // First piece of persistent wave gw: returns false when the wave has no work.
 __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T) {
-  cptr<long long> P = konst(a.tile_pre + (adj ? a.total_tiles + 1 : 0));
+  const long long *Pg = a.tile_pre + (adj ? a.total_tiles + 1 : 0);
+  cptr<long long> P = konst(Pg);
   const long long tot = P[a.total_tiles];
   w.adj = adj;
   if (tot <= 0) return false;
   const long long b0 = ((long long)gw * tot + nwaves - 1) / nwaves;
   w.end = ((long long)(gw + 1) * tot + nwaves - 1) / nwaves;
   if (b0 >= tot || w.end <= b0) return false;
-  int lo = 0, hi = a.total_tiles - 1;  // last tile with prefix <= b0
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (P[mid] <= b0)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  w.tile = lo;
-  w.slot = 0;
-  w.p = P[lo];
+  // the last tile whose prefix is <= b0 (it has work: a tile without any would share its prefix with
+  // the next one), then the last of its units whose prefix within the tile is <= b0 (units' prefixes
+  // grow strictly: every unit covers at least one pixel)
+  w.tile = wave_last_le(a.total_tiles, b0, [&](int i) { return Pg[i]; });
+  w.p = P[w.tile];
   walk_tile(a, w, T);
-  // skip the units that end at or before b0 (they belong to earlier waves); every unit has a
-  // positive cost, since it covers at least one pixel
+  w.slot = 0;
+  if (w.count > 0) {
+    const int4 *X = a.entry_aux + w.list_base;
+    w.slot = wave_last_le(w.count, b0 - w.p, [&](int i) { return (long long)(adj ? X[i].z : X[i].w); });
+    w.p += adj ? load_aux(a, w.list_base + w.slot).z : load_aux(a, w.list_base + w.slot).w;
+  }
+  // (the search leaves nothing to skip; the loop only guards the invariant)
   for (;;) {
     if (!walk_settle(a, w, T)) return false;
     const long long c = (long long)w.aux.x * chunk_cost(w);
@@ -713,20 +732,28 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
     slots += cnt;
     __syncthreads();
   }
-  // chunks of the tile's earlier units, per unit (first wave, 64 units at a time)
+  // chunks and coverage cost of the tile's earlier units, per unit (first wave, 64 units at a time)
   if (tid < 64) {
-    int run = 0;
+    int run = 0, run_cost = 0;
     for (int base = 0; base < slots; base += 64) {
       const int j = base + tid;
-      const int c = j < slots ? a.entry_aux[list_base + j].x : 0;
-      int x = c;
+      const int4 ax = j < slots ? a.entry_aux[list_base + j] : make_int4(0, 0, 0, 0);
+      const int c = ax.x, k = ax.x * ax.y;
+      int x = c, y = k;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (tid >= o) x += y;
+        const int xu = __shfl_up(x, o, 64), yu = __shfl_up(y, o, 64);
+        if (tid >= o) {
+          x += xu;
+          y += yu;
+        }
       }
-      if (j < slots) a.entry_aux[list_base + j].z = run + x - c;
+      if (j < slots) {
+        a.entry_aux[list_base + j].z = run + x - c;
+        a.entry_aux[list_base + j].w = run_cost + y - k;
+      }
       run += __shfl(x, 63, 64);
+      run_cost += __shfl(y, 63, 64);
     }
   }
   // tile totals of the unit costs (for the work partition of the persistent kernels)
