@@ -130,6 +130,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.total_ptiles = (int32_t)s->total_ptiles;
   a.total_rows = (int32_t)s->total_rows;
   a.rowbin = s->list_total > kRowBinTests ? 1 : 0;
+  a.scan_in_cover = s->total_tiles <= kScanInCoverTiles ? 1 : 0;
   a.tile = s->tile;
   a.bin_chunk = s->bin_chunk;
   a.unit_cap = (int32_t)s->unit_cap;

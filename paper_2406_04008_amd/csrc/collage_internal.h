@@ -97,6 +97,7 @@ struct KArgs {
   int32_t *tile_list;
   int32_t *item_slot;    // per layout [items][tiles]: the item's slot in the tile's list (set where listed)
   int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
+  int32_t scan_in_cover; // 1: the coverage kernel computes the tile prefixes (no scan launch)
   int32_t total_rows;    // tile rows over all layouts
   int32_t *row_count;    // [rows] items whose support box meets the row band
   int32_t *row_list;     // per layout [tile rows][items]: those items, in item order
@@ -166,6 +167,7 @@ constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
+constexpr int kScanInCoverTiles = 512;  // up to this many tiles the coverage kernel scans them itself
 constexpr int64_t kRowBinTests = 1 << 21;  // box tests (tiles x items) above which the row pass is used
 constexpr int kLossTerms = 9;   // overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
 constexpr double kWmseIn = 1.0;    // eq. 5 penalty inside the container

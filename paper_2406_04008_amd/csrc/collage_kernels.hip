@@ -50,6 +50,11 @@ __device__ __forceinline__ cptr<T> konst(const T *p) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_ll(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
 
 __device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
   cptr<int> q = (cptr<int>)(p + i);
@@ -515,6 +520,7 @@ struct Walk {
   int64_t pix_off, list_base;
   long long p, end;        // cost prefix of the current unit (in this pass); end of the wave's range
   long long q0;            // first chunk of the tile
+  const long long *Q;      // [tiles + 1] chunk prefix of the tiles (LDS or global)
   int4 aux;                // (chunks, cost per chunk, chunks and cost of the tile's earlier units) of the unit
   int jlo, jhi;            // the wave's chunks [jlo, jhi) of the current unit
   bool adj;
@@ -538,7 +544,7 @@ __device__ __forceinline__ void walk_tile(const KArgs &a, Walk &w, int T) {
   w.pix_off = LS[b].pix_off;
   w.list_base = LS[b].list_off + (int64_t)lt * nb;
   w.count = konst(a.tile_count)[w.tile];
-  w.q0 = konst(a.tile_pre)[(a.total_tiles + 1) + w.tile];
+  w.q0 = uniform_ll(w.Q[w.tile]);
 }
 
 __device__ __forceinline__ int chunk_cost(const Walk &w) { return w.adj ? 1 : w.aux.y; }
@@ -587,10 +593,11 @@ __device__ __forceinline__ int wave_last_le(int n, long long x, F val) {
 }
 
 // First piece of persistent wave gw: returns false when the wave has no work.
-__device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T) {
-  const long long *Pg = a.tile_pre + (adj ? a.total_tiles + 1 : 0);
-  cptr<long long> P = konst(Pg);
-  const long long tot = P[a.total_tiles];
+// P: [tiles + 1] prefix of the pass's tile costs (chunks for the adjoint passes); Q: the chunk prefix.
+__device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T,
+                                           const long long *P, const long long *Q) {
+  const long long tot = uniform_ll(P[a.total_tiles]);
+  w.Q = Q;
   w.adj = adj;
   if (tot <= 0) return false;
   const long long b0 = ((long long)gw * tot + nwaves - 1) / nwaves;
@@ -599,8 +606,8 @@ __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int 
   // the last tile whose prefix is <= b0 (it has work: a tile without any would share its prefix with
   // the next one), then the last of its units whose prefix within the tile is <= b0 (units' prefixes
   // grow strictly: every unit covers at least one pixel)
-  w.tile = wave_last_le(a.total_tiles, b0, [&](int i) { return Pg[i]; });
-  w.p = P[w.tile];
+  w.tile = wave_last_le(a.total_tiles, b0, [&](int i) { return P[i]; });
+  w.p = uniform_ll(P[w.tile]);
   walk_tile(a, w, T);
   w.slot = 0;
   if (w.count > 0) {
@@ -970,6 +977,57 @@ __device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int 
   py = r.y0 + ly;
 }
 
+// Exclusive prefix sums of the tiles' coverage costs (pc) and chunks (pq), [tiles + 1] each, for at most
+// kScanInCoverTiles tiles, by one 256-thread workgroup into LDS (two tiles per thread, DPP wave scans).
+// Workgroup 0 also writes them to tile_pre for the later passes and advances the Adam step counter,
+// which the scan kernel does otherwise.
+__device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq) {
+  __shared__ unsigned long long s_w[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nt = a.total_tiles, t0 = 2 * tid;
+  const int2 c0 = t0 < nt ? a.tile_cost[t0] : make_int2(0, 0);
+  const int2 c1 = t0 + 1 < nt ? a.tile_cost[t0 + 1] : make_int2(0, 0);
+  const unsigned long long vc = (unsigned long long)c0.x + (unsigned long long)c1.x;
+  const unsigned long long vq = (unsigned long long)c0.y + (unsigned long long)c1.y;
+  const unsigned long long xc = wave_incl_scan_u64(vc), xq = wave_incl_scan_u64(vq);
+  if (lane == 63) {
+    s_w[0][w] = xc;
+    s_w[1][w] = xq;
+  }
+  __syncthreads();
+  unsigned long long oc = 0, oq = 0, tc = 0, tq = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < w) {
+      oc += s_w[0][j];
+      oq += s_w[1][j];
+    }
+    tc += s_w[0][j];
+    tq += s_w[1][j];
+  }
+  const long long ec = (long long)(oc + xc - vc), eq = (long long)(oq + xq - vq);
+  if (t0 < nt) {
+    pc[t0] = ec;
+    pq[t0] = eq;
+  }
+  if (t0 + 1 < nt) {
+    pc[t0 + 1] = ec + c0.x;
+    pq[t0 + 1] = eq + c0.y;
+  }
+  if (tid == 0) {
+    pc[nt] = (long long)tc;
+    pq[nt] = (long long)tq;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int t = tid; t <= nt; t += 256) {
+      a.tile_pre[t] = pc[t];
+      a.tile_pre[nt + 1 + t] = pq[t];
+    }
+    if (tid == 0 && a.step_inc != nullptr) a.step_inc[0] = a.step_inc[0] + 1;
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // k_cover: coverage of every (unit, pixel) into the fixed-point accumulators.
 // ------------------------------------------------------------------------------------------------
@@ -985,7 +1043,16 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
-  for (bool ok = walk_begin(a, wk, gw, nwaves, false, T); ok; ok = walk_next(a, wk, T)) {
+  // the tiles' cost and chunk prefixes: computed here in LDS by every workgroup for small scenes (no
+  // separate scan launch; workgroup 0 publishes them for the later passes), else from the scan kernel
+  __shared__ long long s_pre[2][kScanInCoverTiles + 1];
+  const long long *P = a.tile_pre, *Q = a.tile_pre + (a.total_tiles + 1);
+  if (a.scan_in_cover) {
+    cover_tile_scan(a, s_pre[0], s_pre[1]);
+    P = s_pre[0];
+    Q = s_pre[1];
+  }
+  for (bool ok = walk_begin(a, wk, gw, nwaves, false, T, P, Q); ok; ok = walk_next(a, wk, T)) {
     const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
     const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
     const long long q = walk_chunk0(wk);
@@ -1353,7 +1420,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
-  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T); ok; ok = walk_next(a, wk, T)) {
+  const long long *Qg = a.tile_pre + (a.total_tiles + 1);
+  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
     const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
     const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
     const long long q = walk_chunk0(wk);
@@ -1477,7 +1545,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
-  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T); ok; ok = walk_next(a, wk, T)) {
+  const long long *Qg = a.tile_pre + (a.total_tiles + 1);
+  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
     const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
     const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
     const long long q = walk_chunk0(wk);
@@ -1818,6 +1887,7 @@ hipError_t launch_bin(const KArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_scan(const KArgs &a, hipStream_t st) {
+  if (a.scan_in_cover) return hipSuccess;  // the coverage kernel computes the prefixes itself
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
