@@ -64,10 +64,16 @@ __device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
 // v moved between lanes by the DPP control CTRL (rows outside ROW_MASK and lanes whose source is out of
 // the row read 0); the two 32-bit halves move separately.
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v, unsigned long long old = 0ull) {
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(old >> 32), (int)(unsigned)(v >> 32), CTRL, ROW_MASK,
+                                             0xf, false);
   return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: Hillis-Steele within each row of 16 lanes
@@ -101,23 +107,52 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 // The sum over a wave's 64 lanes (every lane active), broadcast to all of them.
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
+__device__ __forceinline__ unsigned long long readlane63_u64(unsigned long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Inclusive prefix sum of 32-bit values over the wave (the DPP pattern of wave_incl_scan_u64).
+__device__ __forceinline__ unsigned wave_incl_scan_u32(unsigned v) {
+  v += dpp_u32<0x111, 0xf>(v);
+  v += dpp_u32<0x112, 0xf>(v);
+  v += dpp_u32<0x114, 0xf>(v);
+  v += dpp_u32<0x118, 0xf>(v);
+  v += dpp_u32<0x142, 0xa>(v);
+  v += dpp_u32<0x143, 0xc>(v);
+  return v;
+}
+
+// Sum over the wave's lanes (every lane active), broadcast.
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return (long long)readlane63_u64(wave_incl_scan_u64((unsigned long long)v));
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+// Minimum and maximum over the wave's lanes (every lane active), broadcast: the scan pattern with the
+// operation's identity moved into lanes without a source.
+template <bool MAX>
+__device__ __forceinline__ double wave_extreme(double x) {
+  const unsigned long long id = (unsigned long long)__double_as_longlong(MAX ? -INFINITY : INFINITY);
+  unsigned long long v = (unsigned long long)__double_as_longlong(x);
+#define COLLAGE_EXT_STEP(CTRL, MASK)                                                      \
+  {                                                                                       \
+    const double o = __longlong_as_double((long long)dpp_u64<CTRL, MASK>(v, id));         \
+    const double c = __longlong_as_double((long long)v);                                  \
+    v = (unsigned long long)__double_as_longlong(MAX ? fmax(c, o) : fmin(c, o));          \
+  }
+  COLLAGE_EXT_STEP(0x111, 0xf)
+  COLLAGE_EXT_STEP(0x112, 0xf)
+  COLLAGE_EXT_STEP(0x114, 0xf)
+  COLLAGE_EXT_STEP(0x118, 0xf)
+  COLLAGE_EXT_STEP(0x142, 0xa)
+  COLLAGE_EXT_STEP(0x143, 0xc)
+#undef COLLAGE_EXT_STEP
+  return __longlong_as_double((long long)readlane63_u64(v));
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
+__device__ __forceinline__ double wave_min(double v) { return wave_extreme<false>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_extreme<true>(v); }
 
 __device__ __forceinline__ int layout_of_shape(cptr<LayoutRec> L, int B, int sid) {
   int lo = 0, hi = B - 1;
@@ -746,21 +781,13 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       const int j = base + tid;
       const int4 ax = j < slots ? a.entry_aux[list_base + j] : make_int4(0, 0, 0, 0);
       const int c = ax.x, k = ax.x * ax.y;
-      int x = c, y = k;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int xu = __shfl_up(x, o, 64), yu = __shfl_up(y, o, 64);
-        if (tid >= o) {
-          x += xu;
-          y += yu;
-        }
-      }
+      const int x = (int)wave_incl_scan_u32((unsigned)c), y = (int)wave_incl_scan_u32((unsigned)k);
       if (j < slots) {
         a.entry_aux[list_base + j].z = run + x - c;
         a.entry_aux[list_base + j].w = run_cost + y - k;
       }
-      run += __shfl(x, 63, 64);
-      run_cost += __shfl(y, 63, 64);
+      run += __builtin_amdgcn_readlane(x, 63);
+      run_cost += __builtin_amdgcn_readlane(y, 63);
     }
   }
   // tile totals of the unit costs (for the work partition of the persistent kernels)
@@ -1705,13 +1732,8 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
         cnt = ax.x;
         first = q0[lt] + ax.z;
       }
-      int x = cnt;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-      }
-      const int pre = x - cnt, total = __shfl(x, 63, 64);
+      const int x = (int)wave_incl_scan_u32((unsigned)cnt);
+      const int pre = x - cnt, total = __builtin_amdgcn_readlane(x, 63);
       // then the chunks of those units, one per lane, all loads in flight together
       for (int kb = 0; kb < total; kb += 64) {
         const int kk = kb + lane;
