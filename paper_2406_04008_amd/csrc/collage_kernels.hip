@@ -1737,15 +1737,10 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
       // then the chunks of those units, one per lane, all loads in flight together
       for (int kb = 0; kb < total; kb += 64) {
         const int kk = kb + lane;
-        int lo = 0, hi = nl - 1;  // the last tile whose first chunk is <= kk
-#pragma unroll
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (__shfl(pre, mid, 64) <= kk)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
+        // the last tile whose first chunk is <= kk: the number of later tiles starting at or before kk
+        // (the tiles' first chunks are read lane by lane into scalar registers; an item meets few tiles)
+        int lo = 0;
+        for (int t = 1; t < nl; ++t) lo += __builtin_amdgcn_readlane(pre, t) <= kk ? 1 : 0;
         const long long f = __shfl(first, lo, 64);
         const int pt = __shfl(pre, lo, 64);
         if (kk < total) {
