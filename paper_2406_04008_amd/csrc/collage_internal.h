@@ -177,6 +177,7 @@ constexpr int kUniHalo = 11;    // largest window radius (2 + 3 (kUniWindows - 1
 constexpr int kPixTile = 32;    // pixel tile edge of the per-pixel and window passes
 constexpr int kPixThreads = kPixTile * kPixTile;  // their workgroup: one thread per pixel
 constexpr int kEpilogueCost = 32;  // per-pixel work after the scan, in edge evaluations (work partition)
+constexpr int kUnitCost = 128;     // per-unit setup (records, edge staging), spread over the unit's chunks
 constexpr int kMaxVertsPerItem = 32767;
 constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point scale of the coverage accumulators
 constexpr double kFixInv = 1.0 / 1099511627776.0;

@@ -766,7 +766,7 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       a.item_slot[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = slots + q;
       const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
       const int chunks = (r.n + 63) >> 6;
-      const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost;
+      const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
       a.entry_aux[list_base + slots + q] = make_int4(chunks, cpc, 0, 0);
       my_cost += (long long)chunks * cpc;
       my_quads += chunks;
