@@ -57,7 +57,7 @@ struct collage_scene {
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_islot = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
-         off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0;
+         off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
 };
 
@@ -155,6 +155,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.row_count = reinterpret_cast<int32_t *>(w + s->off_rcount);
   a.row_list = reinterpret_cast<int32_t *>(w + s->off_rlist);
   a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
+  a.units = reinterpret_cast<UnitRec *>(w + s->off_units);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
   a.partial = reinterpret_cast<double4 *>(w + s->off_partial);
@@ -311,6 +312,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->adjoint_grid = cus * kAdjointBlocksPerCU;
   s->off_aux = off;
   off = align256(off + sizeof(int4) * (size_t)list);
+  s->off_units = off;
+  off = align256(off + sizeof(UnitRec) * (size_t)list);
   s->off_tcost = off;
   off = align256(off + sizeof(int2) * (size_t)tiles);
   s->off_tpre = off;

@@ -37,6 +37,16 @@ struct alignas(16) ShapeRec {
   double sw_ds;      // open: d sw / d s = k w sign(s)
 };
 
+// One (tile, item) work unit as the persistent passes read it, written by the binning kernel beside the
+// unit's list entry: a wave loads one record per unit instead of the list entry and then the item's.
+struct alignas(16) UnitRec {
+  int32_t eo, ec, nv, open;  // the item's first edge record (= first vertex), edges, vertices, open flag
+  int32_t x0, y0, w, n;      // the unit rectangle: the item's support box clipped to the tile (w x n / w px)
+  float cxf, cyf, orient;    // the item's origin (float) and outline orientation
+  int32_t pad_;
+  double cx, cy, sw, sw_ds;  // the origin (double), stroke radius and its derivative in s
+};
+
 // Per edge (a, b) of an item, in level px relative to the item's origin (cx, cy).
 // b is stored explicitly so that the half-open crossing test compares every vertex with the same
 // float value from both edges that share it.
@@ -101,6 +111,7 @@ struct KArgs {
   int32_t total_rows;    // tile rows over all layouts
   int32_t *row_count;    // [rows] items whose support box meets the row band
   int32_t *row_list;     // per layout [tile rows][items]: those items, in item order
+  UnitRec *units;        // per list entry (tile, slot) = unit: its record
   int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
                          // chunks of the tile's earlier units, coverage cost of the tile's earlier units)
   int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units

@@ -766,6 +766,27 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       a.item_slot[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = slots + q;
       const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
       const int chunks = (r.n + 63) >> 6;
+      {
+        const ShapeRec &sr = a.shapes[sid];
+        UnitRec u;
+        u.eo = sr.edge_off;
+        u.ec = sr.edge_cnt;
+        u.nv = a.vert_off[sid + 1] - a.vert_off[sid];
+        u.open = sr.open;
+        u.x0 = r.x0;
+        u.y0 = r.y0;
+        u.w = r.w;
+        u.n = r.n;
+        u.cxf = sr.cxf;
+        u.cyf = sr.cyf;
+        u.orient = sr.orient;
+        u.pad_ = 0;
+        u.cx = sr.cx;
+        u.cy = sr.cy;
+        u.sw = sr.sw;
+        u.sw_ds = sr.sw_ds;
+        a.units[list_base + slots + q] = u;
+      }
       const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
       a.entry_aux[list_base + slots + q] = make_int4(chunks, cpc, 0, 0);
       my_cost += (long long)chunks * cpc;
@@ -1066,7 +1087,6 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
-  cptr<ShapeRec> SR = konst(a.shapes);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
@@ -1080,14 +1100,14 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
     Q = s_pre[1];
   }
   for (bool ok = walk_begin(a, wk, gw, nwaves, false, T, P, Q); ok; ok = walk_next(a, wk, T)) {
-    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
-    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
+    const Rect r = {U->x0, U->y0, U->w, U->n};
     const long long q = walk_chunk0(wk);
-    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
-    const float cxf = SR[item].cxf, cyf = SR[item].cyf;
-    const double cx = SR[item].cx, cy = SR[item].cy;
-    const bool open = SR[item].open != 0;
-    const double sw = SR[item].sw;
+    const int eo = U->eo, ec = U->ec;
+    const float cxf = U->cxf, cyf = U->cyf;
+    const double cx = U->cx, cy = U->cy;
+    const bool open = U->open != 0;
+    const double sw = U->sw;
     const bool staged = ec <= kStageEdges;
     if (staged) stage_edges(a.edges + eo, ec, S, lane);
     for (int j = wk.jlo; j < wk.jhi; ++j) {
@@ -1443,20 +1463,19 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   __shared__ float4 s_stage[kPersistWaves][kStageSlots];
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
-  cptr<ShapeRec> SR = konst(a.shapes);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
   for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
-    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
-    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
+    const Rect r = {U->x0, U->y0, U->w, U->n};
     const long long q = walk_chunk0(wk);
-    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
-    const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
-    const double cx = SR[item].cx, cy = SR[item].cy;
-    const bool open = SR[item].open != 0;
-    const double sw = SR[item].sw, sw_ds = SR[item].sw_ds;
+    const int eo = U->eo, ec = U->ec;
+    const float cxf = U->cxf, cyf = U->cyf, orient = U->orient;
+    const double cx = U->cx, cy = U->cy;
+    const bool open = U->open != 0;
+    const double sw = U->sw, sw_ds = U->sw_ds;
     // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1568,21 +1587,19 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
   const int lane = threadIdx.x & 63;
   float4 *S = s_stage[threadIdx.x >> 6];
   unsigned long long *L = s_vacc[threadIdx.x >> 6];
-  cptr<ShapeRec> SR = konst(a.shapes);
   const int gw = global_wave();
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
   for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
-    const int item = uniform(konst(a.tile_list)[wk.list_base + wk.slot]);
-    const Rect r = unit_rect(load_box(konst(a.bbox), item), wk.x0, wk.y0, T);
+    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
+    const Rect r = {U->x0, U->y0, U->w, U->n};
     const long long q = walk_chunk0(wk);
-    const int eo = SR[item].edge_off, ec = SR[item].edge_cnt;
-    const int nv = a.vert_off[item + 1] - a.vert_off[item];
-    const float cxf = SR[item].cxf, cyf = SR[item].cyf, orient = SR[item].orient;
-    const double cx = SR[item].cx, cy = SR[item].cy;
-    const bool open = SR[item].open != 0;
-    const double sw = SR[item].sw;
+    const int eo = U->eo, ec = U->ec, nv = U->nv;
+    const float cxf = U->cxf, cyf = U->cyf, orient = U->orient;
+    const double cx = U->cx, cy = U->cy;
+    const bool open = U->open != 0;
+    const double sw = U->sw;
     const bool staged = ec <= kStageEdges;
     // small items: the piece's vertex sums gather in the wave's LDS (64-bit integer atomics, so the
     // order does not matter), then one global atomic per vertex and component; large items add directly
