@@ -65,7 +65,7 @@ def support_pairs(scene, params, level):
     return int(n.sum())
 
 
-def cpu_baseline(scene, level, budget_s=16.0, max_iters=2000):
+def cpu_baseline(scene, level, budget_s=22.0, max_iters=2000):
     """The FP64 oracle (forward, backward, Adam) on the same scene, timed on this host's cores."""
     from oracle import oracle as orc
 

@@ -1754,10 +1754,23 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
       // then the chunks of those units, one per lane, all loads in flight together
       for (int kb = 0; kb < total; kb += 64) {
         const int kk = kb + lane;
-        // the last tile whose first chunk is <= kk: the number of later tiles starting at or before kk
-        // (the tiles' first chunks are read lane by lane into scalar registers; an item meets few tiles)
+        // the last tile whose first chunk is <= kk: for a few tiles, the number of later tiles starting
+        // at or before kk (their first chunks read lane by lane into scalar registers); for many, a
+        // binary search over the lanes
         int lo = 0;
-        for (int t = 1; t < nl; ++t) lo += __builtin_amdgcn_readlane(pre, t) <= kk ? 1 : 0;
+        if (nl <= 8) {
+          for (int t = 1; t < nl; ++t) lo += __builtin_amdgcn_readlane(pre, t) <= kk ? 1 : 0;
+        } else {
+          int hi = nl - 1;
+#pragma unroll
+          for (int step = 0; step < 6; ++step) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (__shfl(pre, mid, 64) <= kk)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+        }
         const long long f = __shfl(first, lo, 64);
         const int pt = __shfl(pre, lo, 64);
         if (kk < total) {
