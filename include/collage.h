@@ -199,9 +199,11 @@ int collage_render_shapes(const collage_scene *scene, const float *params, int32
                           float *alpha_pad, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Event timer: `count` pairs of HIP events (timing enabled).  collage_iterate_n records one pair per
- * epoch around the coverage kernel.  collage_timer_elapsed waits for the events and writes the `count`
- * durations in milliseconds.
+ * Event timer: `count` pairs of HIP events (timing enabled).  collage_iterate_n timestamps the coverage
+ * kernel of epochs 0, d, 2d, ... with d = ceil(epochs / count): every epoch when count >= epochs, else a
+ * spread sample (each stamped launch costs a few microseconds of stream time, so a sample keeps the
+ * timed work close to an untimed call).  collage_timer_elapsed waits for the events and writes `count`
+ * durations in milliseconds: those of the pairs the last collage_iterate_n call recorded, then NaN.
  */
 typedef struct collage_timer collage_timer;
 int collage_timer_create(int32_t count, collage_timer **out);
@@ -212,8 +214,8 @@ void collage_timer_destroy(collage_timer *timer);
  * `epochs` (1..65536) consecutive collage_iterate epochs in one call, on `stream`.  Equivalent to that
  * many collage_iterate calls; loss, grad and the optional images are those of the last epoch.  Within
  * the call, the update of each epoch also transforms the items for the next one (one launch fewer per
- * epoch).  With a non-NULL `timer` (at least `epochs` pairs), pair e is timestamped with the start and
- * the end of epoch e's coverage kernel.  Errors: those of collage_iterate; COLLAGE_ERR_SIZE if the timer is too small.
+ * epoch).  With a non-NULL `timer` of c pairs, pair j is timestamped with the start and the end of the
+ * coverage kernel of epoch j d, d = ceil(epochs / c).  Errors: those of collage_iterate.
  */
 int collage_iterate_n(const collage_scene *scene, float *params, float *cov, float *cov_pad, float *loss, float *grad,
                       float *m, float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps,

@@ -199,8 +199,8 @@ class CollageScene:
 
     def iterate_n(self, params, m, v, step, epochs: int, loss=None, grad=None, timer: Optional["Timer"] = None,
                   stream=None, lr_px=None, betas=(0.9, 0.999), eps=1e-8):
-        """`epochs` epochs in one call (collage_iterate_n); with `timer`, one event pair per epoch around the
-        coverage kernel.  Returns (loss, grad) of the last epoch."""
+        """`epochs` epochs in one call (collage_iterate_n); with a timer of c pairs, the coverage kernels of
+        epochs 0, d, 2d, ... (d = ceil(epochs / c)) are timestamped.  Returns (loss, grad) of the last epoch."""
         lr_px = self.scene.lr_px if lr_px is None else lr_px
         loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device) if loss is None else loss
         grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
@@ -285,9 +285,10 @@ class Timer:
         self.handle = h
 
     def elapsed_ms(self) -> np.ndarray:
+        """Durations of the pairs the last iterate_n call recorded (the unrecorded tail is dropped)."""
         out = np.zeros(self.count, np.float32)
         _lib.check(self.lib.collage_timer_elapsed(self.handle, out.ctypes.data_as(_lib._f32p)), "collage_timer_elapsed")
-        return out
+        return out[~np.isnan(out)]
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <limits>
 #include <vector>
 
 #include "collage.h"
@@ -68,6 +69,7 @@ struct collage_graph {
 
 struct collage_timer {
   std::vector<hipEvent_t> start, stop;
+  int32_t recorded = 0;  // pairs recorded by the last collage_iterate_n call
 };
 
 namespace {
@@ -494,7 +496,8 @@ namespace {
 
 // n consecutive epochs (forward, loss, backward, Adam).  Only the first epoch launches the transform
 // kernel: the update kernel of every other epoch transforms the items with their new parameters.
-// With a timer, pair e of `timer` is recorded around epoch e's coverage kernel.
+// With a timer of c pairs, the coverage kernels of epochs 0, d, 2d, ... (d = ceil(n / c)) are timestamped,
+// pair j around epoch j d: a spread sample of the call's launches when c < n, every launch otherwise.
 int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_pad, float *loss, float *grad, float *m,
                  float *v, int32_t *step, float lr_px, float beta1, float beta2, float eps, void *ws, size_t ws_bytes,
                  void *stream, int32_t n, collage_timer *timer) {
@@ -503,7 +506,6 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
     return fail(COLLAGE_ERR_INVALID, "an iterate buffer is NULL");
   if (s->N > 0 && !s->rho) return fail(COLLAGE_ERR_INVALID, "the scene has no rho (needed by the update)");
   if (n < 1 || n > 65536) return fail(COLLAGE_ERR_INVALID, "epochs must be 1..65536 (got %d)", n);
-  if (timer && (int64_t)timer->start.size() < n) return fail(COLLAGE_ERR_SIZE, "the timer has fewer pairs than epochs");
   int rc = check_adam(lr_px, beta1, beta2, eps);
   if (rc) return rc;
   rc = check_ws(s, ws, ws_bytes);
@@ -526,11 +528,15 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
   a.eps = eps;
   a.write_loss = 1;
   a.keep_codes = 1;
+  const int32_t stride = timer ? (int32_t)((n + (int64_t)timer->start.size() - 1) / (int64_t)timer->start.size()) : 1;
+  if (timer) timer->recorded = (n + stride - 1) / stride;
   hipError_t e = launch_transform(a, st);
   for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+    const bool stamp = timer && i % stride == 0;
     e = launch_bin(a, st);
     if (e == hipSuccess) e = launch_scan(a, st);
-    if (e == hipSuccess) e = launch_cover(a, st, timer ? timer->start[i] : nullptr, timer ? timer->stop[i] : nullptr);
+    if (e == hipSuccess)
+      e = launch_cover(a, st, stamp ? timer->start[i / stride] : nullptr, stamp ? timer->stop[i / stride] : nullptr);
     if (e == hipSuccess) e = launch_pixel(a, true, st);
     if (e == hipSuccess) e = launch_uniform_grad(a, st);
     if (e == hipSuccess) e = launch_adjoint(a, st);
@@ -580,6 +586,10 @@ int collage_timer_create(int32_t count, collage_timer **out) {
 int collage_timer_elapsed(collage_timer *t, float *ms) {
   if (!t || !ms) return fail(COLLAGE_ERR_INVALID, "timer or ms is NULL");
   for (size_t i = 0; i < t->start.size(); ++i) {
+    if ((int64_t)i >= t->recorded) {
+      ms[i] = std::numeric_limits<float>::quiet_NaN();
+      continue;
+    }
     hipError_t e = hipEventSynchronize(t->stop[i]);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], t->start[i], t->stop[i]);
     if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");

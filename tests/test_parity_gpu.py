@@ -13,7 +13,7 @@ import torch
 from oracle.oracle import Oracle
 from paper_2406_04008_amd import _lib
 from paper_2406_04008_amd import scenes as S
-from paper_2406_04008_amd.collage import CollageLoss, CollageScene
+from paper_2406_04008_amd.collage import CollageLoss, CollageScene, Timer
 from tests.parity_util import check_grad, check_image, check_loss, check_vgrad, grad_error
 
 pytestmark = pytest.mark.gpu
@@ -196,6 +196,26 @@ def test_iterate_n_equals_repeated_iterate(tile):
     assert torch.equal(p1, p2) and torch.equal(m1, m2) and torch.equal(v1, v2)
     assert torch.equal(l1, l2) and torch.equal(g1, g2)
     assert int(s1.item()) == int(s2.item()) == 5
+
+
+@pytest.mark.parametrize("pairs,epochs,stamped", [(3, 7, 3), (10, 7, 7), (2, 7, 2), (1, 1, 1)])
+def test_iterate_n_timer_sampling(pairs, epochs, stamped):
+    # a timer of c pairs stamps the coverage launches of epochs 0, d, 2d, ... (d = ceil(epochs / c));
+    # the timestamps change nothing in what the epochs compute
+    sc = S.random_scene(4, [(60, 44), (33, 47)], [12, 7], off_canvas=0.2)
+    _say("timer", pairs, epochs)
+    cs = CollageScene(sc, tile=16)
+    p1 = cs.params_tensor()
+    m1, v1, s1 = cs.new_state()
+    l1, g1 = cs.iterate_n(p1, m1, v1, s1, epochs)
+    p2 = cs.params_tensor()
+    m2, v2, s2 = cs.new_state()
+    t = Timer(pairs)
+    l2, g2 = cs.iterate_n(p2, m2, v2, s2, epochs, timer=t)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(l1, l2) and torch.equal(g1, g2)
+    ms = t.elapsed_ms()
+    assert len(ms) == stamped and np.all(ms > 0) and np.all(ms < 1e3)
 
 
 def test_graph_replay_matches_eager():
