@@ -57,7 +57,7 @@ struct collage_scene {
   // workspace layout
   int64_t unit_cap = 0;
   size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_islot = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
 };
@@ -153,7 +153,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
   a.block_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
-  a.item_slot = reinterpret_cast<int32_t *>(w + s->off_islot);
+  a.item_unit = reinterpret_cast<int2 *>(w + s->off_iunit);
   a.row_count = reinterpret_cast<int32_t *>(w + s->off_rcount);
   a.row_list = reinterpret_cast<int32_t *>(w + s->off_rlist);
   a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
@@ -300,8 +300,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)s->V);
   s->off_list = off;
   off = align256(off + sizeof(int32_t) * (size_t)list);
-  s->off_islot = off;
-  off = align256(off + sizeof(int32_t) * (size_t)list);
+  s->off_iunit = off;
+  off = align256(off + sizeof(int2) * (size_t)list);
   s->off_rcount = off;
   off = align256(off + sizeof(int32_t) * (size_t)rows);
   s->off_rlist = off;

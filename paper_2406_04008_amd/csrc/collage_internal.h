@@ -105,7 +105,8 @@ struct KArgs {
   int32_t *counters;
   int32_t *tile_count;
   int32_t *tile_list;
-  int32_t *item_slot;    // per layout [items][tiles]: the item's slot in the tile's list (set where listed)
+  int2 *item_unit;       // per layout [items][tiles]: the item's unit in the tile (its chunks, chunks of the
+                         // tile's earlier units), set where the tile lists the item
   int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
   int32_t scan_in_cover; // 1: the coverage kernel computes the tile prefixes (no scan launch)
   int32_t total_rows;    // tile rows over all layouts

@@ -154,6 +154,23 @@ __device__ __forceinline__ double wave_extreme(double x) {
 __device__ __forceinline__ double wave_min(double v) { return wave_extreme<false>(v); }
 __device__ __forceinline__ double wave_max(double v) { return wave_extreme<true>(v); }
 
+// The bias corrections 1 - beta^t of step t, computed in one place for every caller so that all update
+// paths round them alike.  beta^t by binary powering in double (at most 2 log2 t + 2 products, so a
+// relative error below 1e-14): 1 - beta^t then rounds to the float nearest the exact value except in
+// rare near-halfway cases, with a dependent chain far shorter than a general float power function.
+__device__ __forceinline__ float2 adam_bias_of(const KArgs &a, int32_t t) {
+  double p1 = 1.0, p2 = 1.0, b1 = (double)a.beta1, b2 = (double)a.beta2;
+  for (unsigned n = t > 0 ? (unsigned)t : 0u; n != 0u; n >>= 1) {
+    if (n & 1u) {
+      p1 *= b1;
+      p2 *= b2;
+    }
+    b1 *= b1;
+    b2 *= b2;
+  }
+  return make_float2((float)(1.0 - p1), (float)(1.0 - p2));
+}
+
 __device__ __forceinline__ int layout_of_shape(cptr<LayoutRec> L, int B, int sid) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
@@ -189,14 +206,60 @@ __device__ __forceinline__ void place_vertex(double c, double sn, double s, doub
   y = k * (sn * sx + c * sy);
 }
 
+// What the transform of an item reads besides its parameters: loaded ahead of the parameters where
+// those come out of the same kernel (the update), so that the loads overlap the work before it.
+constexpr int kTransformPre = 2;  // edges per lane loaded ahead (items of up to 128 edges)
+struct TransformPre {
+  int v0, n, ec;
+  float wst;                        // stroke half-width, 0 for a closed item
+  float2 va[kTransformPre], vb[kTransformPre];  // end points of edges lane + 64 r
+};
+
+__device__ __forceinline__ int transform_edge_end(bool open, int n, int m) {
+  // an open item has edges between consecutive vertices only (a single vertex: one point edge)
+  return open ? min(m + 1, n - 1) : (m + 1 == n ? 0 : m + 1);
+}
+
+// What lanes past an item's last edge, and items without a stroke array, load (global memory, like the
+// arrays they stand in for, so that the loads stay plain global loads).
+__device__ float2 kNoVertex = {0.0f, 0.0f};
+__device__ float kNoFloat = 0.0f;
+
+// The loads are unconditional (lanes without an edge read kNoVertex), so that nothing consumes their
+// results before the caller does.
+__device__ __forceinline__ TransformPre transform_preload(const KArgs &a, int sid, int lane) {
+  TransformPre t;
+  t.v0 = a.vert_off[sid];
+  t.n = a.vert_off[sid + 1] - t.v0;
+  t.wst = *(a.stroke ? a.stroke + sid : &kNoFloat);
+  const bool open = t.wst > 0.0f;
+  t.ec = open ? (t.n > 1 ? t.n - 1 : t.n) : t.n;
+  const float2 *V = reinterpret_cast<const float2 *>(a.verts) + t.v0;
+#pragma unroll
+  for (int r = 0; r < kTransformPre; ++r) {
+    const int m = lane + 64 * r;
+    const bool has = m < t.ec;
+    t.va[r] = *(has ? V + m : &kNoVertex);
+    t.vb[r] = *(has ? V + transform_edge_end(open, t.n, m) : &kNoVertex);
+  }
+  return t;
+}
+
+// An empty asm statement that takes the preloaded vertices as read and rewritten: the compiler cannot
+// move their conversions ahead of it, so the loads stay in flight through the work in between.
+__device__ __forceinline__ void transform_hold(TransformPre &t) {
+#pragma unroll
+  for (int r = 0; r < kTransformPre; ++r)
+    asm volatile("" : "+v"(t.va[r].x), "+v"(t.va[r].y), "+v"(t.vb[r].x), "+v"(t.vb[r].y));
+}
+
 // One wave transforms item sid with parameters p (the same in every lane).
-__device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
+__device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, const TransformPre &tp) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_shape(LS, a.num_layouts, sid);
   const double k = (double)LS[b].k;
   const int W = LS[b].W, H = LS[b].H;
-  const int v0 = a.vert_off[sid];
-  const int n = a.vert_off[sid + 1] - v0;
+  const int v0 = tp.v0, n = tp.n, ec = tp.ec;
   const bool finite = isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w);
   double sn, c;
   sincos(finite ? (double)p.z : 0.0, &sn, &c);
@@ -205,29 +268,35 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
   const float2 *V = reinterpret_cast<const float2 *>(a.verts) + v0;
   if (a.vacc)
     for (int m = lane; m < 2 * n; m += 64) a.vacc[2 * v0 + m] = 0ull;
-  // an open item has edges between consecutive vertices only (a single vertex: one point edge)
-  const float wst = a.stroke ? a.stroke[sid] : 0.0f;
+  const float wst = tp.wst;
   const bool open = wst > 0.0f;
-  const int ec = open ? (n > 1 ? n - 1 : n) : n;
   double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY, area2 = 0.0;
-  for (int m = lane; m < ec; m += 64) {
-    const int mb = open ? min(m + 1, n - 1) : (m + 1 == n ? 0 : m + 1);
+  for (int r = 0, m = lane; m < ec; ++r, m += 64) {
+    float2 va, vb;
+    static_assert(kTransformPre == 2, "the preloaded edges are picked by r == 0 / r == 1");
+    if (r < kTransformPre) {
+      va = r == 0 ? tp.va[0] : tp.va[1];
+      vb = r == 0 ? tp.vb[0] : tp.vb[1];
+    } else {
+      va = V[m];
+      vb = V[transform_edge_end(open, n, m)];
+    }
     double ax, ay, bx, by;
-    place_vertex(c, sn, s, k, V[m], ax, ay);
-    place_vertex(c, sn, s, k, V[mb], bx, by);
+    place_vertex(c, sn, s, k, va, ax, ay);
+    place_vertex(c, sn, s, k, vb, bx, by);
     const double ex = bx - ax, ey = by - ay;
     const double ee = ex * ex + ey * ey;
     const double inv = ee > 0.0 ? 1.0 / ee : 0.0;
-    EdgeRec r;
-    r.ax = (float)ax;
-    r.ay = (float)ay;
-    r.exs = (float)(ex * inv);
-    r.eys = (float)(ey * inv);
-    r.ex = (float)ex;
-    r.ey = (float)ey;
-    r.by = (float)by;  // equals the next edge's ay: the same double rounded the same way
-    r.slope = ey != 0.0 ? (float)(ex / ey) : 0.0f;
-    a.edges[v0 + m] = r;
+    EdgeRec er;
+    er.ax = (float)ax;
+    er.ay = (float)ay;
+    er.exs = (float)(ex * inv);
+    er.eys = (float)(ey * inv);
+    er.ex = (float)ex;
+    er.ey = (float)ey;
+    er.by = (float)by;  // equals the next edge's ay: the same double rounded the same way
+    er.slope = ey != 0.0 ? (float)(ex / ey) : 0.0f;
+    a.edges[v0 + m] = er;
     EdgeD rd;
     rd.ax = ax;
     rd.ay = ay;
@@ -235,13 +304,10 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p) {
     rd.ey = ey;
     rd.inv_ee = inv;
     // d v' / d s = k R(theta) v for both end points (exact also when s = 0)
-    {
-      const float2 va = V[m], vb = V[mb];
-      rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
-      rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
-      rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
-      rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
-    }
+    rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
+    rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
+    rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
+    rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
     a.edges_d[v0 + m] = rd;
     mnx = fmin(mnx, fmin(ax, bx));
     mxx = fmax(mxx, fmax(ax, bx));
@@ -297,7 +363,7 @@ __global__ __launch_bounds__(256) void k_transform(KArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < CNT_WORDS) a.counters[threadIdx.x] = 0;
   const int sid = blockIdx.x * 4 + wave;
   if (sid >= a.num_shapes) return;
-  transform_item(a, sid, lane, reinterpret_cast<const float4 *>(a.params)[sid]);
+  transform_item(a, sid, lane, reinterpret_cast<const float4 *>(a.params)[sid], transform_preload(a, sid, lane));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -763,7 +829,6 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
                                   src);
     for (int q = tid; q < cnt; q += NT) {
       const int sid = s_list[q];
-      a.item_slot[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = slots + q;
       const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
       const int chunks = (r.n + 63) >> 6;
       {
@@ -806,6 +871,8 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       if (j < slots) {
         a.entry_aux[list_base + j].z = run + x - c;
         a.entry_aux[list_base + j].w = run_cost + y - k;
+        const int sid = a.tile_list[list_base + j];
+        a.item_unit[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = make_int2(c, run + x - c);
       }
       run += __builtin_amdgcn_readlane(x, 63);
       run_cost += __builtin_amdgcn_readlane(y, 63);
@@ -1681,20 +1748,24 @@ __global__ __launch_bounds__(256) void k_vfinal(KArgs a) {
 struct AdamIn {
   float4 p, m, v;
   float rho;
+  float bc1, bc2;  // bias corrections 1 - beta1^t, 1 - beta2^t of the step t (already incremented)
 };
 
-__device__ __forceinline__ AdamIn adam_load(const KArgs &a, int sid) {
+
+// bias: the step's bias corrections (adam_bias_of), computed by the caller or loaded.
+__device__ __forceinline__ AdamIn adam_load(const KArgs &a, int sid, float2 bias) {
   AdamIn r;
   r.p = reinterpret_cast<const float4 *>(a.param_io)[sid];
   r.m = reinterpret_cast<const float4 *>(a.adam_m)[sid];
   r.v = reinterpret_cast<const float4 *>(a.adam_v)[sid];
-  r.rho = a.rho ? a.rho[sid] : 0.0f;
+  r.rho = *(a.rho ? a.rho + sid : &kNoFloat);
+  r.bc1 = bias.x;
+  r.bc2 = bias.y;
   return r;
 }
 
 __device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g, float k, const AdamIn &in) {
-  const float t = (float)a.step[0];
-  const float bc1 = 1.0f - powf(a.beta1, t), bc2 = 1.0f - powf(a.beta2, t);
+  const float bc1 = in.bc1, bc2 = in.bc2;
   const float lr_t = a.lr_px / k;
   const float lr_r = in.rho > 0.0f ? a.lr_px / (k * in.rho) : 0.0f;
   const float gg[4] = {g.x, g.y, g.z, g.w};
@@ -1715,24 +1786,38 @@ __device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g,
   return make_float4(pp[0], pp[1], pp[2], pp[3]);
 }
 
-template <int T>
-__device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
+constexpr int kFinGather = 4;  // rounds of 64 adjoint partials an update wave loads before summing them
+
+// ADAM: update the parameters; XFORM (with ADAM): transform the items with the updated parameters.
+// The loads of the update and of the transform are issued first and consumed last, so that they are in
+// flight while the gradient is gathered.
+// s_map: per wave of the block, T * T entries of LDS for the chunk -> partial map.
+template <int T, bool ADAM, bool XFORM>
+__device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T]) {
+  constexpr bool do_adam = ADAM, do_transform = ADAM && XFORM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sid = blockIdx.x * 4 + wave;
   if (sid >= a.num_shapes) return;
   cptr<ShapeRec> SR = konst(a.shapes);
   cptr<LayoutRec> LS = konst(a.layouts);
-  const int b = SR[sid].layout;
-  const float k = SR[sid].k;
+  const int b = a.num_layouts == 1 ? 0 : uniform(SR[sid].layout);  // scalar: the layout's fields are scalar loads
+  const float k = LS[b].k;
   const int4 bb = load_box(konst(a.bbox), sid);
+  const int bad = a.shapes[sid].bad;  // loaded with the others, consumed by lane 0 at the end
   AdamIn ain;
-  if (do_adam && lane == 0) ain = adam_load(a, sid);
+  // every lane (one request): no branch around the loads
+  if constexpr (do_adam) ain = adam_load(a, sid, make_float2(0.0f, 0.0f));
+  int32_t t_step = 0;
+  if constexpr (do_adam) t_step = uniform(a.step[0]);
+  TransformPre tp;
+  if constexpr (do_transform) tp = transform_preload(a, sid, lane);
   const int ntx = LS[b].ntx, ntiles = ntx * LS[b].nty, nb = LS[b].shape_end - LS[b].shape_begin;
   const int tile_off = LS[b].tile_off;
   const int64_t list_off = LS[b].list_off;
-  const int32_t *slot_of = a.item_slot + list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
+  const int2 *unit_of = a.item_unit + list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
   const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+  long long *map = s_map[wave];
   if (bb.x <= bb.z && bb.y <= bb.w) {
     // every tile that the support box meets lists the item; its units' adjoint partials (one per
     // chunk) are spread over the lanes and summed by a fixed reduction
@@ -1740,45 +1825,37 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
     for (int r0 = 0; r0 < nt; r0 += 64) {
       // up to 64 tiles at a time, one per lane: the unit's chunk count and first partial
-      const int nl = min(nt - r0, 64), j = r0 + lane;
+      const int j = r0 + lane;
       int cnt = 0;
       long long first = 0;
       if (j < nt) {
         const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
-        const int4 ax = a.entry_aux[list_off + (int64_t)lt * nb + slot_of[lt]];
-        cnt = ax.x;
-        first = q0[lt] + ax.z;
+        const int2 u = unit_of[lt];
+        cnt = u.x;
+        first = q0[lt] + u.y;
       }
       const int x = (int)wave_incl_scan_u32((unsigned)cnt);
       const int pre = x - cnt, total = __builtin_amdgcn_readlane(x, 63);
-      // then the chunks of those units, one per lane, all loads in flight together
-      for (int kb = 0; kb < total; kb += 64) {
-        const int kk = kb + lane;
-        // the last tile whose first chunk is <= kk: for a few tiles, the number of later tiles starting
-        // at or before kk (their first chunks read lane by lane into scalar registers); for many, a
-        // binary search over the lanes
-        int lo = 0;
-        if (nl <= 8) {
-          for (int t = 1; t < nl; ++t) lo += __builtin_amdgcn_readlane(pre, t) <= kk ? 1 : 0;
-        } else {
-          int hi = nl - 1;
+      // chunk kk of the batch -> its partial, in the wave's LDS map (a unit has at most T * T / 64
+      // chunks); the wave's LDS operations run in program order, so the reads below see these writes
+      const int nmap = min(total, T * T);
+      for (int c = 0; c < cnt && pre + c < nmap; ++c) map[pre + c] = first + c;
+      // then the chunks, one per lane, kFinGather rounds of 64 with all their loads in flight together
+      // before they are summed (in round order)
+      for (int kb = 0; kb < nmap; kb += 64 * kFinGather) {
+        double4 v[kFinGather];
 #pragma unroll
-          for (int step = 0; step < 6; ++step) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (__shfl(pre, mid, 64) <= kk)
-              lo = mid;
-            else
-              hi = mid - 1;
-          }
+        for (int r = 0; r < kFinGather; ++r) {
+          const int kk = kb + 64 * r + lane;
+          v[r] = make_double4(0.0, 0.0, 0.0, 0.0);
+          if (kk < nmap) v[r] = a.partial[map[kk]];
         }
-        const long long f = __shfl(first, lo, 64);
-        const int pt = __shfl(pre, lo, 64);
-        if (kk < total) {
-          const double4 v = a.partial[f + (kk - pt)];
-          acc.x += v.x;
-          acc.y += v.y;
-          acc.z += v.z;
-          acc.w += v.w;
+#pragma unroll
+        for (int r = 0; r < kFinGather; ++r) {
+          acc.x += v[r].x;
+          acc.y += v[r].y;
+          acc.z += v[r].z;
+          acc.w += v[r].w;
         }
       }
     }
@@ -1792,17 +1869,23 @@ __device__ void finalize_grad(const KArgs &a, bool do_adam, bool do_transform) {
     // the object-space downward force adds d(H - k t_y)/dt_y = -k per unit of its weight
     const double c_od = (double)a.w[8] * (a.dloss ? (double)a.dloss[kLossTerms * b + 8] : 1.0);
     float4 g = make_float4((float)(-(double)k * acc.x), (float)(-(double)k * (acc.y + c_od)), (float)acc.z, (float)acc.w);
-    if (SR[sid].bad != 0) g = make_float4(NAN, NAN, NAN, NAN);
+    if (bad != 0) g = make_float4(NAN, NAN, NAN, NAN);
     if (a.grad_out) reinterpret_cast<float4 *>(a.grad_out)[sid] = g;
-    if (do_adam) pn = adam_update(a, sid, g, k, ain);
+    if constexpr (do_adam) {
+      const float2 bias = adam_bias_of(a, t_step);
+      ain.bc1 = bias.x;
+      ain.bc2 = bias.y;
+      pn = adam_update(a, sid, g, k, ain);
+    }
   }
-  if (do_transform) {
+  if constexpr (do_transform) {
     // the next epoch of the same call starts from the updated parameters: transform them now
     pn.x = __shfl(pn.x, 0, 64);
     pn.y = __shfl(pn.y, 0, 64);
     pn.z = __shfl(pn.z, 0, 64);
     pn.w = __shfl(pn.w, 0, 64);
-    transform_item(a, sid, lane, pn);
+    transform_hold(tp);
+    transform_item(a, sid, lane, pn, tp);
   }
 }
 
@@ -1835,8 +1918,14 @@ __device__ void finalize_loss(const KArgs &a, int b) {
 
 template <int T>
 __global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int flags) {
+  __shared__ long long s_map[4][T * T];
   if ((int)blockIdx.x < grad_blocks) {
-    finalize_grad<T>(a, (flags & 1) != 0, (flags & 4) != 0);
+    if (flags & 4)
+      finalize_grad<T, true, true>(a, s_map);
+    else if (flags & 1)
+      finalize_grad<T, true, false>(a, s_map);
+    else
+      finalize_grad<T, false, false>(a, s_map);
   } else if (flags & 2) {
     finalize_loss(a, blockIdx.x - grad_blocks);
   }
@@ -1863,7 +1952,7 @@ __global__ __launch_bounds__(256) void k_adam(KArgs a) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_shape(LS, a.num_layouts, sid);
   const float4 g = reinterpret_cast<const float4 *>(a.grad_out)[sid];
-  adam_update(a, sid, g, LS[b].k, adam_load(a, sid));
+  adam_update(a, sid, g, LS[b].k, adam_load(a, sid, adam_bias_of(a, a.step[0])));
 }
 
 // ------------------------------------------------------------------------------------------------
