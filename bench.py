@@ -399,7 +399,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "dtype_note": "float32 edge scan; float64 per-(pixel, item) distance, coverage, loss and adjoint",
+        "dtype_note": "float32 edge scan; float64 per-(pixel, item) distance, coverage, loss and adjoint (its logistic-derivative factor in float32)",
         "data": "synthetic",
         "config": {"workload": "512x512 level of the 128-256-512-1024 schedule; 500 closed cubic-Bezier items "
                                "(4-16 segments, 8 points each), 10-ellipse container, padding 2 px, "

@@ -66,7 +66,7 @@ struct alignas(16) EdgeD {
   double inv_ee;        // 1 / |b - a|^2 (0 for a degenerate edge)
   double kra_x, kra_y;  // k R(theta) v_a: the unscaled end point a (its derivative with respect to s)
   double kre_x, kre_y;  // k R(theta) (v_b - v_a)
-  double pad;
+  double inv_len;       // 1 / |b - a| = sqrt(inv_ee) (0 for a degenerate edge): the unit normal's scale
 };
 
 // Work counters at the start of the workspace (zeroed by the transform kernel of every call).

@@ -303,6 +303,7 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     rd.ex = ex;
     rd.ey = ey;
     rd.inv_ee = inv;
+    rd.inv_len = sqrt(inv);
     // d v' / d s = k R(theta) v for both end points (exact also when s = 0)
     rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
     rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
@@ -509,14 +510,18 @@ __device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double 
 
 // omega = G dalpha/dsd + G_pad dalpha_pad/dsd of one (pixel, item), from one exponential: with
 // E = e^-x (x = sd / tau), sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used
-// (x >= -(r_cut + r_pad) / tau).
+// (x >= -(r_cut + r_pad) / tau).  The logistic factor is evaluated in float (relative error a few 1e-7,
+// far below the gradient's tolerance): in double its exponential and two divisions were about 40% of the
+// adjoint's float64 instructions.  Within that range E <= e^((r_cut + max(r_pad, 0)) / tau) and
+// E / (1 + E)^2 <= 1/4, so nothing overflows; deep inside, E underflows to 0 where the double value is
+// below 1e-44.
 __device__ __forceinline__ double adjoint_omega(const KArgs &a, double sd, double G, double Gp) {
   double dal = 0.0, dalp = 0.0;
   if (sd + (double)a.r_pad >= -(double)a.r_cut) {
-    const double E = exp(-sd * a.inv_tau_d), Ep = E * a.pad_factor;
-    const double r = 1.0 / (1.0 + E), rp = 1.0 / (1.0 + Ep);
-    if (sd >= -(double)a.r_cut) dal = E * r * r * a.inv_tau_d;
-    dalp = Ep * rp * rp * a.inv_tau_d;
+    const float E = expf((float)(-sd * a.inv_tau_d)), Ep = E * (float)a.pad_factor;
+    const float r = 1.0f / (1.0f + E), rp = 1.0f / (1.0f + Ep);
+    if (sd >= -(double)a.r_cut) dal = (double)(E * r * r) * a.inv_tau_d;
+    dalp = (double)(Ep * rp * rp) * a.inv_tau_d;
   }
   return G * dal + Gp * dalp;
 }
@@ -528,7 +533,7 @@ __device__ __forceinline__ double adjoint_omega(const KArgs &a, double sd, doubl
 __device__ __forceinline__ void adjoint_normal(const EdgeD &e, const PairD &q, bool par, float orient, bool open,
                                                double &nx, double &ny) {
   if (q.u > 0.0 && q.u < 1.0) {
-    const double il = sqrt(e.inv_ee);
+    const double il = e.inv_len;
     double sg = (double)orient;
     if (q.d >= 1e-4 || open) {
       const double side = q.qy * e.ex - q.qx * e.ey;
