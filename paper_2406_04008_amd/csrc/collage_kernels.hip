@@ -1400,8 +1400,12 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
     const double yinv = (double)u.H - (py + 0.5);
     const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
     const double O = fmin(S, 1.0), Wp = kWmseIn * M + kWmseOut * (1.0 - M);
-    const double cx = (px + 0.5) - 0.5 * u.W, cy = (py + 0.5) - 0.5 * u.H;
-    const double dist = sqrt(cx * cx + cy * cy);
+    // the centre term's distance only when that term is on (a uniform branch)
+    double dist = 0.0;
+    if (a.w[7] != 0.0f) {
+      const double cx = (px + 0.5) - 0.5 * u.W, cy = (py + 0.5) - 0.5 * u.H;
+      dist = sqrt(cx * cx + cy * cy);
+    }
     term[0] += ov * ov;
     term[1] += S * (1.0 - M);
     term[2] += M * (un * un);
