@@ -806,6 +806,9 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64;
   __shared__ int s_list[kMaxBinChunk];
   __shared__ int s_wcnt[NW];
+  // the first kMaxBinChunk units' item, chunks and cost, for the prefix pass below (later units of a
+  // tile that lists more items are read back from global memory)
+  __shared__ int s_usid[kMaxBinChunk], s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
   const int tile = blockIdx.x, tid = threadIdx.x;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_tile(LS, a.num_layouts, tile);
@@ -859,6 +862,11 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       }
       const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
       a.entry_aux[list_base + slots + q] = make_int4(chunks, cpc, 0, 0);
+      if (slots + q < kMaxBinChunk) {
+        s_usid[slots + q] = sid;
+        s_uch[slots + q] = chunks;
+        s_ucost[slots + q] = chunks * cpc;
+      }
       my_cost += (long long)chunks * cpc;
       my_quads += chunks;
     }
@@ -870,13 +878,23 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
     int run = 0, run_cost = 0;
     for (int base = 0; base < slots; base += 64) {
       const int j = base + tid;
-      const int4 ax = j < slots ? a.entry_aux[list_base + j] : make_int4(0, 0, 0, 0);
-      const int c = ax.x, k = ax.x * ax.y;
+      int c = 0, k = 0, sid = 0;
+      if (j < slots) {
+        if (j < kMaxBinChunk) {
+          c = s_uch[j];
+          k = s_ucost[j];
+          sid = s_usid[j];
+        } else {
+          const int4 ax = a.entry_aux[list_base + j];
+          c = ax.x;
+          k = ax.x * ax.y;
+          sid = a.tile_list[list_base + j];
+        }
+      }
       const int x = (int)wave_incl_scan_u32((unsigned)c), y = (int)wave_incl_scan_u32((unsigned)k);
       if (j < slots) {
         a.entry_aux[list_base + j].z = run + x - c;
         a.entry_aux[list_base + j].w = run_cost + y - k;
-        const int sid = a.tile_list[list_base + j];
         a.item_unit[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = make_int2(c, run + x - c);
       }
       run += __builtin_amdgcn_readlane(x, 63);

@@ -89,6 +89,22 @@ def test_backward_parity_autograd(name, tile, oracles):
     check_grad(_np(p.grad), g_ref)
 
 
+def test_tiles_listing_more_units_than_lds_holds():
+    # 1600 small items on a 40 x 40 canvas: the middle 8 x 8 tiles list more than the 1024 units whose
+    # chunks and costs the binning kernel keeps in LDS, so the rest are read back from global memory
+    sc = S.random_scene(11, [(40, 40)], [1600], kinds=("poly", "star"), radius=(0.8, 2.5))
+    _say("many units per tile", sc.num_shapes)
+    cs = CollageScene(sc, tile=8)
+    from oracle.oracle import Oracle as _O
+    o = _O(sc)
+    cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
+    S_, Sp, L = o.forward(sc.params)
+    check_image(_np(cov), S_, "S")
+    check_image(_np(cov_pad), Sp, "S_pad")
+    check_loss(_np(loss), L)
+    check_grad(_np(grad), o.backward(sc.params))
+
+
 @pytest.mark.parametrize("code_capacity,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
 @pytest.mark.parametrize("tile", [16, 8, 32])
 @pytest.mark.parametrize("name", list(SCENES))
