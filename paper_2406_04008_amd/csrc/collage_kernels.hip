@@ -200,6 +200,28 @@ __device__ __forceinline__ int layout_of_tile(cptr<LayoutRec> L, int B, int tile
 // ------------------------------------------------------------------------------------------------
 // k_transform: eq. 2 for every vertex, edge records, support box, orientation.
 // ------------------------------------------------------------------------------------------------
+// Nontemporal (streaming) vector stores for bulk outputs that later kernels read, mostly from other XCDs:
+// the lines leave this XCD's L2 as they are written instead of being written back when the kernel
+// ends (measured: update kernel 8.3 -> 7.5 us, per-pixel pass 6.9 -> 6.1 us, binning 5.5 -> 5.3 us).
+typedef float nt_f32x4 __attribute__((ext_vector_type(4)));
+typedef double nt_f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned long long nt_u64x2 __attribute__((ext_vector_type(2)));
+static_assert(sizeof(EdgeRec) == 2 * sizeof(nt_f32x4) && sizeof(EdgeD) == 5 * sizeof(nt_f64x2), "record sizes");
+
+__device__ __forceinline__ void stream_store(EdgeRec *dst, const EdgeRec &r) {
+  const nt_f32x4 *src = reinterpret_cast<const nt_f32x4 *>(&r);
+  nt_f32x4 *d = reinterpret_cast<nt_f32x4 *>(dst);
+  __builtin_nontemporal_store(src[0], d);
+  __builtin_nontemporal_store(src[1], d + 1);
+}
+
+__device__ __forceinline__ void stream_store(EdgeD *dst, const EdgeD &r) {
+  const nt_f64x2 *src = reinterpret_cast<const nt_f64x2 *>(&r);
+  nt_f64x2 *d = reinterpret_cast<nt_f64x2 *>(dst);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) __builtin_nontemporal_store(src[i], d + i);
+}
+
 __device__ __forceinline__ void place_vertex(double c, double sn, double s, double k, float2 v, double &x, double &y) {
   const double sx = s * (double)v.x, sy = s * (double)v.y;
   x = k * (c * sx - sn * sy);
@@ -296,7 +318,7 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     er.ey = (float)ey;
     er.by = (float)by;  // equals the next edge's ay: the same double rounded the same way
     er.slope = ey != 0.0 ? (float)(ex / ey) : 0.0f;
-    a.edges[v0 + m] = er;
+    stream_store(a.edges + v0 + m, er);
     EdgeD rd;
     rd.ax = ax;
     rd.ay = ay;
@@ -309,7 +331,7 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
     rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
     rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
-    a.edges_d[v0 + m] = rd;
+    stream_store(a.edges_d + v0 + m, rd);
     mnx = fmin(mnx, fmin(ax, bx));
     mxx = fmax(mxx, fmax(ax, bx));
     mny = fmin(mny, fmin(ay, by));
@@ -822,8 +844,7 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
     const int pxi = x0 + q % T, pyi = y0 + q / T;
     if (pxi < W && pyi < H) {
       const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
-      a.acc[2 * pix] = 0ull;
-      a.acc[2 * pix + 1] = 0ull;
+      __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
     }
   }
   int slots = 0;
@@ -1436,7 +1457,7 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
       if (S < 1.0) G -= 2.0 * c_w * (Wp * (M - S));
       G += c_cen * dist;
       const double Gp = 2.0 * c_p * pv;
-      a.gbuf[pix[k]] = make_double2(G, Gp);
+      __builtin_nontemporal_store((nt_f64x2){G, Gp}, reinterpret_cast<nt_f64x2 *>(a.gbuf + pix[k]));
     }
   }
   if (UNI) {
