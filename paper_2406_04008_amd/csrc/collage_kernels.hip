@@ -9,7 +9,8 @@
 //   k_bin        one workgroup per screen tile: the layout's items whose support box meets the tile,
 //                in item order; each (tile, item) is a work unit, the box clipped to the tile, packed
 //                row by row into 64-pixel chunks.  Clears the tile's coverage accumulators.
-//   k_scan       one workgroup: prefix sums of the tiles' work costs and chunk counts.
+//   k_scan       one workgroup: prefix sums of the tiles' work costs and chunk counts (up to
+//                kScanInCoverTiles tiles every coverage workgroup computes them itself instead).
 //   k_cover      persistent waves, each taking an equal share of the pass's cost (split at chunk
 //                granularity); per unit the wave stages the item's edge records in LDS, and per chunk
 //                every lane scans them in float32 for its pixel's nearest edge and crossing parity,
@@ -30,7 +31,8 @@
 //   k_finalize   one wave per item sums its units' partials in a fixed order (gradient, then the
 //                optional Adam update and the next epoch's transform); one workgroup per layout sums
 //                the loss blocks in a fixed order.
-// Results are bitwise reproducible.
+// Bulk outputs that later kernels read are written with nontemporal stores.  Results are bitwise
+// reproducible.
 #include "collage_internal.h"
 
 #include <hip/hip_ext.h>
@@ -633,14 +635,14 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
 
 // Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  A unit
 // covers the rectangle where the item's support box meets the tile, packed row by row into chunks of
-// 64 pixels (one pixel per lane).  A chunk costs (edges + kEpilogueCost) in the coverage pass and 1 in
-// the adjoint pass.  Chunks are numbered through the whole pass in unit order (the same numbering in
+// 64 pixels (one pixel per lane).  A chunk costs (edges + kEpilogueCost + its share of kUnitCost) in the
+// coverage pass and 1 in the adjoint pass.  Chunks are numbered through the whole pass in unit order (the same numbering in
 // both passes: it indexes the nearest-edge codes kept between them and the adjoint partials).
 //
 // The persistent wave w of W processes the chunks whose cost interval [p, p + c) ends in
 // (B_w, B_{w+1}], where B_w = ceil(w * total / W) and p is the chunk's cost prefix.  It finds the tile
-// holding B_w by binary search over the tile prefix sums and walks from there; a unit may be split
-// between consecutive waves.  Every wave gets the same work to within one chunk, and no counter is
+// holding B_w, then the unit within it, by 64-way searches over their prefix sums (one probe per lane
+// and round) and walks from there; a unit may be split between consecutive waves.  Every wave gets the same work to within one chunk, and no counter is
 // shared between waves.
 struct Walk {
   int tile, slot, count;   // current unit = slot `slot` of tile `tile` (which has `count` units)
