@@ -99,11 +99,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cover_512px_500items_traffic.md
 
 
 def kernel_digest() -> str:
-    """Digest of the kernel sources: a traffic figure measured on other sources is not reported."""
+    """Digest of the kernel sources without their // comments and blank lines: a traffic figure measured
+    on other code is not reported (an edit of the comments alone keeps it)."""
     h = hashlib.sha256()
     for name in ("collage_kernels.hip", "collage_internal.h"):
-        with open(os.path.join(ROOT, "paper_2406_04008_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2406_04008_amd", "csrc", name), encoding="utf-8") as f:
+            for line in f:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
