@@ -1440,10 +1440,11 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
     if (a.cov_pad_out) a.cov_pad_out[pix[k]] = (float)Sp;
     const double yinv = (double)u.H - (py + 0.5);
     const double ov = fmax(S - 1.0, 0.0), un = fmax(1.0 - S, 0.0), pv = fmax(Sp - 1.0, 0.0);
+    // the terms that a scene leaves at weight 0 (uniform branches) are neither summed nor differentiated
+    const bool on_w = a.w[6] != 0.0f, on_cen = a.w[7] != 0.0f;
     const double O = fmin(S, 1.0), Wp = kWmseIn * M + kWmseOut * (1.0 - M);
-    // the centre term's distance only when that term is on (a uniform branch)
     double dist = 0.0;
-    if (a.w[7] != 0.0f) {
+    if (on_cen) {
       const double cx = (px + 0.5) - 0.5 * u.W, cy = (py + 0.5) - 0.5 * u.H;
       dist = sqrt(cx * cx + cy * cy);
     }
@@ -1452,12 +1453,12 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
     term[2] += M * (un * un);
     term[3] += pv * pv;
     term[4] += S * yinv;
-    term[6] += Wp * ((M - O) * (M - O));
-    term[7] += S * dist;
+    if (on_w) term[6] += Wp * ((M - O) * (M - O));
+    if (on_cen) term[7] += S * dist;
     if (GRAD) {
       double G = 2.0 * c_ov * ov + c_c * (1.0 - M) - 2.0 * c_f * (M * un) + c_d * yinv;
-      if (S < 1.0) G -= 2.0 * c_w * (Wp * (M - S));
-      G += c_cen * dist;
+      if (on_w && S < 1.0) G -= 2.0 * c_w * (Wp * (M - S));
+      if (on_cen) G += c_cen * dist;
       const double Gp = 2.0 * c_p * pv;
       __builtin_nontemporal_store((nt_f64x2){G, Gp}, reinterpret_cast<nt_f64x2 *>(a.gbuf + pix[k]));
     }
