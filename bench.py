@@ -297,7 +297,7 @@ def main():
                     help="after the timed region, copy 256 MiB device to device (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the collage path has no multi-GPU form",
               file=sys.stderr)
         sys.exit(2)
     if not (1 <= args.steps <= 4096 and 0 <= args.warmup <= 4096):

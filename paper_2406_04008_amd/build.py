@@ -17,8 +17,8 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # keep every float operation as written: the distance of the coverage pass and of the adjoint
-    # pass must round identically, and the loss sums are compensated by hand
+    # keep every float operation as written: the scan and the re-decision of the nearest edge must
+    # round identically, and every sum runs in a fixed order
     "-ffp-contract=off",
     # no packed FP32 instructions (they are not used by this code and are excluded on purpose)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

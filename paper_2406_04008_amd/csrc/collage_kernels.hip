@@ -636,14 +636,15 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
 // Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  A unit
 // covers the rectangle where the item's support box meets the tile, packed row by row into chunks of
 // 64 pixels (one pixel per lane).  A chunk costs (edges + kEpilogueCost + its share of kUnitCost) in the
-// coverage pass and 1 in the adjoint pass.  Chunks are numbered through the whole pass in unit order (the same numbering in
-// both passes: it indexes the nearest-edge codes kept between them and the adjoint partials).
+// coverage pass and 1 in the adjoint pass.  Chunks are numbered through the whole pass in unit order
+// (the same numbering in both passes: it indexes the nearest-edge codes kept between them and the
+// adjoint partials).
 //
 // The persistent wave w of W processes the chunks whose cost interval [p, p + c) ends in
 // (B_w, B_{w+1}], where B_w = ceil(w * total / W) and p is the chunk's cost prefix.  It finds the tile
 // holding B_w, then the unit within it, by 64-way searches over their prefix sums (one probe per lane
-// and round) and walks from there; a unit may be split between consecutive waves.  Every wave gets the same work to within one chunk, and no counter is
-// shared between waves.
+// and step) and walks from there; a unit may be split between consecutive waves.  Every wave gets the
+// same work to within one chunk, and no counter is shared between waves.
 struct Walk {
   int tile, slot, count;   // current unit = slot `slot` of tile `tile` (which has `count` units)
   int W, x0, y0;           // canvas width and origin of the tile
