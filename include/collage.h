@@ -51,7 +51,8 @@
  *   - Results are deterministic: the same inputs give bitwise the same outputs on the same device.
  *   - Precision: the nearest edge of every (pixel, item) is found by a float32 scan of the item's
  *     edges; the signed distance to that edge, the coverage, the loss sums and the gradient terms
- *     are then evaluated in double precision and returned as float32.
+ *     are then evaluated in double precision (the gradient's logistic factor sigma'(sd / tau) / tau
+ *     in float32, a relative error of a few 1e-7) and returned as float32.
  */
 #ifndef COLLAGE_H_
 #define COLLAGE_H_
