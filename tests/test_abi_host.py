@@ -95,6 +95,20 @@ def test_offsets_validation():
     assert lib.collage_scene_create(None, ctypes.byref(out)) == _lib.ERR_INVALID
 
 
+def test_timer_argument_errors():
+    # checked on the host before any HIP call
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    assert lib.collage_timer_create(0, ctypes.byref(out)) == _lib.ERR_INVALID
+    assert lib.collage_timer_create(65537, ctypes.byref(out)) == _lib.ERR_INVALID
+    assert lib.collage_timer_create(4, None) == _lib.ERR_INVALID
+    ms = (ctypes.c_float * 4)()
+    assert lib.collage_timer_elapsed(None, ms) == _lib.ERR_INVALID
+    lib.collage_timer_destroy(None)  # a no-op
+    assert lib.collage_iterate_n(None, None, None, None, None, None, None, None, None, 0.5, 0.9, 0.999, 1e-8,
+                                 None, 0, 1, None, None) == _lib.ERR_INVALID
+
+
 def test_null_scene_calls_fail_cleanly():
     lib = _lib.load()
     nb = ctypes.c_size_t()
