@@ -151,7 +151,8 @@ def coarse_to_fine(sc):
 def batched_vs_loop(steps):
     """64 independent layouts (sides 128..512, 20..400 items) at full resolution: one batched scene (every
     kernel launched once per epoch over all layouts) against a loop over 64 one-layout scenes on the same
-    stream, same epochs from the same start.  Per-layout results are bitwise identical in the two forms."""
+    stream, same epochs from the same start, each scene's epochs in one multi-epoch call.  Per-layout
+    results are bitwise identical in the two forms."""
     import torch
 
     from paper_2406_04008_amd import _lib, autotune, scenes
@@ -173,9 +174,8 @@ def batched_vs_loop(steps):
         e1 = torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(stream):
             e0.record(stream)
-            for _ in range(reps):
-                for c, p, m, v, st, loss, grad in state:
-                    c.iterate(p, m, v, st, loss=loss, grad=grad)
+            for c, p, m, v, st, loss, grad in state:
+                c.iterate_n(p, m, v, st, reps, loss=loss, grad=grad, stream=stream)
             e1.record(stream)
         stream.synchronize()
         return e0.elapsed_time(e1), torch.cat([s_[1] for s_ in state]).cpu().numpy()
