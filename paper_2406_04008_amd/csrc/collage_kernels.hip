@@ -28,7 +28,7 @@
 //   k_vgrad,     (outline-vertex gradients only) the adjoint's walk once more, adding each pixel's
 //   k_vfinal     d sd / d(end points of its nearest edge) into per-vertex fixed-point sums, then back
 //                through eq. 2 per vertex.
-//   k_finalize   one wave per item sums its units' partials in a fixed order (gradient, then the
+//   k_finalize   one wave per item (two or four items per workgroup) sums its units' partials in a fixed order (gradient, then the
 //                optional Adam update and the next epoch's transform); one workgroup per layout sums
 //                the loss blocks in a fixed order.
 // Bulk outputs that later kernels read are written with nontemporal stores.  Results are bitwise
@@ -1859,12 +1859,14 @@ constexpr int kFinGather = 4;  // rounds of 64 adjoint partials an update wave l
 // ADAM: update the parameters; XFORM (with ADAM): transform the items with the updated parameters.
 // The loads of the update and of the transform are issued first and consumed last, so that they are in
 // flight while the gradient is gathered.
-// s_map: per wave of the block, T * T entries of LDS for the chunk -> partial map.
+// s_map: per wave of the block, T * T entries of LDS for the chunk -> partial map.  per: items per
+// workgroup (its first per waves take one each).
 template <int T, bool ADAM, bool XFORM>
-__device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T]) {
+__device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T], int per) {
   constexpr bool do_adam = ADAM, do_transform = ADAM && XFORM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int sid = blockIdx.x * 4 + wave;
+  if (wave >= per) return;
+  const int sid = blockIdx.x * per + wave;
   if (sid >= a.num_shapes) return;
   cptr<ShapeRec> SR = konst(a.shapes);
   cptr<LayoutRec> LS = konst(a.layouts);
@@ -1985,15 +1987,15 @@ __device__ void finalize_loss(const KArgs &a, int b) {
 }
 
 template <int T>
-__global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int flags) {
+__global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int flags, int per) {
   __shared__ long long s_map[4][T * T];
   if ((int)blockIdx.x < grad_blocks) {
     if (flags & 4)
-      finalize_grad<T, true, true>(a, s_map);
+      finalize_grad<T, true, true>(a, s_map, per);
     else if (flags & 1)
-      finalize_grad<T, true, false>(a, s_map);
+      finalize_grad<T, true, false>(a, s_map, per);
     else
-      finalize_grad<T, false, false>(a, s_map);
+      finalize_grad<T, false, false>(a, s_map, per);
   } else if (flags & 2) {
     finalize_loss(a, blockIdx.x - grad_blocks);
   }
@@ -2143,11 +2145,14 @@ hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
 
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
                            bool do_transform) {
-  const int gb = do_grad ? (a.num_shapes + 3) / 4 : 0;
+  // each item's gradient is a short chain of dependent loads: with fewer than 2048 items, two items
+  // per workgroup spread the chains over twice the compute units
+  const int per = a.num_shapes >= 2048 ? 4 : 2;
+  const int gb = do_grad ? (a.num_shapes + per - 1) / per : 0;
   const int lb = do_loss ? a.num_layouts : 0;
   if (gb + lb == 0) return hipSuccess;
   const int flags = (do_adam ? 1 : 0) | (do_loss ? 2 : 0) | (do_adam && do_transform ? 4 : 0);
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, flags));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, flags, per));
   return hipGetLastError();
 }
 
