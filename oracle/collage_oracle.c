@@ -718,6 +718,56 @@ int oracle_collage_lr(const oracle_scene *sc, const double *rho, double lr_px, d
   return 0;
 }
 
+/*
+ * Quality metrics of Sec. 6 ("Metrics of Collage Quality"), on hard rasters: pixel p is covered by
+ * item i when sd_i(p) >= 0, and lies in the target shape when M(p) >= 1/2.  Per layout b, with T the
+ * number of target pixels,
+ *   out[3 b + 0]  LC = (covered pixels in the target) / T             (layout coverage)
+ *   out[3 b + 1]  OO = (pixels covered by two or more items) / T      (object overlap)
+ *   out[3 b + 2]  EA = (covered pixels outside the target) / T        (exceeding area)
+ * (all 0 for a layout without target pixels).  counts (may be NULL) receives per layout
+ * [4 b + 0..3] = T, covered in the target, overlap pixels, covered outside the target.
+ * Test tooling: the metrics of a finished layout.
+ */
+int oracle_quality(const oracle_scene *sc, const double *params, double *out, int64_t *counts) {
+  if (!sc || !params || !out) return -1;
+  if (sc->use_bbox && !sc->use_cutoff) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  for (int b = 0; b < sc->B; ++b) {
+    const int W = sc->width[b], H = sc->height[b];
+    const int64_t off = pixel_offset(sc, b);
+    int64_t target = 0, in_cov = 0, overlap = 0, out_cov = 0;
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < W; ++i) {
+        int n_cov = 0;
+        for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) {
+          const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+          if (n == 0 || !in_box(pr.box + 4 * q, i, j)) continue;
+          const sd_result r = item_distance(sc, params, q, sc->scale[b], i + 0.5, j + 0.5, pr.P + 2 * sc->vert_off[q], n);
+          if (r.sd >= 0.0) ++n_cov;
+        }
+        const int in_target = sc->mask ? sc->mask[off + (int64_t)j * W + i] >= 0.5 : 0;
+        target += in_target;
+        if (n_cov >= 1 && in_target) ++in_cov;
+        if (n_cov >= 1 && !in_target) ++out_cov;
+        if (n_cov >= 2) ++overlap;
+      }
+    const double T = (double)target;
+    out[3 * b + 0] = target > 0 ? (double)in_cov / T : 0.0;
+    out[3 * b + 1] = target > 0 ? (double)overlap / T : 0.0;
+    out[3 * b + 2] = target > 0 ? (double)out_cov / T : 0.0;
+    if (counts) {
+      counts[4 * b + 0] = target;
+      counts[4 * b + 1] = in_cov;
+      counts[4 * b + 2] = overlap;
+      counts[4 * b + 3] = out_cov;
+    }
+  }
+  release(&pr);
+  return 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -61,6 +61,7 @@ def lib():
         L.oracle_adam.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
         L.oracle_collage_lr.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_double, _dp]
+        L.oracle_quality.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         _LIB = L
@@ -226,6 +227,17 @@ class Oracle:
                 pm[q, c] -= hs[c]
                 g[q, c] = (self.loss(pp, dloss) - self.loss(pm, dloss)) / (2 * hs[c])
         return g
+
+    def quality(self, params):
+        """Sec. 6 metrics per layout on hard rasters (sd >= 0 covers a pixel, M >= 1/2 is the target):
+        (metrics [B, 3] = LC, OO, EA;  counts [B, 4] = target, covered in target, overlap, covered outside)."""
+        p = _d(params).reshape(-1)
+        B = self.scene.num_layouts
+        out = np.zeros(3 * B)
+        cnt = np.zeros(4 * B, np.int64)
+        rc = lib().oracle_quality(ctypes.byref(self._s), _ptr(p), _ptr(out), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        assert rc == 0
+        return out.reshape(B, 3), cnt.reshape(B, 4)
 
     def _layout_of(self, q):
         return int(np.searchsorted(self.shape_off, q, side="right") - 1)

@@ -580,3 +580,194 @@ def test_vertex_gradient_sums_to_the_parameter_gradient():
         assert np.allclose(R @ gm.sum(0) / s, g[q, :2], rtol=0, atol=1e-9 * scale)
         assert abs((vm[:, 0] * gm[:, 1] - vm[:, 1] * gm[:, 0]).sum() - g[q, 2]) <= 1e-9 * scale
         assert abs((vm * gm).sum() / s - g[q, 3]) <= 1e-9 * scale
+
+
+# --------------------------------------------------------------------------------------------------
+# The update of eq. 4 at a level with k != 1: learning rates in level pixels (large coarse steps)
+# --------------------------------------------------------------------------------------------------
+def _eq2_vertices(sc, p, k):
+    """Transformed vertices of every item, level px (eq. 2 with a uniform scale), for the pin below."""
+    out = []
+    V = sc.verts.astype(np.float64)
+    for q in range(sc.num_shapes):
+        a, b = sc.vert_off[q], sc.vert_off[q + 1]
+        c, s_ = math.cos(p[q, 2]), math.sin(p[q, 2])
+        R = np.array([[c, -s_], [s_, c]])
+        out.append(k * (p[q, 3] * V[a:b] @ R.T + p[q, :2]))
+    return out
+
+
+@pytest.mark.parametrize("level", [128, 256, 1024])
+def test_first_adam_step_moves_every_item_by_lr_px_level_pixels(level):
+    """Adam's first step is lr sign(g) (to eps / |g|).  With the learning rates read in level pixels,
+    one step at a level of scale k != 1 moves every item's origin by exactly lr_px level px per axis,
+    and its rim point (the vertex at radius rho) by lr_px level px along its arc under theta alone and
+    along its ray under s alone, whatever k and rho are.  Learning rates of lr_px * k or lr_px / rho
+    without k fail this at every level here."""
+    sc = S.config3(0)
+    o = Oracle(sc, level=level)
+    k = level / sc.level_ref
+    assert k != 1.0
+    lr_px = sc.lr_px
+    rng = np.random.default_rng(level)
+    p0 = sc.params.astype(np.float64)
+    g = rng.choice([-1.0, 1.0], p0.shape) * rng.uniform(1.0, 10.0, p0.shape)
+    z = np.zeros_like(p0)
+    p1, _, _ = o.adam(p0, g, z, z, 1, o.learning_rates(lr_px))
+    before = _eq2_vertices(sc, p0, k)
+    rim = [int(np.argmax(np.hypot(*sc.verts[sc.vert_off[q]:sc.vert_off[q + 1]].astype(np.float64).T)))
+           for q in range(sc.num_shapes)]
+    # translation alone: every vertex (and the origin) moves by lr_px level px per axis
+    pt = p0.copy()
+    pt[:, :2] = p1[:, :2]
+    for q, (va, vb) in enumerate(zip(before, _eq2_vertices(sc, pt, k))):
+        np.testing.assert_allclose(np.abs(vb - va), lr_px, rtol=1e-6)
+        assert np.all(np.sign(vb - va)[0] == -np.sign(g[q, :2]))
+    # rotation alone: the rim point travels lr_px level px along its circle about the origin k t
+    pr = p0.copy()
+    pr[:, 2] = p1[:, 2]
+    for q, (va, vb) in enumerate(zip(before, _eq2_vertices(sc, pr, k))):
+        ra, rb = va[rim[q]] - k * p0[q, :2], vb[rim[q]] - k * p0[q, :2]
+        turn = math.atan2(ra[0] * rb[1] - ra[1] * rb[0], ra @ rb)
+        assert abs(abs(turn) * np.hypot(*ra) - lr_px) < 1e-6 * lr_px, (q, turn, np.hypot(*ra))
+    # scale alone: the rim point moves lr_px level px along its ray
+    ps = p0.copy()
+    ps[:, 3] = p1[:, 3]
+    for q, (va, vb) in enumerate(zip(before, _eq2_vertices(sc, ps, k))):
+        assert abs(np.hypot(*(vb[rim[q]] - va[rim[q]])) - lr_px) < 1e-6 * lr_px
+
+
+# --------------------------------------------------------------------------------------------------
+# Open items of several segments: no closing segment, right-angle joins
+# --------------------------------------------------------------------------------------------------
+U_SIDE = 24.0
+
+
+def _u_scene(w, theta, s=1.0, c=(31.37, 30.81), size=64):
+    """A U: three segments of length U_SIDE with two right-angle joins; the mouth is open."""
+    U = np.array([[0.0, U_SIDE], [0.0, 0.0], [U_SIDE, 0.0], [U_SIDE, U_SIDE]])
+    return S.multi_shape_scene([U], np.array([[c[0], c[1], theta, s]]), size, size, stroke=[w],
+                               w_overlap=0, w_contain=1, w_fill=0)
+
+
+def test_open_polyline_distance_in_the_mouth_of_a_u():
+    """Inside the U's mouth (item frame, arms at x = -/+ s a, base at y = -s a, mouth at y = +s a, with
+    a = U_SIDE / 2) the distance to the polyline is min(x + s a, s a - x, y + s a): the open side is no
+    segment.  A closing segment from the last vertex to the first would cap it by s a - y."""
+    w, th, s = 1.3, 0.41, 1.1
+    sc = _u_scene(w, th, s)
+    sd = Oracle(sc).signed_distance(sc.params)[0].reshape(64, 64)
+    t = sc.params[0].astype(np.float64)
+    j, i = np.mgrid[0:64, 0:64]
+    dx, dy = i + 0.5 - t[0], j + 0.5 - t[1]
+    xr = math.cos(t[2]) * dx + math.sin(t[2]) * dy
+    yr = -math.sin(t[2]) * dx + math.cos(t[2]) * dy
+    s = t[3]  # the scene's float32 values
+    a = s * float(sc.verts[3, 0])
+    assert float(sc.verts[3, 0]) == -float(sc.verts[0, 0]) == float(sc.verts[0, 1]) == -float(sc.verts[1, 1])
+    mouth = (np.abs(xr) < a) & (yr > -a) & (yr < a)
+    ref = s * float(sc.stroke[0]) - np.minimum(np.minimum(xr + a, a - xr), yr + a)
+    assert mouth.sum() > 300
+    assert np.abs(sd[mouth] - ref[mouth]).max() < 1e-9
+    # the pixels nearest the mouth line are far from any segment (a closing segment would be within 1 px)
+    near_mouth = mouth & (yr > a - 1.0) & (np.abs(xr) < a / 2)
+    assert near_mouth.sum() > 5 and np.all(sd[near_mouth] < -(a / 2 - 2.0))
+
+
+def test_open_polyline_u_area_closed_form():
+    """sum_p alpha of a stroked U by the coarea formula: the level set at distance x outside is the
+    boundary of the U stroked to half-width w + x, at depth x < w inside that of half-width w - x, and
+    a U stroked to half-width y (no merging of the arms, y < U_SIDE / 2) has the area
+        A(y) = 2 y (3 L) + pi y^2 - 2 y^2 (1 - pi / 4)
+    (three rectangles, two end caps, and per right-angle join a quarter disk outside minus a y x y
+    square counted twice inside), so the perimeter A'(y).  The expected sum is
+        A(w) + int_0^r_cut sigma(-x / tau) A'(w + x) dx - int_0^w sigma(-x / tau) A'(w - x) dx,
+    by 1-D quadrature.  A closing segment adds 2 w L = 120 px^2."""
+    w, L = 2.5, U_SIDE
+    assert w + R_CUT < L / 2
+
+    def A(y):
+        return 2 * y * 3 * L + math.pi * y * y - 2 * y * y * (1 - math.pi / 4)
+
+    def Ap(y):
+        return 6 * L + 2 * math.pi * y - 4 * y * (1 - math.pi / 4)
+
+    out, _ = integrate.quad(lambda x: _sigmoid(-x / TAU) * Ap(w + x), 0.0, R_CUT, epsabs=1e-12, limit=200)
+    inn, _ = integrate.quad(lambda x: _sigmoid(-x / TAU) * Ap(w - x), 0.0, w, epsabs=1e-12, limit=200)
+    expect = A(w) + out - inn
+
+    def f(c):
+        sc = _u_scene(w, 0.29, 1.0, c=c)
+        return Oracle(sc).forward(sc.params)[2][0, 1]
+
+    val = _offset_average(f, (31.9, 31.3))
+    assert abs(val - expect) < 2e-3 * Ap(w), (val, expect)
+
+
+# --------------------------------------------------------------------------------------------------
+# Quality metrics of Sec. 6 on hard rasters (test tooling): pixel counts of axis-aligned rectangles
+# --------------------------------------------------------------------------------------------------
+def _centres_in(lo, hi):
+    """Number of pixel centres i + 1/2 in [lo, hi] (generic end points: none on a centre)."""
+    return max(0, math.floor(hi - 0.5) - math.ceil(lo - 0.5) + 1)
+
+
+def test_quality_metrics_count_pixels_of_rectangles():
+    """Target: an axis-aligned rectangle container; items: three axis-aligned rectangles, two of them
+    overlapping and one reaching out of the container.  LC, OO and EA are ratios of pixel-centre
+    counts of intervals, which are exact integers here."""
+    W, H = 60, 50
+    box = (30.3, 24.7, 21.2, 17.9)  # container centre and half-sides
+    rects = [((20.2, 20.6), (6.3, 4.1)), ((27.1, 23.3), (5.2, 7.7)), ((47.6, 38.4), (6.9, 5.3))]
+    outlines = [S.rectangle(hw, hh) for _, (hw, hh) in rects]
+    params = np.array([[c[0], c[1], 0.0, 1.0] for c, _ in rects])
+    lay = S.Layout(W, H, 0, 3, rects=np.array([[box[0], box[1], box[2], box[3], 0.0]]))
+    sc = S.assemble("quality", outlines, params, [lay], [1], 1)
+    # the values the oracle sees (float32 storage)
+    P = sc.params.astype(np.float64)
+    half = [np.abs(sc.verts[sc.vert_off[q]:sc.vert_off[q + 1]].astype(np.float64)).max(0) for q in range(3)]
+    ivx = [(P[q, 0] - half[q][0], P[q, 0] + half[q][0]) for q in range(3)]
+    ivy = [(P[q, 1] - half[q][1], P[q, 1] + half[q][1]) for q in range(3)]
+    bx, by = (box[0] - box[2], box[0] + box[2]), (box[1] - box[3], box[1] + box[3])
+
+    def cnt(x, y):
+        return _centres_in(*x) * _centres_in(*y)
+
+    def cap(u, v):
+        return (max(u[0], v[0]), min(u[1], v[1]))
+
+    target = cnt(bx, by)
+    # pixels of each item, of the overlap of items 0 and 1, and of each item inside the container
+    n = [cnt(ivx[q], ivy[q]) for q in range(3)]
+    ov = cnt(cap(ivx[0], ivx[1]), cap(ivy[0], ivy[1]))
+    inside = [cnt(cap(ivx[q], bx), cap(ivy[q], by)) for q in range(3)]
+    ov_in = cnt(cap(cap(ivx[0], ivx[1]), bx), cap(cap(ivy[0], ivy[1]), by))
+    assert ov > 0 and n[2] > inside[2] > 0 and cnt(cap(ivx[2], ivx[1]), cap(ivy[2], ivy[1])) == 0
+    covered_in = sum(inside) - ov_in
+    covered_out = sum(n) - ov - covered_in
+    m, c = Oracle(sc).quality(sc.params)
+    assert list(c[0]) == [target, covered_in, ov, covered_out]
+    np.testing.assert_allclose(m[0], [covered_in / target, ov / target, covered_out / target], rtol=1e-15)
+
+
+# --------------------------------------------------------------------------------------------------
+# The workload with 8 items on 64 x 64: 200 Adam steps of the oracle end in a packed layout
+# --------------------------------------------------------------------------------------------------
+def test_config1_two_hundred_adam_steps_reach_a_packed_layout():
+    """Sec. 4 (Fig. 2): 200 epochs of forward, backward and the update.  Layouts are local minima,
+    not unique, so the end state is checked by bands of the Sec. 6 metrics: the loss falls by more
+    than 5x, the items cover over 80% of the disk, and overlap and excess stay under 5% of it.  (The
+    seed-0 start covers 17%.)"""
+    sc = S.config1(0)
+    o = Oracle(sc)
+    p = sc.params.astype(np.float64)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    lr = o.learning_rates()
+    L0 = o.loss(p)
+    q0, _ = o.quality(p)
+    for t in range(1, 201):
+        p, m, v = o.adam(p, o.backward(p), m, v, t, lr)
+    L1 = o.loss(p)
+    q1, _ = o.quality(p)
+    assert L1 < L0 / 5, (L0, L1)
+    assert q0[0, 0] < 0.3 and q1[0, 0] > 0.8 and q1[0, 1] < 0.05 and q1[0, 2] < 0.05, (q0, q1)
