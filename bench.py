@@ -31,9 +31,11 @@ METRIC = "fwd+bwd collage iterations/sec and pixel·edge evals/s at 512², 500 s
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 vector lane-operations per second
 # (float32 without packed instructions; an FMA counts as one operation)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# algorithmic lane-operations per (pixel, edge) of one nearest-edge scan with index tracking:
-# distance 11 (2 sub, mul+fma, mul, clamp, 2 fma, mul+fma, min), crossing 6, argmin tracking 3
-OPS_PER_PAIR = 20
+# algorithmic lane-operations per (pixel, edge) of the forward scan: distance 11 (2 sub, mul+fma, mul,
+# clamp, 2 fma, mul+fma, min) and crossing 6 (2 cmp, xor, fma, cmp, and/xor); tracking which edge holds
+# the minimum adds 3 more, reported beside the roofline fraction but not counted in it
+FWD_OPS_PER_PAIR = 17
+ARGMIN_OPS_PER_PAIR = 3
 # the timed region stamps the coverage launch of every TIMER_STRIDE-th epoch with a HIP event pair
 TIMER_STRIDE = 8
 
@@ -67,14 +69,12 @@ def support_pairs(scene, params, level):
     return int(n.sum())
 
 
-def cpu_baseline(scene, level, budget_s=22.0, max_iters=2000):
-    """The FP64 oracle (forward, backward, Adam) on the same scene, timed on this host's cores."""
+def cpu_baseline(scene, level, budget_s=14.0, budget_1core_s=10.0, max_iters=2000):
+    """The FP64 oracle (forward, backward, Adam) on the same scene from the seed-0 layout, timed on all of
+    this host's cores and then on one core."""
     from oracle import oracle as orc
 
     o = orc.Oracle(scene, level=level)
-    p = scene.params.astype(np.float64)
-    m = np.zeros_like(p)
-    v = np.zeros_like(p)
     lr = o.learning_rates()
 
     def one(t, p, m, v):
@@ -82,17 +82,31 @@ def cpu_baseline(scene, level, budget_s=22.0, max_iters=2000):
         g = o.backward(p)
         return o.adam(p, g, m, v, t, lr)
 
-    t0 = time.perf_counter()
-    p, m, v = one(1, p, m, v)  # warm-up
-    first = time.perf_counter() - t0
-    n = int(max(2, min(max_iters, budget_s / max(first, 1e-3))))
-    t0 = time.perf_counter()
-    for t in range(2, n + 2):
-        p, m, v = one(t, p, m, v)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "it/s", "cores": orc.num_threads(), "kind": "oracle",
+    def timed(budget):
+        p = scene.params.astype(np.float64)
+        m = np.zeros_like(p)
+        v = np.zeros_like(p)
+        t0 = time.perf_counter()
+        p, m, v = one(1, p, m, v)  # warm-up
+        first = time.perf_counter() - t0
+        n = int(max(2, min(max_iters, budget / max(first, 1e-3))))
+        t0 = time.perf_counter()
+        for t in range(2, n + 2):
+            p, m, v = one(t, p, m, v)
+        return n, time.perf_counter() - t0
+
+    cores = orc.num_threads()
+    n, dt = timed(budget_s)
+    orc.set_threads(1)
+    try:
+        n1, dt1 = timed(budget_1core_s)
+    finally:
+        orc.set_threads(cores)
+    return {"value": n / dt, "unit": "it/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} oracle epochs (forward, backward, Adam; FP64) of the same 512x512 / 500-item "
-                      f"scene from the seed-0 layout, {dt:.1f} s"}
+                      f"scene from the seed-0 layout on {cores} threads, {dt:.1f} s; then {n1} epochs on 1 "
+                      f"thread, {dt1:.1f} s",
+            "value_1core": n1 / dt1, "speedup_all_cores": (n / dt) / (n1 / dt1)}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cover_512px_500items_traffic.md")
@@ -125,9 +139,26 @@ def measured_traffic(tile: int):
         return None
 
 
-def coarse_to_fine(sc):
+def scans_per_epoch(status):
+    """Scans of the edges per epoch from the status words of the call's last epoch: the coverage pass
+    scans every chunk once, and the adjoint scans again the chunks beyond the code capacity."""
+    from paper_2406_04008_amd import _lib
+
+    chunks = int(status[_lib.STATUS_CHUNKS])
+    return 1.0 + (int(status[_lib.STATUS_RESCANNED]) / chunks if chunks > 0 else 0.0)
+
+
+def implied_valu_frac(evals_per_s):
+    """The fraction of the VALU peak that `evals_per_s` pixel-edge evaluations would need at the forward
+    scan's algorithmic operation count: a figure above 1 cannot have been measured."""
+    return FWD_OPS_PER_PAIR * evals_per_s / PEAK_LANE_OPS
+
+
+def coarse_to_fine(sc, sample_every=10):
     """The whole coarse-to-fine schedule of a scene (300 epochs per level), one captured hipGraph per
-    level, launch configurations autotuned per level."""
+    level, launch configurations autotuned per level.  The pixel-edge figures count the pairs of the
+    parameters the epochs actually scanned: the schedule is replayed eagerly (bitwise the same epochs)
+    keeping every `sample_every`-th epoch's parameters."""
     import torch
 
     from paper_2406_04008_amd import autotune
@@ -138,21 +169,40 @@ def coarse_to_fine(sc):
     sched.run(keep_level_params=False)  # warm-up (instantiated graphs, caches)
     res = sched.run(keep_level_params=False)
     assert np.all(np.isfinite(res.params)), "non-finite parameters after the schedule"
-    last = sched.levels[-1]
-    pairs = support_pairs(sc, sc.params, last)
+    # eager replay of the same epochs, level by level, with parameter samples and the status words
+    p = sched.scenes[0].params_tensor()
+    m, v, st = sched.scenes[0].new_state()
+    levels = []
+    for i, cs in enumerate(sched.scenes):
+        cs.reset_state(m, v, st)
+        samples, scans = [], []
+        for e in range(sched.steps):
+            if e % sample_every == 0:
+                samples.append(p.detach().cpu().numpy())
+            cs.iterate(p, m, v, st, lr_px=sched.lr_px)
+            if e % sample_every == 0:
+                scans.append(scans_per_epoch(cs.status()))
+        pairs = float(np.mean([support_pairs(sc, x, sched.levels[i]) for x in samples]))
+        run = res.levels[i]
+        its = run.steps / (run.gpu_ms / 1e3)
+        ev = float(np.mean(scans)) * pairs * its
+        levels.append({"level": run.level, "tile": run.tile, "ms_per_epoch": run.gpu_ms / run.steps,
+                       "final_loss": [float(x) for x in run.loss.sum(0)],
+                       "pixel_edge_pairs_per_scan_mean": pairs, "scans_per_epoch": float(np.mean(scans)),
+                       "pixel_edge_evals_per_s": ev, "implied_valu_frac": implied_valu_frac(ev)})
+    torch.cuda.synchronize()
+    replay_same = bool(np.array_equal(p.cpu().numpy(), res.params))
     return {"scene": sc.name, "epochs": res.epochs, "gpu_s": res.gpu_ms / 1e3,
-            "it_per_s": res.epochs / (res.gpu_ms / 1e3),
-            "levels": [{"level": l.level, "tile": l.tile, "ms_per_epoch": l.gpu_ms / l.steps,
-                        "final_loss": [float(x) for x in l.loss.sum(0)]} for l in res.levels],
-            "finest_level_pixel_edge_pairs_seed0": pairs,
-            "finest_level_pixel_edge_evals_per_s": 2.0 * pairs / (res.levels[-1].gpu_ms / 1e3 / res.levels[-1].steps)}
+            "it_per_s": res.epochs / (res.gpu_ms / 1e3), "levels": levels,
+            "pairs_sampled_every": sample_every, "eager_replay_matches_graphs": replay_same}
 
 
 def batched_vs_loop(steps):
     """64 independent layouts (sides 128..512, 20..400 items) at full resolution: one batched scene (every
     kernel launched once per epoch over all layouts) against a loop over 64 one-layout scenes on the same
     stream, same epochs from the same start, each scene's epochs in one multi-epoch call.  Per-layout
-    results are bitwise identical in the two forms."""
+    results are bitwise identical in the two forms.  The pixel-edge figures count the pairs of the
+    parameters each epoch scanned (an eager replay of the same epochs)."""
     import torch
 
     from paper_2406_04008_amd import _lib, autotune, scenes
@@ -186,14 +236,29 @@ def batched_vs_loop(steps):
     run(loop, 2)
     tb, pb = run(batched, steps)
     tl, pl = run(loop, steps)
-    pairs = support_pairs(sc, sc.params, level)
-    return {"layouts": sc.num_layouts, "items": sc.num_shapes, "pixels": int(batched[0].num_pixels),
-            "pixel_edge_pairs_per_scan": pairs, "steps": steps, "tile": cfg.tile,
-            "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk,
-            "batched_it_per_s": steps / (tb / 1e3), "loop_it_per_s": steps / (tl / 1e3),
-            "batched_pixel_edge_evals_per_s": 2.0 * pairs * steps / (tb / 1e3),
-            "loop_pixel_edge_evals_per_s": 2.0 * pairs * steps / (tl / 1e3),
-            "speedup": tl / tb, "batched_matches_loop": bool(np.array_equal(pb, pl))}
+    # the batched epochs once more, eagerly, keeping the parameters of every epoch
+    cs = batched[0]
+    p = cs.params_tensor()
+    m, v, st = cs.new_state()
+    pairs_each, scans = [], []
+    for _ in range(steps):
+        pairs_each.append(support_pairs(sc, p.cpu().numpy(), level))
+        cs.iterate(p, m, v, st)
+        scans.append(scans_per_epoch(cs.status()))
+    torch.cuda.synchronize()
+    pairs = float(np.mean(pairs_each))
+    scan = float(np.mean(scans))
+    out = {"layouts": sc.num_layouts, "items": sc.num_shapes, "pixels": int(cs.num_pixels),
+           "pixel_edge_pairs_per_scan_mean": pairs, "pixel_edge_pairs_seed0": int(pairs_each[0]),
+           "scans_per_epoch": scan, "steps": steps, "tile": cfg.tile,
+           "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk,
+           "batched_it_per_s": steps / (tb / 1e3), "loop_it_per_s": steps / (tl / 1e3),
+           "batched_pixel_edge_evals_per_s": scan * pairs * steps / (tb / 1e3),
+           "loop_pixel_edge_evals_per_s": scan * pairs * steps / (tl / 1e3),
+           "speedup": tl / tb, "batched_matches_loop": bool(np.array_equal(pb, pl)),
+           "eager_replay_matches": bool(np.array_equal(p.cpu().numpy(), pb))}
+    out["implied_valu_frac"] = implied_valu_frac(out["batched_pixel_edge_evals_per_s"])
+    return out
 
 
 def uniform_term(sc, level, cfg, steps, weight=2e-3):
@@ -279,6 +344,67 @@ def vertex_grad(sc, level, cfg, reps=50):
     return out
 
 
+def seed0_layout(cs, p0, reps):
+    """Epochs at the fixed seed-0 parameters: `reps` times collage_forward_backward at p0 then collage_step
+    into a scratch copy (the parameters the next forward reads never change), HIP events around them."""
+    import torch
+
+    from paper_2406_04008_amd import _lib
+
+    stream = torch.cuda.Stream()
+    p_fix = p0.clone()
+    p_s = p0.clone()
+    m, v, st = cs.new_state()
+    loss = torch.empty(cs.B, _lib.LOSS_TERMS, device="cuda")
+    grad = torch.empty(cs.N, 4, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            cs.forward_backward(p_fix, want_cov=False, loss=loss, grad=grad)
+            cs.step(p_s, grad, m, v, st)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            cs.forward_backward(p_fix, want_cov=False, loss=loss, grad=grad)
+            cs.step(p_s, grad, m, v, st)
+        e1.record(stream)
+    stream.synchronize()
+    status = cs.status(stream)
+    assert torch.equal(p_fix, p0)
+    return reps / (e0.elapsed_time(e1) / 1e3), scans_per_epoch(status)
+
+
+def recompute_only(sc, level, cfg, steps, warmup, p_end_cached):
+    """The timed region of the headline (the same epochs from the seed-0 layout) with no nearest-edge
+    codes kept between the coverage and adjoint passes: the adjoint scans every item's edges again."""
+    import torch
+
+    from paper_2406_04008_amd import _lib
+    from paper_2406_04008_amd.collage import CollageScene
+
+    cs = CollageScene(sc, level=level, tile=cfg.tile, code_capacity=0, bin_chunk=cfg.bin_chunk)
+    stream = torch.cuda.Stream()
+    loss = torch.empty(cs.B, _lib.LOSS_TERMS, device="cuda")
+    grad = torch.empty(cs.N, 4, device="cuda")
+    out = {}
+    for timed in (False, True):
+        p = cs.params_tensor()
+        m, v, st = cs.new_state()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            cs.iterate_n(p, m, v, st, steps if timed else max(warmup, 1), loss=loss, grad=grad, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        if timed:
+            out = {"it_per_s": steps / (e0.elapsed_time(e1) / 1e3), "scans_per_epoch": scans_per_epoch(cs.status(stream)),
+                   "matches_cached_codes": bool(np.array_equal(p.cpu().numpy(), p_end_cached))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,7 +469,6 @@ def main():
         if args.warmup:
             cs.iterate_n(params, m, v, step, args.warmup, loss=loss, grad=grad, stream=stream)
     reset()
-    p_start = params.detach().cpu().numpy().copy()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -355,6 +480,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     region_ms = ev0.elapsed_time(ev1)
+    scans = scans_per_epoch(cs.status(stream))
     p_end = params.detach().cpu().numpy().copy()
     tiles_ms = timer.elapsed_ms()
     assert np.all(np.isfinite(p_end)), "non-finite parameters after the timed region"
@@ -390,7 +516,12 @@ def main():
     assert len(stamped) == len(tiles_ms)
     tile_ms = float(np.mean(tiles_ms))
     # algorithmic work of the stamped launches over their summed durations
-    achieved = OPS_PER_PAIR * float(stamped.sum()) / (float(np.sum(tiles_ms)) * 1e-3)
+    achieved = FWD_OPS_PER_PAIR * float(stamped.sum()) / (float(np.sum(tiles_ms)) * 1e-3)
+    achieved_argmin = (FWD_OPS_PER_PAIR + ARGMIN_OPS_PER_PAIR) * float(stamped.sum()) / (float(np.sum(tiles_ms)) * 1e-3)
+    # the fixed seed-0 layout (its pairs, every epoch) and the form that keeps no codes between passes
+    seed0_its, seed0_scans = seed0_layout(cs, p0, args.steps)
+    rc = recompute_only(sc, args.level, cfg, args.steps, args.warmup, p_end)
+    rc["pixel_edge_evals_per_s"] = rc["scans_per_epoch"] * pairs * rc["it_per_s"]
     out = {
         "metric": METRIC,
         "value": its,
@@ -409,10 +540,15 @@ def main():
                                "(4-16 segments, 8 points each), 10-ellipse container, padding 2 px, "
                                "downward force 1e-3, seed 0", "tile": cfg.tile,
                    "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk},
-        "pixel_edge_evals_per_s": 2.0 * pairs * its,
+        "form": "the coverage pass keeps each (pixel, item)'s nearest-edge code (2 bytes) for the adjoint, "
+                "which evaluates that one edge; recompute_only keeps none and scans again",
+        "pixel_edge_evals_per_s": scans * pairs * its,
         "pixel_edge_pairs_per_scan": pairs,
+        "scans_per_epoch": scans,
         "pixel_edge_pairs_seed0_layout": int(pairs_each[0]),
-        "pixel_edge_evals_per_s_seed0_layout": 2.0 * float(pairs_each[0]) * its,
+        "seed0_layout_it_per_s": seed0_its,
+        "pixel_edge_evals_per_s_seed0_layout": seed0_scans * float(pairs_each[0]) * seed0_its,
+        "recompute_only": rc,
         "replay_matches_timed": replay_same,
         "wall_s": wall,
         "graph_it_per_s": args.steps / (graph_ms / 1e3),
@@ -425,7 +561,9 @@ def main():
             "unit": "TOP/s",
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": measured_traffic(cfg.tile),
-            "ops_per_pair": OPS_PER_PAIR,
+            "ops_per_pair": FWD_OPS_PER_PAIR,
+            "argmin_ops_per_pair": ARGMIN_OPS_PER_PAIR,
+            "frac_with_argmin": achieved_argmin / PEAK_LANE_OPS,
             "kernel_ms_mean": tile_ms,
             "kernel_launches_timed": int(len(tiles_ms)),
             "kernel_timing": f"HIP events on the coverage launch of every {TIMER_STRIDE}th epoch of the timed region",
@@ -456,6 +594,17 @@ def main():
         out["paper_preset"] = paper_preset(sc, args.level, cfg, args.steps)
     if "vertex" in extras:
         out["vertex_grad"] = vertex_grad(sc, args.level, cfg)
+    # no pixel-edge figure may imply more forward-scan work per second than the VALU peak
+    figs = {"headline": out["pixel_edge_evals_per_s"], "seed0": out["pixel_edge_evals_per_s_seed0_layout"],
+            "recompute_only": rc["pixel_edge_evals_per_s"]}
+    for key in ("coarse_to_fine", "open_shapes"):
+        for lv in out.get(key, {}).get("levels", []):
+            figs[f"{key}_{lv['level']}"] = lv["pixel_edge_evals_per_s"]
+    if "batched" in out:
+        figs["batched"] = out["batched"]["batched_pixel_edge_evals_per_s"]
+    implied = {k_: implied_valu_frac(v_) for k_, v_ in figs.items()}
+    out["implied_valu_frac_max"] = max(implied.values())
+    assert out["implied_valu_frac_max"] <= 1.0, implied
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.level)
     print(json.dumps(out), flush=True)

@@ -74,6 +74,24 @@ extern "C" {
 /* collage_scene_desc.flags: divide the image-mismatch loss terms by the canvas area (eqs. 5, 6) */
 #define COLLAGE_FLAG_AREA_MEAN 1u
 
+/*
+ * Device status words: COLLAGE_STATUS_WORDS int32 values at offset 0 of the workspace, zeroed at the
+ * start of every call that takes a workspace and written by its kernels (never read by the library).
+ *   [COLLAGE_STATUS_NONFINITE]  (epoch, item) pairs of the call whose parameters were not all finite:
+ *                               such an item is skipped by the coverage (it covers no pixel) and its
+ *                               gradient is NaN.  Counted by every call that evaluates the losses or the
+ *                               gradient (not by collage_render_shapes).
+ *   [COLLAGE_STATUS_CHUNKS]     64-pixel chunks of (screen tile, item) work in the coverage pass of the
+ *                               call's last epoch (the units of work of the rasterization).
+ *   [COLLAGE_STATUS_RESCANNED]  of those, the chunks whose nearest edges the adjoint found by scanning
+ *                               the edges again, beyond the scene's code capacity (0 without a backward).
+ * The other words are reserved (0).  collage_read_status copies them to the host.
+ */
+#define COLLAGE_STATUS_NONFINITE 0
+#define COLLAGE_STATUS_CHUNKS 1
+#define COLLAGE_STATUS_RESCANNED 2
+#define COLLAGE_STATUS_WORDS 8
+
 
 typedef struct collage_scene collage_scene; /* opaque host handle */
 
@@ -120,13 +138,31 @@ typedef struct collage_scene_desc {
   uint32_t flags;               /* 0 or COLLAGE_FLAG_AREA_MEAN; other bits are rejected */
 } collage_scene_desc;
 
-/* Validates `desc`, copies its host arrays and allocates the scene's small device tables.
- * On success *out owns them until collage_scene_destroy. */
+/*
+ * The collage problem of Sec. 3 ("Collage Problem") at one level of the schedule of Sec. 4.3: B
+ * containers C_b, each with its items G_i (outlines in their own frames, vertex arrays), the level
+ * scale k_b, and the loss constants of Sec. 4.2.  Validates `desc` (COLLAGE_ERR_INVALID,
+ * COLLAGE_ERR_SIZE or COLLAGE_ERR_UNSUPPORTED, nothing allocated), copies its host arrays and
+ * allocates the scene's two small device tables (layout records, vertex offsets: the only device
+ * memory the library allocates, COLLAGE_ERR_HIP if that fails).  On success *out owns them until
+ * collage_scene_destroy (NULL is ignored).  Device pointers of `desc` stay borrowed.
+ */
 int collage_scene_create(const collage_scene_desc *desc, collage_scene **out);
 void collage_scene_destroy(collage_scene *scene);
 
-/* Bytes of device workspace the compute calls need for this scene (256-byte aligned base expected). */
+/*
+ * Bytes of device workspace the compute calls need for this scene: the per-epoch intermediates of
+ * Fig. 2 (transformed edges of eq. 2, per-tile item lists, the coverage sums S and S_pad, dLoss/dS, the
+ * adjoint partials) and the status words at offset 0.  The caller allocates it (256-byte aligned) and
+ * owns it; calls on one workspace must not overlap.  COLLAGE_ERR_INVALID for NULL arguments.
+ */
 int collage_workspace_size(const collage_scene *scene, size_t *bytes);
+
+/* Copies the COLLAGE_STATUS_WORDS status words of `workspace` to the host array `status`, after the work
+ * queued on `stream` (this call waits for the stream).  COLLAGE_ERR_INVALID for NULL arguments,
+ * COLLAGE_ERR_WORKSPACE for a workspace smaller than the scene's, COLLAGE_ERR_HIP if the copy fails. */
+int collage_read_status(const collage_scene *scene, const void *workspace, size_t workspace_bytes, int32_t *status,
+                        void *stream);
 
 /* Number of pixels over all layouts (length of packed images) and of screen tiles. */
 int collage_scene_info(const collage_scene *scene, int64_t *num_pixels, int64_t *num_tiles);
@@ -193,8 +229,11 @@ int collage_iterate(const collage_scene *scene, float *params, float *cov, float
                     void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Per-item coverage images for items [first, first + count): alpha and (optionally) alpha_pad,
- * each image the size of the item's layout canvas, written one after another.
+ * Per-item coverage images of the differentiable rasterization (Sec. 3 "Differentiable Rendering"; the
+ * alpha of the conventions above) for items [first, first + count): alpha and (optionally) alpha_pad,
+ * each image the size of the item's layout canvas (row-major), written one after another.  For tests
+ * and small scenes: the losses themselves never need per-item images.  COLLAGE_ERR_SIZE for a range
+ * outside [0, N) or more than 65535 items, COLLAGE_ERR_INVALID for NULL params or alpha.
  */
 int collage_render_shapes(const collage_scene *scene, const float *params, int32_t first, int32_t count, float *alpha,
                           float *alpha_pad, void *workspace, size_t workspace_bytes, void *stream);

@@ -22,6 +22,10 @@ ERR_UNSUPPORTED = -5
 FLAG_NONE = 0
 FLAG_AREA_MEAN = 1
 LOSS_TERMS = 9  # overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
+STATUS_WORDS = 8
+STATUS_NONFINITE = 0  # (epoch, item) pairs of the last call whose parameters were not all finite
+STATUS_CHUNKS = 1  # 64-pixel chunks of the last epoch's coverage pass
+STATUS_RESCANNED = 2  # of those, chunks the adjoint rescanned (beyond the code capacity)
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -49,6 +53,7 @@ SIGNATURES = [
     ("collage_scene_destroy", None, [_vp]),
     ("collage_workspace_size", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("collage_scene_info", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    ("collage_read_status", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _vp]),
     ("collage_forward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_forward_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),

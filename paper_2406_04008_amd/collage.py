@@ -105,6 +105,17 @@ class CollageScene:
     def _ws(self):
         return _ptr(self.workspace), self.workspace.numel()
 
+    def status(self, stream=None) -> np.ndarray:
+        """The device status words of the workspace after the work queued on `stream` (the current stream
+        by default): [STATUS_NONFINITE] counts the (epoch, item) pairs of the last call with non-finite
+        parameters.  Waits for the stream."""
+        out = np.zeros(_lib.STATUS_WORDS, np.int32)
+        ws, nb = self._ws()
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        _lib.check(self.lib.collage_read_status(self.handle, ws, nb, out.ctypes.data_as(_lib._i32p), st),
+                   "collage_read_status")
+        return out
+
     def params_tensor(self, params=None) -> torch.Tensor:
         p = self.scene.params if params is None else params
         if isinstance(p, torch.Tensor):
@@ -148,12 +159,15 @@ class CollageScene:
         _lib.check(rc, "collage_backward_vertices")
         return grad, grad_verts
 
-    def forward_backward(self, params: torch.Tensor, want_cov: bool = True):
+    def forward_backward(self, params: torch.Tensor, want_cov: bool = True, loss: Optional[torch.Tensor] = None,
+                         grad: Optional[torch.Tensor] = None):
         _need(params, (self.N, 4), "params")
         cov = torch.empty(self.num_pixels, device=self.device) if want_cov else None
         cov_pad = torch.empty(self.num_pixels, device=self.device) if want_cov else None
-        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device)
-        grad = torch.empty(self.N, 4, device=self.device)
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device) if loss is None else loss
+        grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
+        _need(loss, (self.B, _lib.LOSS_TERMS), "loss")
+        _need(grad, (self.N, 4), "grad")
         ws, nb = self._ws()
         rc = self.lib.collage_forward_backward(self.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss),
                                                _ptr(grad), ws, nb, _stream(self.device))

@@ -56,7 +56,7 @@ struct collage_scene {
   int32_t *d_vert_off = nullptr;
   // workspace layout
   int64_t unit_cap = 0;
-  size_t off_counters = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
+  size_t off_status = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
@@ -145,7 +145,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.rho = s->rho;
   a.mask = s->mask;
   a.stroke = s->stroke;
-  a.counters = reinterpret_cast<int32_t *>(w + s->off_counters);
+  a.status = reinterpret_cast<int32_t *>(w + s->off_status);
   a.shapes = reinterpret_cast<ShapeRec *>(w + s->off_shapes);
   a.bbox = reinterpret_cast<int4 *>(w + s->off_bbox);
   a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
@@ -280,8 +280,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   if (code_cap < 0) code_cap = std::max<int64_t>(65536, 4 * ((pix + 63) / 64));
   s->code_cap = std::min<int64_t>(code_cap, max_chunks);
   size_t off = 0;
-  s->off_counters = off;
-  off = align256(off + sizeof(int32_t) * CNT_WORDS);
+  s->off_status = off;
+  off = align256(off + sizeof(int32_t) * kStatusWords);
   s->off_shapes = off;
   off = align256(off + sizeof(ShapeRec) * (size_t)s->N);
   s->off_bbox = off;
@@ -357,6 +357,17 @@ int collage_workspace_size(const collage_scene *s, size_t *bytes) {
   if (!s || !bytes) return fail(COLLAGE_ERR_INVALID, "scene or bytes is NULL");
   *bytes = s->ws_bytes;
   return COLLAGE_OK;
+}
+
+int collage_read_status(const collage_scene *s, const void *ws, size_t ws_bytes, int32_t *status, void *stream) {
+  if (!s || !status) return fail(COLLAGE_ERR_INVALID, "scene or status is NULL");
+  int rc = check_ws(s, const_cast<void *>(ws), ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char *w = static_cast<const char *>(ws) + s->off_status;
+  hipError_t e = hipMemcpyAsync(status, w, sizeof(int32_t) * kStatusWords, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_read_status");
 }
 
 int collage_scene_info(const collage_scene *s, int64_t *num_pixels, int64_t *num_tiles) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "collage.h"
+
 namespace collage {
 
 // One layout of a batch at one level (device copy built at scene creation).
@@ -69,8 +71,9 @@ struct alignas(16) EdgeD {
   double inv_len;       // 1 / |b - a| = sqrt(inv_ee) (0 for a degenerate edge): the unit normal's scale
 };
 
-// Work counters at the start of the workspace (zeroed by the transform kernel of every call).
-enum Counter { CNT_UNITS = 0, CNT_WORDS = 8 };
+// Status words at the start of the workspace (COLLAGE_STATUS_* of collage.h), zeroed by the transform
+// kernel, which every compute call launches first.
+constexpr int kStatusWords = COLLAGE_STATUS_WORDS;
 constexpr int kPersistWaves = 4;      // waves per workgroup of the persistent kernels
 constexpr int kCoverBlocksPerCU = 6;  // resident workgroups per CU: coverage kernel (LDS and VGPR bound)
 constexpr int kAdjointBlocksPerCU = 4;  // and adjoint kernel (VGPR bound)
@@ -102,7 +105,7 @@ struct KArgs {
   EdgeRec *edges;
   EdgeD *edges_d;
   // binning outputs
-  int32_t *counters;
+  int32_t *status;       // [kStatusWords] device status words (workspace offset 0)
   int32_t *tile_count;
   int32_t *tile_list;
   int2 *item_unit;       // per layout [items][tiles]: the item's unit in the tile (its chunks, chunks of the

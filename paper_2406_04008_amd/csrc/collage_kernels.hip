@@ -385,7 +385,7 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
 
 __global__ __launch_bounds__(256) void k_transform(KArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (blockIdx.x == 0 && threadIdx.x < CNT_WORDS) a.counters[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kStatusWords) a.status[threadIdx.x] = 0;
   const int sid = blockIdx.x * 4 + wave;
   if (sid >= a.num_shapes) return;
   transform_item(a, sid, lane, reinterpret_cast<const float4 *>(a.params)[sid], transform_preload(a, sid, lane));
@@ -985,6 +985,13 @@ __device__ __forceinline__ long long block_exclusive_scan(long long v, long long
   return off + x - v;
 }
 
+// The chunk counts of the pass in the status words (one thread writes them once per epoch).
+__device__ __forceinline__ void publish_chunk_status(const KArgs &a, long long chunks) {
+  const long long beyond = chunks > a.code_cap ? chunks - a.code_cap : 0;
+  a.status[COLLAGE_STATUS_CHUNKS] = (int32_t)min(chunks, (long long)INT32_MAX);
+  a.status[COLLAGE_STATUS_RESCANNED] = a.keep_codes ? (int32_t)min(beyond, (long long)INT32_MAX) : 0;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
   __shared__ long long s_w[16];
   const int tid = threadIdx.x;
@@ -1024,6 +1031,7 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
     prc[nt] = tot_c;
     prq[nt] = tot_q;
     if (a.step_inc != nullptr) a.step_inc[0] = a.step_inc[0] + 1;
+    publish_chunk_status(a, tot_q);
   }
 }
 
@@ -1202,7 +1210,10 @@ __device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq) {
       a.tile_pre[t] = pc[t];
       a.tile_pre[nt + 1 + t] = pq[t];
     }
-    if (tid == 0 && a.step_inc != nullptr) a.step_inc[0] = a.step_inc[0] + 1;
+    if (tid == 0) {
+      if (a.step_inc != nullptr) a.step_inc[0] = a.step_inc[0] + 1;
+      publish_chunk_status(a, (long long)tq);
+    }
   }
 }
 
@@ -1497,6 +1508,13 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
       }
     }
     if (GRAD && mine[0]) a.uflags[pix[0]] = (uint8_t)bits;
+  }
+  if (blockIdx.x == LS[u.b].ptile_off) {
+    // the first tile of each layout counts the layout's items whose parameters are not finite into the
+    // status word (zeroed by this call's transform kernel)
+    int bad = 0;
+    for (int q = LS[u.b].shape_begin + tid; q < LS[u.b].shape_end; q += NT) bad += a.shapes[q].bad;
+    if (bad != 0) atomicAdd(&a.status[COLLAGE_STATUS_NONFINITE], bad);
   }
   if (a.write_loss) {
     if (a.w[8] != 0.0f && blockIdx.x == LS[u.b].ptile_off) {
@@ -1907,9 +1925,12 @@ __device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T], int per
       const int x = (int)wave_incl_scan_u32((unsigned)cnt);
       const int pre = x - cnt, total = __builtin_amdgcn_readlane(x, 63);
       // chunk kk of the batch -> its partial, in the wave's LDS map (a unit has at most T * T / 64
-      // chunks); the wave's LDS operations run in program order, so the reads below see these writes
+      // chunks); the wave's LDS operations complete in program order
       const int nmap = min(total, T * T);
       for (int c = 0; c < cnt && pre + c < nmap; ++c) map[pre + c] = first + c;
+      // the map's writes come before any lane reads it, and (below) its reads before the next round's
+      // writes: a wave barrier keeps the compiler from moving LDS accesses across either point
+      __builtin_amdgcn_wave_barrier();
       // then the chunks, one per lane, kFinGather rounds of 64 with all their loads in flight together
       // before they are summed (in round order)
       for (int kb = 0; kb < nmap; kb += 64 * kFinGather) {
@@ -1928,6 +1949,7 @@ __device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T], int per
           acc.w += v[r].w;
         }
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   acc.x = wave_sum(acc.x);

@@ -119,6 +119,8 @@ def test_null_scene_calls_fail_cleanly():
     assert lib.collage_forward_backward(None, None, None, None, None, None, None, 0, None) == _lib.ERR_INVALID
     assert lib.collage_graph_launch(None, 1, None) == _lib.ERR_INVALID
     assert lib.collage_adam_reset(None, None, None, None, None) == _lib.ERR_INVALID
+    st = (ctypes.c_int32 * _lib.STATUS_WORDS)()
+    assert lib.collage_read_status(None, None, 0, st, None) == _lib.ERR_INVALID
     out_g = ctypes.c_void_p()
     # graph capture is refused on the NULL stream and for unknown flags before any HIP call
     assert lib.collage_graph_create(None, None, None, None, None, None, None, None, None, 0.5, 0.9, 0.999, 1e-8,

@@ -176,6 +176,45 @@ def test_adam_step_matches_torch():
     np.testing.assert_allclose(_np(p_lib), _np(pt), rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("level", [128, 1024])
+def test_adam_step_at_coarse_and_fine_levels(level):
+    """Eq. 4 as Adam at levels of scale k = 0.25 and 2 of the metric scene: two collage_step calls against
+    torch.optim.Adam with the learning rates of the definition (lr_px / k for t, lr_px / (k rho_i) for theta
+    and s: every item moves by lr_px level px) and against the oracle's update."""
+    sc = S.config3(0)
+    _say("adam level", level)
+    k = level / sc.level_ref
+    cs = CollageScene(sc, level=level)
+    p = cs.params_tensor()
+    _, _, _, g = cs.forward_backward(p, want_cov=False)
+    m, v, step = cs.new_state()
+    p_lib = p.clone()
+    cs.step(p_lib, g, m, v, step)
+    cs.step(p_lib, g, m, v, step)
+    assert int(step.item()) == 2
+    p0, g0 = _np(p).astype(np.float64), _np(g).astype(np.float64)
+    lr = np.zeros((sc.num_shapes, 4))
+    lr[:, :2] = sc.lr_px / k
+    lr[:, 2:] = sc.lr_px / (k * sc.rho.astype(np.float64))[:, None]
+    ts = [torch.tensor(p0[i, c], dtype=torch.float64, requires_grad=True) for i in range(sc.num_shapes) for c in range(4)]
+    opt = torch.optim.Adam([{"params": [t], "lr": float(lr.reshape(-1)[j])} for j, t in enumerate(ts)],
+                           betas=(0.9, 0.999), eps=1e-8)
+    for _ in range(2):
+        for j, t in enumerate(ts):
+            t.grad = torch.tensor(g0.reshape(-1)[j], dtype=torch.float64)
+        opt.step()
+    pt = np.array([t.item() for t in ts]).reshape(-1, 4)
+    o = Oracle(sc, level=level)
+    lr_o = o.learning_rates()
+    po, mo, vo = o.adam(p0, g0, np.zeros_like(p0), np.zeros_like(p0), 1, lr_o)
+    po, mo, vo = o.adam(po, g0, mo, vo, 2, lr_o)
+    np.testing.assert_allclose(lr_o, lr, rtol=1e-12)
+    np.testing.assert_allclose(_np(p_lib), pt, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(_np(p_lib), po, rtol=1e-6, atol=1e-6)
+    # the step moved the items: by about 2 lr_px level px over two steps where the gradient is not small
+    assert np.abs(k * (_np(p_lib)[:, :2] - p0[:, :2])).max() > 0.9 * sc.lr_px
+
+
 def test_iterate_equals_fused_then_step():
     sc = S.random_scene(4, [(40, 33), (29, 45)], [5, 6])
     _say("iterate")
@@ -503,6 +542,21 @@ def test_edge_cases():
     g = _np(grad)
     assert np.all(np.isnan(g[3])) and np.all(np.isfinite(np.delete(g, 3, 0)))
     assert np.all(np.isfinite(_np(loss)))
+    # the status word counts the item once per epoch of the call, and is cleared by the next call
+    assert cs.status()[_lib.STATUS_NONFINITE] == 1
+    m, v, st = cs.new_state()
+    pn = cs.params_tensor(p)
+    cs.iterate_n(pn, m, v, st, 3)
+    assert cs.status()[_lib.STATUS_NONFINITE] == 3
+    cs.forward_backward(cs.params_tensor())
+    st_ = cs.status()
+    assert st_[_lib.STATUS_NONFINITE] == 0 and st_[_lib.STATUS_CHUNKS] > 0 and st_[_lib.STATUS_RESCANNED] == 0
+    assert list(st_[3:]) == [0] * (_lib.STATUS_WORDS - 3)
+    # with no kept codes, the adjoint rescans every chunk of the pass
+    cs0 = CollageScene(sc2, code_capacity=0)
+    cs0.forward_backward(cs0.params_tensor())
+    st0 = cs0.status()
+    assert st0[_lib.STATUS_RESCANNED] == st0[_lib.STATUS_CHUNKS] == st_[_lib.STATUS_CHUNKS]
 
 
 def test_degenerate_scales():
