@@ -57,7 +57,7 @@ struct collage_scene {
   // workspace layout
   int64_t unit_cap = 0;
   size_t off_status = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_partial = 0, off_acc = 0,
+         off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_head = 0, off_spill = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
 };
@@ -160,7 +160,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.units = reinterpret_cast<UnitRec *>(w + s->off_units);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
-  a.partial = reinterpret_cast<double4 *>(w + s->off_partial);
+  a.head = reinterpret_cast<double4 *>(w + s->off_head);
+  a.spill = reinterpret_cast<double4 *>(w + s->off_spill);
   a.acc = reinterpret_cast<unsigned long long *>(w + s->off_acc);
   a.gbuf = reinterpret_cast<double2 *>(w + s->off_gbuf);
   a.codes = reinterpret_cast<uint16_t *>(w + s->off_codes);
@@ -320,8 +321,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + sizeof(int2) * (size_t)tiles);
   s->off_tpre = off;
   off = align256(off + sizeof(long long) * 2 * ((size_t)tiles + 1));
-  s->off_partial = off;
-  off = align256(off + sizeof(double4) * (size_t)s->chunk_cap);
+  s->off_head = off;
+  off = align256(off + sizeof(double4) * (size_t)list);
+  s->off_spill = off;
+  off = align256(off + sizeof(double4) * (size_t)s->adjoint_grid * kPersistWaves);
   s->off_acc = off;
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)pix);
   s->off_gbuf = off;

@@ -41,13 +41,22 @@ struct alignas(16) ShapeRec {
 
 // One (tile, item) work unit as the persistent passes read it, written by the binning kernel beside the
 // unit's list entry: a wave loads one record per unit instead of the list entry and then the item's.
+// 48 bytes: the small fields are packed (vertex and edge counts <= 32767, canvas coordinates <= 32767,
+// the rectangle's width <= 32 and its pixel count <= 1024).
 struct alignas(16) UnitRec {
-  int32_t eo, ec, nv, open;  // the item's first edge record (= first vertex), edges, vertices, open flag
-  int32_t x0, y0, w, n;      // the unit rectangle: the item's support box clipped to the tile (w x n / w px)
-  float cxf, cyf, orient;    // the item's origin (float) and outline orientation
+  int32_t eo;      // the item's first edge record (= first vertex)
+  int32_t ecnv;    // edges (bits 0-15) and vertices (bits 16-31) of the item
+  int32_t flags;   // kUnitOpen: open polyline; kUnitClockwise: the outline's orientation is clockwise
+  int32_t head;    // the unit's entry of the per-(item, tile) map: where the adjoint's head partial goes
+  int32_t xy;      // the unit rectangle (the item's support box clipped to the tile): x0 | y0 << 16
+  int32_t wn;      // its width | its pixel count << 16 (w x n / w px)
+  int32_t sid;     // the item (an open item's stroke radius is read from its ShapeRec)
   int32_t pad_;
-  double cx, cy, sw, sw_ds;  // the origin (double), stroke radius and its derivative in s
+  double cx, cy;   // the item's origin (double; the scan uses it rounded to float)
 };
+constexpr int32_t kUnitOpen = 1;
+constexpr int32_t kUnitClockwise = 2;
+static_assert(sizeof(UnitRec) == 48, "unit record size");
 
 // Per edge (a, b) of an item, in level px relative to the item's origin (cx, cy).
 // b is stored explicitly so that the half-open crossing test compares every vertex with the same
@@ -88,7 +97,7 @@ struct KArgs {
   int32_t tile;          // tile edge in px (8, 16 or 32)
   int32_t bin_chunk;     // items binned per pass
   int32_t unit_cap;      // upper bound of the number of units (list entries)
-  int64_t chunk_cap;     // upper bound of the number of 64-pixel chunks of a pass
+  int64_t chunk_cap;     // upper bound of the number of 64-pixel chunks of a pass (bounds the code capacity)
   int64_t code_cap;      // 64-pixel chunks whose nearest-edge codes are kept between the coverage and
                          // adjoint passes (the first code_cap chunks of the pass)
   int32_t cover_grid;    // workgroups of the persistent coverage kernel (all resident at once)
@@ -109,7 +118,8 @@ struct KArgs {
   int32_t *tile_count;
   int32_t *tile_list;
   int2 *item_unit;       // per layout [items][tiles]: the item's unit in the tile (its chunks, chunks of the
-                         // tile's earlier units), set where the tile lists the item
+                         // tile's earlier units), set where the tile lists the item; the same index holds
+                         // the unit's head partial
   int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
   int32_t scan_in_cover; // 1: the coverage kernel computes the tile prefixes (no scan launch)
   int32_t total_rows;    // tile rows over all layouts
@@ -124,8 +134,10 @@ struct KArgs {
   // accumulators
   unsigned long long *acc;  // [pixels][2] fixed-point S and S_pad (2^-40 units)
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
-  double4 *partial;         // [chunks of the pass] adjoint sums (n_x, n_y, theta, scale terms) of the
-                            // piece of a unit that starts at the chunk, 0 for other chunks
+  double4 *head;            // per layout [items][tiles] (the item_unit index): the adjoint sums (n_x, n_y,
+                            // theta, scale terms) of the piece of the unit that starts at its first chunk
+  double4 *spill;           // [adjoint waves]: the sums of a wave's first piece when it starts inside a unit
+                            // (only a wave's first piece can; the update finds such waves by their shares)
   double *block_loss;       // per pixel tile: the kLossTerms weighted loss-term sums
   uint8_t *uflags;          // [pixels] bit j: M != 0 and A_j < 1 (the uniform term's active windows)
   unsigned long long *vacc; // [V][2] outline-vertex adjoint sums, level frame, 2^-32 fixed point; null

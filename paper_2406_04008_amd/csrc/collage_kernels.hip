@@ -23,14 +23,15 @@
 //                tile's window occupancies from a summed-area table of the tile and its halo.
 //   k_unif_grad  (uniform term on) the same tiles: the term's share of dLoss/dS from window sums of
 //                the pixels' active-window bits.
-//   k_adjoint    persistent waves again: per chunk, the gradient terms of its pixels (double), one
-//                partial per piece of a unit.
+//   k_adjoint    persistent waves again: per chunk, the gradient terms of its pixels (double), summed
+//                per piece of a unit: the piece at a unit's first chunk into the unit's head partial,
+//                a piece that starts inside a unit (only a wave's first can) into the wave's spill.
 //   k_vgrad,     (outline-vertex gradients only) the adjoint's walk once more, adding each pixel's
 //   k_vfinal     d sd / d(end points of its nearest edge) into per-vertex fixed-point sums, then back
 //                through eq. 2 per vertex.
-//   k_finalize   one wave per item (two or four items per workgroup) sums its units' partials in a fixed order (gradient, then the
-//                optional Adam update and the next epoch's transform); one workgroup per layout sums
-//                the loss blocks in a fixed order.
+//   k_finalize   one wave per item (two or four items per workgroup) sums its units' head and spill
+//                partials in a fixed order (gradient, then the optional Adam update and the next
+//                epoch's transform); one workgroup per layout sums the loss blocks in a fixed order.
 // Bulk outputs that later kernels read are written with nontemporal stores.  Results are bitwise
 // reproducible.
 #include "collage_internal.h"
@@ -883,21 +884,15 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
         const ShapeRec &sr = a.shapes[sid];
         UnitRec u;
         u.eo = sr.edge_off;
-        u.ec = sr.edge_cnt;
-        u.nv = a.vert_off[sid + 1] - a.vert_off[sid];
-        u.open = sr.open;
-        u.x0 = r.x0;
-        u.y0 = r.y0;
-        u.w = r.w;
-        u.n = r.n;
-        u.cxf = sr.cxf;
-        u.cyf = sr.cyf;
-        u.orient = sr.orient;
+        u.ecnv = sr.edge_cnt | ((a.vert_off[sid + 1] - a.vert_off[sid]) << 16);
+        u.flags = (sr.open ? kUnitOpen : 0) | (sr.orient < 0.0f ? kUnitClockwise : 0);
+        u.head = (int32_t)(LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt);
+        u.xy = r.x0 | (r.y0 << 16);
+        u.wn = r.w | (r.n << 16);
+        u.sid = sid;
         u.pad_ = 0;
         u.cx = sr.cx;
         u.cy = sr.cy;
-        u.sw = sr.sw;
-        u.sw_ds = sr.sw_ds;
         a.units[list_base + slots + q] = u;
       }
       const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
@@ -1163,6 +1158,45 @@ __device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int 
   py = r.y0 + ly;
 }
 
+// A unit record as the persistent passes use it (scalar loads and unpacking).  The float origin of the
+// scan is the double origin rounded, as the transform rounds it.
+struct UnitView {
+  Rect r;
+  int eo, ec, nv, head;
+  bool open;
+  float orient;
+  double cx, cy;
+  float cxf, cyf;
+  double sw, sw_ds;  // an open item's stroke radius and its derivative in s (0 for a closed item)
+};
+
+__device__ __forceinline__ UnitView unit_view(const KArgs &a, cptr<UnitRec> U) {
+  UnitView v;
+  const int xy = U->xy, wn = U->wn, ecnv = U->ecnv, fl = U->flags;
+  v.r.x0 = xy & 0xffff;
+  v.r.y0 = xy >> 16;
+  v.r.w = wn & 0xffff;
+  v.r.n = wn >> 16;
+  v.eo = U->eo;
+  v.ec = ecnv & 0xffff;
+  v.nv = ecnv >> 16;
+  v.head = U->head;
+  v.open = (fl & kUnitOpen) != 0;
+  v.orient = (fl & kUnitClockwise) ? -1.0f : 1.0f;
+  v.cx = U->cx;
+  v.cy = U->cy;
+  v.cxf = (float)v.cx;
+  v.cyf = (float)v.cy;
+  v.sw = 0.0;
+  v.sw_ds = 0.0;
+  if (v.open) {
+    cptr<ShapeRec> SR = konst(a.shapes) + U->sid;
+    v.sw = SR->sw;
+    v.sw_ds = SR->sw_ds;
+  }
+  return v;
+}
+
 // Exclusive prefix sums of the tiles' coverage costs (pc) and chunks (pq), [tiles + 1] each, for at most
 // kScanInCoverTiles tiles, by one 256-thread workgroup into LDS (two tiles per thread, DPP wave scans).
 // Workgroup 0 also writes them to tile_pre for the later passes and advances the Adam step counter,
@@ -1241,14 +1275,14 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
     Q = s_pre[1];
   }
   for (bool ok = walk_begin(a, wk, gw, nwaves, false, T, P, Q); ok; ok = walk_next(a, wk, T)) {
-    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
-    const Rect r = {U->x0, U->y0, U->w, U->n};
+    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+    const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
-    const int eo = U->eo, ec = U->ec;
-    const float cxf = U->cxf, cyf = U->cyf;
-    const double cx = U->cx, cy = U->cy;
-    const bool open = U->open != 0;
-    const double sw = U->sw;
+    const int eo = uv.eo, ec = uv.ec;
+    const float cxf = uv.cxf, cyf = uv.cyf;
+    const double cx = uv.cx, cy = uv.cy;
+    const bool open = uv.open;
+    const double sw = uv.sw;
     const bool staged = ec <= kStageEdges;
     if (staged) stage_edges(a.edges + eo, ec, S, lane);
     for (int j = wk.jlo; j < wk.jhi; ++j) {
@@ -1609,7 +1643,8 @@ __global__ __launch_bounds__(kPixThreads) void k_unif_grad(KArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// k_adjoint: per unit, the gradient terms of its pixels reduced to one partial per (tile, item).
+// k_adjoint: per unit, the gradient terms of its pixels reduced to a head partial per (tile, item) and a
+// spill per wave.
 // ------------------------------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
@@ -1621,14 +1656,14 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
   for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
-    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
-    const Rect r = {U->x0, U->y0, U->w, U->n};
+    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+    const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
-    const int eo = U->eo, ec = U->ec;
-    const float cxf = U->cxf, cyf = U->cyf, orient = U->orient;
-    const double cx = U->cx, cy = U->cy;
-    const bool open = U->open != 0;
-    const double sw = U->sw, sw_ds = U->sw_ds;
+    const int eo = uv.eo, ec = uv.ec;
+    const float cxf = uv.cxf, cyf = uv.cyf, orient = uv.orient;
+    const double cx = uv.cx, cy = uv.cy;
+    const bool open = uv.open;
+    const double sw = uv.sw, sw_ds = uv.sw_ds;
     // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1711,9 +1746,14 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
     acc.y = wave_sum(acc.y);
     acc.z = wave_sum(acc.z);
     acc.w = wave_sum(acc.w);
-    // the piece's sum sits at its first chunk; the piece's other chunks hold zeros
-    if (lane == 0) a.partial[q + wk.jlo] = acc;
-    for (int j = wk.jlo + 1 + lane; j < wk.jhi; j += 64) a.partial[q + j] = make_double4(0.0, 0.0, 0.0, 0.0);
+    // the piece that starts at the unit's first chunk is its head; only a wave's first piece can start
+    // inside a unit, and then it is the wave's spill
+    if (lane == 0) {
+      if (wk.jlo == 0)
+        a.head[uv.head] = acc;
+      else
+        a.spill[gw] = acc;
+    }
   }
 }
 
@@ -1745,14 +1785,14 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
   for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
-    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
-    const Rect r = {U->x0, U->y0, U->w, U->n};
+    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+    const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
-    const int eo = U->eo, ec = U->ec, nv = U->nv;
-    const float cxf = U->cxf, cyf = U->cyf, orient = U->orient;
-    const double cx = U->cx, cy = U->cy;
-    const bool open = U->open != 0;
-    const double sw = U->sw;
+    const int eo = uv.eo, ec = uv.ec, nv = uv.nv;
+    const float cxf = uv.cxf, cyf = uv.cyf, orient = uv.orient;
+    const double cx = uv.cx, cy = uv.cy;
+    const bool open = uv.open;
+    const double sw = uv.sw;
     const bool staged = ec <= kStageEdges;
     // small items: the piece's vertex sums gather in the wave's LDS (64-bit integer atomics, so the
     // order does not matter), then one global atomic per vertex and component; large items add directly
@@ -1872,15 +1912,16 @@ __device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g,
   return make_float4(pp[0], pp[1], pp[2], pp[3]);
 }
 
-constexpr int kFinGather = 4;  // rounds of 64 adjoint partials an update wave loads before summing them
+// The adjoint's waves split the pass's chunks in equal shares: wave w starts at chunk ceil(w tot / W).
+__device__ __forceinline__ long long adjoint_share(long long tot, long long w, long long W) {
+  return (w * tot + W - 1) / W;
+}
 
 // ADAM: update the parameters; XFORM (with ADAM): transform the items with the updated parameters.
 // The loads of the update and of the transform are issued first and consumed last, so that they are in
-// flight while the gradient is gathered.
-// s_map: per wave of the block, T * T entries of LDS for the chunk -> partial map.  per: items per
-// workgroup (its first per waves take one each).
+// flight while the gradient is gathered.  per: items per workgroup (its first per waves take one each).
 template <int T, bool ADAM, bool XFORM>
-__device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T], int per) {
+__device__ void finalize_grad(const KArgs &a, int per) {
   constexpr bool do_adam = ADAM, do_transform = ADAM && XFORM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (wave >= per) return;
@@ -1899,57 +1940,44 @@ __device__ void finalize_grad(const KArgs &a, long long (*s_map)[T * T], int per
   if constexpr (do_adam) t_step = uniform(a.step[0]);
   TransformPre tp;
   if constexpr (do_transform) tp = transform_preload(a, sid, lane);
-  const int ntx = LS[b].ntx, ntiles = ntx * LS[b].nty, nb = LS[b].shape_end - LS[b].shape_begin;
+  const int ntx = LS[b].ntx, ntiles = ntx * LS[b].nty;
   const int tile_off = LS[b].tile_off;
-  const int64_t list_off = LS[b].list_off;
-  const int2 *unit_of = a.item_unit + list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
+  const int64_t unit_base = LS[b].list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
   const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
+  const long long tot = uniform_ll(a.tile_pre[(a.total_tiles + 1) + a.total_tiles]);  // chunks of the pass
+  const long long W = (long long)a.adjoint_grid * kPersistWaves;
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-  long long *map = s_map[wave];
   if (bb.x <= bb.z && bb.y <= bb.w) {
-    // every tile that the support box meets lists the item; its units' adjoint partials (one per
-    // chunk) are spread over the lanes and summed by a fixed reduction
+    // every tile that the support box meets lists the item, and its unit there has at least one chunk.
+    // Per unit (one per lane): the head partial, then the spills of the waves whose share begins inside
+    // the unit's chunks [c0, c1), in wave order: waves w with c0 < ceil(w tot / W) < c1 and a non-empty
+    // share.  The head and the unit's map entry share an index, so all of a lane's first loads are
+    // independent.
     const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
     for (int r0 = 0; r0 < nt; r0 += 64) {
-      // up to 64 tiles at a time, one per lane: the unit's chunk count and first partial
       const int j = r0 + lane;
-      int cnt = 0;
-      long long first = 0;
       if (j < nt) {
         const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
-        const int2 u = unit_of[lt];
-        cnt = u.x;
-        first = q0[lt] + u.y;
-      }
-      const int x = (int)wave_incl_scan_u32((unsigned)cnt);
-      const int pre = x - cnt, total = __builtin_amdgcn_readlane(x, 63);
-      // chunk kk of the batch -> its partial, in the wave's LDS map (a unit has at most T * T / 64
-      // chunks); the wave's LDS operations complete in program order
-      const int nmap = min(total, T * T);
-      for (int c = 0; c < cnt && pre + c < nmap; ++c) map[pre + c] = first + c;
-      // the map's writes come before any lane reads it, and (below) its reads before the next round's
-      // writes: a wave barrier keeps the compiler from moving LDS accesses across either point
-      __builtin_amdgcn_wave_barrier();
-      // then the chunks, one per lane, kFinGather rounds of 64 with all their loads in flight together
-      // before they are summed (in round order)
-      for (int kb = 0; kb < nmap; kb += 64 * kFinGather) {
-        double4 v[kFinGather];
-#pragma unroll
-        for (int r = 0; r < kFinGather; ++r) {
-          const int kk = kb + 64 * r + lane;
-          v[r] = make_double4(0.0, 0.0, 0.0, 0.0);
-          if (kk < nmap) v[r] = a.partial[map[kk]];
-        }
-#pragma unroll
-        for (int r = 0; r < kFinGather; ++r) {
-          acc.x += v[r].x;
-          acc.y += v[r].y;
-          acc.z += v[r].z;
-          acc.w += v[r].w;
+        const int2 u = a.item_unit[unit_base + lt];
+        const double4 h = a.head[unit_base + lt];
+        const long long c0 = q0[lt] + u.y, c1 = c0 + u.x;
+        acc.x += h.x;
+        acc.y += h.y;
+        acc.z += h.z;
+        acc.w += h.w;
+        for (long long w = c0 * W / tot + 1; w < W; ++w) {
+          const long long bw = adjoint_share(tot, w, W);
+          if (bw >= c1) break;
+          if (adjoint_share(tot, w + 1, W) > bw) {
+            const double4 sp = a.spill[w];
+            acc.x += sp.x;
+            acc.y += sp.y;
+            acc.z += sp.z;
+            acc.w += sp.w;
+          }
         }
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
   acc.x = wave_sum(acc.x);
@@ -2010,14 +2038,13 @@ __device__ void finalize_loss(const KArgs &a, int b) {
 
 template <int T>
 __global__ __launch_bounds__(256) void k_finalize(KArgs a, int grad_blocks, int flags, int per) {
-  __shared__ long long s_map[4][T * T];
   if ((int)blockIdx.x < grad_blocks) {
     if (flags & 4)
-      finalize_grad<T, true, true>(a, s_map, per);
+      finalize_grad<T, true, true>(a, per);
     else if (flags & 1)
-      finalize_grad<T, true, false>(a, s_map, per);
+      finalize_grad<T, true, false>(a, per);
     else
-      finalize_grad<T, false, false>(a, s_map, per);
+      finalize_grad<T, false, false>(a, per);
   } else if (flags & 2) {
     finalize_loss(a, blockIdx.x - grad_blocks);
   }
