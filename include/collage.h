@@ -211,6 +211,22 @@ int collage_forward_backward(const collage_scene *scene, const float *params, fl
                              float *loss, float *grad, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * collage_forward_backward for callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same computation and outputs, with the
+ * library's own static scratch (COLLAGE_STATIC_SCRATCH_BYTES, 256-byte aligned, one copy per GPU, held
+ * from the library's first use on that GPU until the process ends) in place of a workspace.  No
+ * device memory is allocated or freed.  The first call on a device looks up that device's copy
+ * (hipGetSymbolAddress); later calls reuse it.  Every call on a GPU shares its scratch: calls that
+ * overlap on one GPU (other streams, other threads) race and give undefined results; the scratch keeps
+ * the last call's contents, and every call initializes what it reads.
+ * Errors: those of collage_forward_backward, and COLLAGE_ERR_WORKSPACE (checked before any launch) when
+ * collage_workspace_size of the scene exceeds COLLAGE_STATIC_SCRATCH_BYTES.
+ */
+#define COLLAGE_STATIC_SCRATCH_BYTES (64u << 20)
+int collage_forward_backward_static(const collage_scene *scene, const float *params, float *cov, float *cov_pad,
+                                    float *loss, float *grad, void *stream);
+
+/*
  * Adam update of the parameters (eq. 4 with Adam moments, bias-corrected, no weight decay).
  * step is a device int32 counter: this call uses t = *step + 1 and stores it back.  Learning rates:
  * lr_px / k for t_x, t_y (lr_px level px per step); lr_px / (k * rho_i) for theta and s (the item's

@@ -23,6 +23,7 @@ FLAG_NONE = 0
 FLAG_AREA_MEAN = 1
 LOSS_TERMS = 9  # overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
 STATUS_WORDS = 8
+STATIC_SCRATCH_BYTES = 64 << 20  # the scratch of collage_forward_backward_static
 STATUS_NONFINITE = 0  # (epoch, item) pairs of the last call whose parameters were not all finite
 STATUS_CHUNKS = 1  # 64-pixel chunks of the last epoch's coverage pass
 STATUS_RESCANNED = 2  # of those, chunks the adjoint rescanned (beyond the code capacity)
@@ -58,6 +59,7 @@ SIGNATURES = [
     ("collage_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_forward_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("collage_backward_vertices", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("collage_forward_backward_static", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("collage_step", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _vp]),
     ("collage_iterate", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,

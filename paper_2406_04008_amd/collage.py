@@ -174,6 +174,22 @@ class CollageScene:
         _lib.check(rc, "collage_forward_backward")
         return cov, cov_pad, loss, grad
 
+    def forward_backward_static(self, params: torch.Tensor, want_cov: bool = True,
+                                loss: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+        """forward_backward on the library's static scratch instead of this scene's workspace
+        (collage_forward_backward_static: no device allocation inside the call)."""
+        _need(params, (self.N, 4), "params")
+        cov = torch.empty(self.num_pixels, device=self.device) if want_cov else None
+        cov_pad = torch.empty(self.num_pixels, device=self.device) if want_cov else None
+        loss = torch.empty(self.B, _lib.LOSS_TERMS, device=self.device) if loss is None else loss
+        grad = torch.empty(self.N, 4, device=self.device) if grad is None else grad
+        _need(loss, (self.B, _lib.LOSS_TERMS), "loss")
+        _need(grad, (self.N, 4), "grad")
+        rc = self.lib.collage_forward_backward_static(self.handle, _ptr(params), _ptr(cov), _ptr(cov_pad), _ptr(loss),
+                                                      _ptr(grad), _stream(self.device))
+        _lib.check(rc, "collage_forward_backward_static")
+        return cov, cov_pad, loss, grad
+
     def new_state(self):
         """Zeroed Adam state (m, v, step) for this scene's parameters."""
         m = torch.zeros(self.N, 4, device=self.device)

@@ -456,6 +456,21 @@ int collage_backward_vertices(const collage_scene *s, const float *params, const
   return e == hipSuccess ? COLLAGE_OK : hip_fail(e, "collage_backward_vertices launch");
 }
 
+int collage_forward_backward_static(const collage_scene *s, const float *params, float *cov, float *cov_pad,
+                                    float *loss, float *grad, void *stream) {
+  if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");
+  if (s->ws_bytes > kStaticScratchBytes)
+    return fail(COLLAGE_ERR_WORKSPACE,
+                "the scene needs a workspace of %zu bytes, more than the %zu bytes of the static scratch; use "
+                "collage_forward_backward with a workspace",
+                s->ws_bytes, kStaticScratchBytes);
+  if (!loss || (s->N > 0 && (!params || !grad))) return fail(COLLAGE_ERR_INVALID, "params, loss or grad is NULL");
+  void *ws = nullptr;
+  hipError_t e = static_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "static scratch (hipGetSymbolAddress)");
+  return collage_forward_backward(s, params, cov, cov_pad, loss, grad, ws, kStaticScratchBytes, stream);
+}
+
 int collage_forward_backward(const collage_scene *s, const float *params, float *cov, float *cov_pad, float *loss,
                              float *grad, void *ws, size_t ws_bytes, void *stream) {
   if (!s) return fail(COLLAGE_ERR_INVALID, "scene is NULL");

@@ -186,6 +186,11 @@ hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_a
                            bool do_transform = false);
 hipError_t launch_adam_reset(float *m, float *v, int32_t *step, int num_shapes, hipStream_t st);
 hipError_t launch_adam_only(const KArgs &a, hipStream_t st);
+// The calling thread's current device's copy of the library's static scratch array (kStaticScratchBytes,
+// 256-byte aligned), found with hipGetSymbolAddress on the first request per device and kept.
+hipError_t static_scratch(void **out);
+constexpr size_t kStaticScratchBytes = COLLAGE_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
 hipError_t launch_render(const KArgs &a, int first, int count, float *alpha, float *alpha_pad, int max_pixels,
                          hipStream_t st);
 

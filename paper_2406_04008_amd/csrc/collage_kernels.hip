@@ -40,6 +40,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace collage {
 
 template <typename T>
@@ -2209,6 +2211,33 @@ hipError_t launch_adam_only(const KArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, const_cast<int32_t *>(a.step));
   if (a.num_shapes > 0) hipLaunchKernelGGL(k_adam, dim3((a.num_shapes + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// The static scratch of the allocation-free entry point: a workspace of kStaticScratchBytes that every
+// GPU the library runs on holds from the module's load until the process ends.  In host code the
+// array's name stands for a host-side shadow, not the device copy: only the address that
+// hipGetSymbolAddress returns, per device, may be passed to kernels or copies.
+// ------------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **out) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_adam_reset(float *m, float *v, int32_t *step, int num_shapes, hipStream_t st) {
