@@ -50,9 +50,10 @@
  *     launch, and collage_last_error() then describes the failure (thread-local).
  *   - Results are deterministic: the same inputs give bitwise the same outputs on the same device.
  *   - Precision: the nearest edge of every (pixel, item) is found by a float32 scan of the item's
- *     edges; the signed distance to that edge, the coverage, the loss sums and the gradient terms
- *     are then evaluated in double precision (the gradient's logistic factor sigma'(sd / tau) / tau
- *     in float32, a relative error of a few 1e-7) and returned as float32.
+ *     edges and re-decided among its neighbours in double precision; the distance to it is evaluated
+ *     in double, the coverage alpha, alpha_pad from it in float32 (a few 1e-7), summed exactly in
+ *     2^-40 fixed point; the loss sums and the gradient terms are double (the gradient's logistic
+ *     factor sigma'(sd / tau) / tau in float32, a relative error of a few 1e-7); outputs are float32.
  */
 #ifndef COLLAGE_H_
 #define COLLAGE_H_
@@ -134,7 +135,8 @@ typedef struct collage_scene_desc {
                                    adjoint rescans the edges of later chunks.  -1 = default (four
                                    items per pixel on average, at least 65536 chunks); 0 = always
                                    rescan */
-  int32_t bin_chunk;            /* items binned per pass over a layout (LDS list size); 0 = default */
+  int32_t bin_chunk;            /* 0..1024, accepted and not used: binning tests each candidate item once and
+                                   writes its unit from the testing thread, with no item list in LDS */
   uint32_t flags;               /* 0 or COLLAGE_FLAG_AREA_MEAN; other bits are rejected */
 } collage_scene_desc;
 

@@ -1,9 +1,8 @@
 """Launch-configuration autotuner for one scene level.
 
-The knobs of the scene (tile edge T in {8, 16, 32}, the code capacity that decides whether the adjoint
-reads the coverage pass's nearest-edge codes or rescans, and the bin chunk, i.e. how many items one
-pass of the binning kernel holds in LDS) change only the speed: every configuration computes the
-same quantities to the same tolerance against the oracle.  The tuner times whole epochs
+The knobs of the scene (tile edge T in {8, 16, 32}, and the code capacity that decides whether the
+adjoint reads the coverage pass's nearest-edge codes or rescans) change only the speed: every
+configuration computes the same quantities to the same tolerance against the oracle.  The tuner times whole epochs
 (collage_iterate_n) of every candidate from the same parameters on the GPU it will run on, and keeps
 the fastest.  Results are cached per (scene signature, level, device name) in memory and, if a path
 is given, in a JSON file.
@@ -33,7 +32,7 @@ class LaunchConfig:
         return {"tile": self.tile, "code_capacity": self.code_capacity, "bin_chunk": self.bin_chunk}
 
 
-DEFAULT_SPACE = [LaunchConfig(t, c, b) for t, c, b in itertools.product((8, 16, 32), (-1, 0), (0, 256))]
+DEFAULT_SPACE = [LaunchConfig(t, c, 0) for t, c in itertools.product((8, 16, 32), (-1, 0))]
 
 _CACHE: Dict[str, Tuple[LaunchConfig, Dict[str, float]]] = {}
 

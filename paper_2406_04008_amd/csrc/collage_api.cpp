@@ -56,7 +56,7 @@ struct collage_scene {
   int32_t *d_vert_off = nullptr;
   // workspace layout
   int64_t unit_cap = 0;
-  size_t off_status = 0, off_shapes = 0, off_bbox = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
+  size_t off_status = 0, off_shapes = 0, off_bins = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_head = 0, off_spill = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
@@ -147,7 +147,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.stroke = s->stroke;
   a.status = reinterpret_cast<int32_t *>(w + s->off_status);
   a.shapes = reinterpret_cast<ShapeRec *>(w + s->off_shapes);
-  a.bbox = reinterpret_cast<int4 *>(w + s->off_bbox);
+  a.bins = reinterpret_cast<BinRec *>(w + s->off_bins);
   a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
   a.edges_d = reinterpret_cast<EdgeD *>(w + s->off_edges_d);
   a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
@@ -285,8 +285,8 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + sizeof(int32_t) * kStatusWords);
   s->off_shapes = off;
   off = align256(off + sizeof(ShapeRec) * (size_t)s->N);
-  s->off_bbox = off;
-  off = align256(off + sizeof(int4) * (size_t)s->N);
+  s->off_bins = off;
+  off = align256(off + sizeof(BinRec) * (size_t)s->N);
   s->off_edges = off;
   off = align256(off + sizeof(EdgeRec) * ((size_t)s->V + kEdgePad));
   s->off_edges_d = off;

@@ -37,7 +37,20 @@ struct alignas(16) ShapeRec {
   int32_t open;      // 1: open polyline, sd = sw - d; 0: closed outline, sd = +-d (even-odd)
   double sw;         // open: stroke radius k |s| w in level px
   double sw_ds;      // open: d sw / d s = k w sign(s)
+  double kc, ks;     // k cos(theta), k sin(theta): k R(theta), for d v' / d s of items with |s| < kScaleFloor
 };
+
+// Per item, written by the transform kernel beside its ShapeRec: what binning reads of each candidate
+// item, in one 48-byte record (the support box it tests, and the fields of the unit records it writes).
+struct alignas(16) BinRec {
+  int4 box;        // inclusive pixel box x0, y0, x1, y1 of the coverage support (empty: x1 < x0)
+  int32_t eo;      // first edge record (= first vertex)
+  int32_t ecnv;    // edges (bits 0-15) and vertices (bits 16-31)
+  int32_t flags;   // kUnitOpen, kUnitClockwise
+  float s;         // scale parameter
+  double cx, cy;   // the item's origin k t, level px
+};
+static_assert(sizeof(BinRec) == 48, "bin record size");
 
 // One (tile, item) work unit as the persistent passes read it, written by the binning kernel beside the
 // unit's list entry: a wave loads one record per unit instead of the list entry and then the item's.
@@ -51,7 +64,7 @@ struct alignas(16) UnitRec {
   int32_t xy;      // the unit rectangle (the item's support box clipped to the tile): x0 | y0 << 16
   int32_t wn;      // its width | its pixel count << 16 (w x n / w px)
   int32_t sid;     // the item (an open item's stroke radius is read from its ShapeRec)
-  int32_t pad_;
+  float s;         // the item's scale parameter
   double cx, cy;   // the item's origin (double; the scan uses it rounded to float)
 };
 constexpr int32_t kUnitOpen = 1;
@@ -75,17 +88,18 @@ struct alignas(16) EdgeD {
   double ax, ay;
   double ex, ey;
   double inv_ee;        // 1 / |b - a|^2 (0 for a degenerate edge)
-  double kra_x, kra_y;  // k R(theta) v_a: the unscaled end point a (its derivative with respect to s)
-  double kre_x, kre_y;  // k R(theta) (v_b - v_a)
   double inv_len;       // 1 / |b - a| = sqrt(inv_ee) (0 for a degenerate edge): the unit normal's scale
 };
+// Below this |s| the adjoint takes d v' / d s = k R(theta) v from the item-frame vertices instead of from
+// the transformed nearest point divided by s (whose digits cancel as s goes to 0).
+constexpr double kScaleFloor = 1e-6;
 
 // Status words at the start of the workspace (COLLAGE_STATUS_* of collage.h), zeroed by the transform
 // kernel, which every compute call launches first.
 constexpr int kStatusWords = COLLAGE_STATUS_WORDS;
 constexpr int kPersistWaves = 4;      // waves per workgroup of the persistent kernels
-constexpr int kCoverBlocksPerCU = 6;  // resident workgroups per CU: coverage kernel (LDS and VGPR bound)
-constexpr int kAdjointBlocksPerCU = 4;  // and adjoint kernel (VGPR bound)
+constexpr int kCoverBlocksPerCU = 6;  // resident workgroups per CU: coverage kernel (7 and 8 measured slower)
+constexpr int kAdjointBlocksPerCU = 4;  // and adjoint kernel (5 measured no faster)
 
 // Kernel arguments (one struct, passed by value).
 struct KArgs {
@@ -110,7 +124,7 @@ struct KArgs {
   const float *params;
   // transform outputs
   ShapeRec *shapes;
-  int4 *bbox;            // inclusive pixel box x0, y0, x1, y1 (empty: x1 < x0)
+  BinRec *bins;          // [N] support box and unit fields of each item
   EdgeRec *edges;
   EdgeD *edges_d;
   // binning outputs

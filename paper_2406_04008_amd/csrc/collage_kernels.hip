@@ -61,7 +61,7 @@ __device__ __forceinline__ long long uniform_ll(long long v) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int4 load_box(cptr<int4> p, int i) {
+__device__ __forceinline__ int4 load_box(cptr<BinRec> p, int i) {
   cptr<int> q = (cptr<int>)(p + i);
   return make_int4(q[0], q[1], q[2], q[3]);
 }
@@ -211,7 +211,7 @@ __device__ __forceinline__ int layout_of_tile(cptr<LayoutRec> L, int B, int tile
 typedef float nt_f32x4 __attribute__((ext_vector_type(4)));
 typedef double nt_f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned long long nt_u64x2 __attribute__((ext_vector_type(2)));
-static_assert(sizeof(EdgeRec) == 2 * sizeof(nt_f32x4) && sizeof(EdgeD) == 5 * sizeof(nt_f64x2), "record sizes");
+static_assert(sizeof(EdgeRec) == 2 * sizeof(nt_f32x4) && sizeof(EdgeD) == 3 * sizeof(nt_f64x2), "record sizes");
 
 __device__ __forceinline__ void stream_store(EdgeRec *dst, const EdgeRec &r) {
   const nt_f32x4 *src = reinterpret_cast<const nt_f32x4 *>(&r);
@@ -224,7 +224,7 @@ __device__ __forceinline__ void stream_store(EdgeD *dst, const EdgeD &r) {
   const nt_f64x2 *src = reinterpret_cast<const nt_f64x2 *>(&r);
   nt_f64x2 *d = reinterpret_cast<nt_f64x2 *>(dst);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) __builtin_nontemporal_store(src[i], d + i);
+  for (int i = 0; i < 3; ++i) __builtin_nontemporal_store(src[i], d + i);
 }
 
 __device__ __forceinline__ void place_vertex(double c, double sn, double s, double k, float2 v, double &x, double &y) {
@@ -331,11 +331,6 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     rd.ey = ey;
     rd.inv_ee = inv;
     rd.inv_len = sqrt(inv);
-    // d v' / d s = k R(theta) v for both end points (exact also when s = 0)
-    rd.kra_x = k * (c * (double)va.x - sn * (double)va.y);
-    rd.kra_y = k * (sn * (double)va.x + c * (double)va.y);
-    rd.kre_x = k * (c * (double)vb.x - sn * (double)vb.y) - rd.kra_x;
-    rd.kre_y = k * (sn * (double)vb.x + c * (double)vb.y) - rd.kra_y;
     stream_store(a.edges_d + v0 + m, rd);
     mnx = fmin(mnx, fmin(ax, bx));
     mxx = fmax(mxx, fmax(ax, bx));
@@ -366,7 +361,15 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
       fy1 = fmin(fy1, (double)(H - 1));
       if (fx0 <= fx1 && fy0 <= fy1) box = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
     }
-    a.bbox[sid] = box;
+    BinRec br;
+    br.box = box;
+    br.eo = v0;
+    br.ecnv = ec | (n << 16);
+    br.flags = (open ? kUnitOpen : 0) | (area2 >= 0.0 ? 0 : kUnitClockwise);
+    br.s = p.w;
+    br.cx = cx;
+    br.cy = cy;
+    a.bins[sid] = br;
     ShapeRec sr;
     sr.cx = cx;
     sr.cy = cy;
@@ -382,6 +385,8 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     sr.open = open ? 1 : 0;
     sr.sw = sw;
     sr.sw_ds = sw_ds;
+    sr.kc = k * c;
+    sr.ks = k * sn;
     a.shapes[sid] = sr;
   }
 }
@@ -524,15 +529,18 @@ __device__ __forceinline__ Nearest nearest_refined(const EdgeD *E, int ec, int b
   return n;
 }
 
-// alpha and alpha_pad of one (pixel, item) from its signed distance, with one exponential: for
-// x = sd / tau, e^-(x + r_pad / tau) = e^-x pad_factor.  Wherever either is not cut to zero,
-// x >= -(r_cut + r_pad) / tau, so e^-x does not overflow.
-__device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double &al, double &alp) {
-  al = alp = 0.0;
-  if (sd + (double)a.r_pad < -(double)a.r_cut) return;
-  const double E = exp(-sd * a.inv_tau_d);
-  if (sd >= -(double)a.r_cut) al = 1.0 / (1.0 + E);
-  alp = 1.0 / (1.0 + E * a.pad_factor);
+// alpha and alpha_pad of one (pixel, item) from its signed distance, in float32 with one exponential:
+// for x = sd / tau, e^-(x + r_pad / tau) = e^-x pad_factor.  The distance comes from the double-precision
+// evaluation of the nearest edge; alpha is within a few 1e-7 of its double value (the 1e-5 image bar
+// leaves room for the sum of many), and it is exact in the fixed-point sums.  Wherever either is not cut
+// to zero, x >= -(r_cut + r_pad) / tau, so e^-x does not overflow.  (Measured: 37.8 -> 36.9 us per coverage
+// pass against the double-precision version, which also held 24 more VGPRs.)
+__device__ __forceinline__ void coverage_pair(const KArgs &a, float sd, float &al, float &alp) {
+  al = alp = 0.0f;
+  if (sd + a.r_pad < -a.r_cut) return;
+  const float E = __expf(-sd * a.inv_tau);
+  if (sd >= -a.r_cut) al = __frcp_rn(1.0f + E);
+  alp = __frcp_rn(1.0f + E * (float)a.pad_factor);
 }
 
 // omega = G dalpha/dsd + G_pad dalpha_pad/dsd of one (pixel, item), from one exponential: with
@@ -575,13 +583,40 @@ __device__ __forceinline__ void adjoint_normal(const EdgeD &e, const PairD &q, b
   }
 }
 
+// The scale terms need d q' / d s for the nearest point q' = a' + u (b' - a') of the nearest edge,
+// k R(theta) (v_a + u (v_b - v_a)) with v the item-frame vertices.  Since q' - k t = s k R(theta) (...),
+// that is (r - q) / s, with r = p - k t and q = p - q' (no extra loads); for |s| < kScaleFloor, where the
+// quotient loses its digits, it is formed from the vertices (V: the item's, bi: the edge, nv: vertices).
+struct ScaleDeriv {
+  double inv_s;  // 1 / s, or 0 for |s| < kScaleFloor
+  double kc, ks; // k R(theta) (used when inv_s = 0)
+  const float2 *V;
+  int bi, nv;
+  bool open;
+};
+
+__device__ __forceinline__ void unscaled_point(const ScaleDeriv &sd, const PairD &q, double rx, double ry,
+                                               double &ux, double &uy) {
+  if (sd.inv_s != 0.0) {
+    ux = (rx - q.qx) * sd.inv_s;
+    uy = (ry - q.qy) * sd.inv_s;
+    return;
+  }
+  const int ib = sd.open ? min(sd.bi + 1, sd.nv - 1) : (sd.bi + 1 == sd.nv ? 0 : sd.bi + 1);
+  const float2 va = sd.V[sd.bi], vb = sd.V[ib];
+  const double vx = (double)va.x + q.u * ((double)vb.x - (double)va.x);
+  const double vy = (double)va.y + q.u * ((double)vb.y - (double)va.y);
+  ux = sd.kc * vx - sd.ks * vy;
+  uy = sd.ks * vx + sd.kc * vy;
+}
+
 // Adjoint terms of one (pixel, item): omega * d sd / d(t, theta, s), up to the factor -k of the
 // translation terms applied by the finalize kernel.
 // For an open item (sw_ds != 0 or open) q.sd = sw - d, par is false (the gradient of -d), and the
 // stroke radius adds d sd / d s = sw_ds.
 __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e, const PairD &q, double rx, double ry,
                                                  bool par, float orient, double G, double Gp, bool open,
-                                                 double sw_ds) {
+                                                 double sw_ds, const ScaleDeriv &sdv) {
   const double om = adjoint_omega(a, q.sd, G, Gp);
   double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
   if (om == 0.0) return t;
@@ -593,8 +628,10 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
   t.x = om * nx;
   t.y = om * ny;
   t.z = om * (nx * ry - ny * rx);
-  // d sd / d s = -n . (k R (v_a + u (v_b - v_a))): the nearest point of the unscaled outline
-  t.w = stroke_term - om * (nx * (e.kra_x + q.u * e.kre_x) + ny * (e.kra_y + q.u * e.kre_y));
+  // d sd / d s = -n . (d q' / d s): the nearest point of the unscaled outline
+  double ux, uy;
+  unscaled_point(sdv, q, rx, ry, ux, uy);
+  t.w = stroke_term - om * (nx * ux + ny * uy);
   return t;
 }
 
@@ -611,7 +648,7 @@ __device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1,
     const int sid = pos < ce ? (src ? src[pos] : pos) : 0;
     bool hit = false;
     if (pos < ce) {
-      const int4 bb = a.bbox[sid];
+      const int4 bb = a.bins[sid].box;
       // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
       hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x1 || bb.z < x0 || bb.y > y1 || bb.w < y0);
     }
@@ -848,7 +885,6 @@ __global__ __launch_bounds__(256) void k_rowbin(KArgs a) {
 template <int T>
 __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64;
-  __shared__ int s_list[kMaxBinChunk];
   __shared__ int s_wcnt[NW];
   // the first kMaxBinChunk units' item, chunks and cost, for the prefix pass below (later units of a
   // tile that lists more items are read back from global memory)
@@ -871,43 +907,63 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   }
   int slots = 0;
   long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
-  // candidates: every item of the layout, or the items listed for the tile's row
+  // candidates: every item of the layout, or the items listed for the tile's row.  Each thread loads its
+  // candidate's whole bin record with the box it tests, so that a hit's unit record needs no further
+  // load: the thread writes it at the item's slot in the tile list.
   const int32_t *src = a.rowbin ? a.row_list + LS[b].row_list_off + (int64_t)tyi * nb : nullptr;
   const int c0 = a.rowbin ? 0 : sb, c1 = a.rowbin ? a.row_count[LS[b].row_off + tyi] : se;
-  for (int cb = c0; cb < c1; cb += a.bin_chunk) {
-    const int ce = min(cb + a.bin_chunk, c1);
-    const int cnt = bin_chunk<NT>(a, cb, ce, x0, y0, x0 + T - 1, y0 + T - 1, s_list, s_wcnt, a.tile_list + list_base + slots,
-                                  src);
-    for (int q = tid; q < cnt; q += NT) {
-      const int sid = s_list[q];
-      const Rect r = unit_rect(a.bbox[sid], x0, y0, T);
+  const int w = tid >> 6, l = tid & 63;
+  for (int base = c0; base < c1; base += NT) {
+    const int pos = base + tid;
+    const int sid = pos < c1 ? (src ? src[pos] : pos) : 0;
+    BinRec br;
+    bool hit = false;
+    if (pos < c1) {
+      br = a.bins[sid];
+      const int4 bb = br.box;
+      // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
+      hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x0 + T - 1 || bb.z < x0 || bb.y > y0 + T - 1 || bb.w < y0);
+    }
+    const unsigned long long m = __ballot(hit);
+    const int before = __popcll(m & ((1ull << l) - 1ull));
+    if (l == 0) s_wcnt[w] = __popcll(m);
+    __syncthreads();
+    int off = slots, tot = slots;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int cj = s_wcnt[j];
+      if (j < w) off += cj;
+      tot += cj;
+    }
+    if (hit) {
+      const int slot = off + before;
+      const Rect r = unit_rect(br.box, x0, y0, T);
       const int chunks = (r.n + 63) >> 6;
-      {
-        const ShapeRec &sr = a.shapes[sid];
-        UnitRec u;
-        u.eo = sr.edge_off;
-        u.ecnv = sr.edge_cnt | ((a.vert_off[sid + 1] - a.vert_off[sid]) << 16);
-        u.flags = (sr.open ? kUnitOpen : 0) | (sr.orient < 0.0f ? kUnitClockwise : 0);
-        u.head = (int32_t)(LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt);
-        u.xy = r.x0 | (r.y0 << 16);
-        u.wn = r.w | (r.n << 16);
-        u.sid = sid;
-        u.pad_ = 0;
-        u.cx = sr.cx;
-        u.cy = sr.cy;
-        a.units[list_base + slots + q] = u;
-      }
-      const int cpc = a.shapes[sid].edge_cnt + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
-      a.entry_aux[list_base + slots + q] = make_int4(chunks, cpc, 0, 0);
-      if (slots + q < kMaxBinChunk) {
-        s_usid[slots + q] = sid;
-        s_uch[slots + q] = chunks;
-        s_ucost[slots + q] = chunks * cpc;
+      const int ec = br.ecnv & 0xffff;
+      UnitRec u;
+      u.eo = br.eo;
+      u.ecnv = br.ecnv;
+      u.flags = br.flags;
+      u.head = (int32_t)(LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt);
+      u.xy = r.x0 | (r.y0 << 16);
+      u.wn = r.w | (r.n << 16);
+      u.sid = sid;
+      u.s = br.s;
+      u.cx = br.cx;
+      u.cy = br.cy;
+      a.units[list_base + slot] = u;
+      a.tile_list[list_base + slot] = sid;
+      const int cpc = ec + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
+      a.entry_aux[list_base + slot] = make_int4(chunks, cpc, 0, 0);
+      if (slot < kMaxBinChunk) {
+        s_usid[slot] = sid;
+        s_uch[slot] = chunks;
+        s_ucost[slot] = chunks * cpc;
       }
       my_cost += (long long)chunks * cpc;
       my_quads += chunks;
     }
-    slots += cnt;
+    slots = tot;
     __syncthreads();
   }
   // chunks and coverage cost of the tile's earlier units, per unit (first wave, 64 units at a time)
@@ -1033,19 +1089,37 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// The scan from LDS.  A wave stages the edge records of its current item in its own LDS slice with
-// coalesced vector loads (items with more than kStageEdges edges go through in segments), then every
-// lane reads each record with a broadcast LDS load.  LDS loads of a wave complete in order, so the next
-// records can be in flight while the current ones are used, which the scalar cache could not sustain
-// (most of its edge fetches missed).  The parity of the crossings and the ordinate test that the
-// next edge shares with this one (b_y of edge e is a_y of edge e + 1, the same float) are kept as
-// wave-wide lane masks in scalar registers.
+// The scan from LDS.  A wave stages the edges of its current item in its own LDS slice (items with more
+// than kStageEdges edges go through in segments), packed to kEdgeFloats floats per edge, then every lane
+// reads each group of four edges with kEdgeFloats broadcast 16-byte LDS loads.  LDS loads of a wave
+// complete in order, so the next records can be in flight while the current ones are used, which the
+// scalar cache could not sustain (most of its edge fetches missed).  The parity of the crossings is kept
+// as wave-wide lane masks in scalar registers.  An edge's crossing needs the ordinate tests of both its
+// end points: that of its b is the next edge's a (the same float), so each edge's crossing is folded in
+// when the next edge is read (the last edge's b is vertex 0).
 // ------------------------------------------------------------------------------------------------
-constexpr int kStageSlots = 2 * kStageEdges + 8;  // float4 slots per wave (+8: the scan reads ahead)
+// Per staged edge: a_x, a_y, e_x / |e|^2, e_y / |e|^2, e_x, e_y, e_x / e_y (b_y is the next edge's a_y).
+// Measured at 512^2 with 500 items: 37.9 us per coverage pass against 39.7 us for the 8 floats of the
+// global record, and 40.6 us for 6 floats with the crossing decided by the sign of a cross product
+// (one more VALU operation per edge for a quarter fewer LDS bytes).
+constexpr int kEdgeFloats = 7;
+// float4 slots per wave: kStageEdges packed edges and one group of four of read-ahead
+constexpr int kStageSlots = kEdgeFloats * (kStageEdges / 4 + 1);
 
 __device__ __forceinline__ void stage_edges(const EdgeRec *E, int ne, float4 *dst, int lane) {
+  float *D = reinterpret_cast<float *>(dst);
   const float4 *src = reinterpret_cast<const float4 *>(E);
-  for (int i = lane; i < 2 * ne; i += 64) dst[i] = src[i];
+  for (int i = lane; i < ne; i += 64) {
+    const float4 r0 = src[2 * i], r1 = src[2 * i + 1];
+    float *d = D + kEdgeFloats * i;
+    d[0] = r0.x;
+    d[1] = r0.y;
+    d[2] = r0.z;
+    d[3] = r0.w;
+    d[4] = r1.x;
+    d[5] = r1.y;
+    d[6] = r1.w;
+  }
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -1053,37 +1127,51 @@ struct ScanState {
   unsigned best;            // bits of the smallest squared distance so far (see scan_group)
   int grp;                  // first edge of the earliest group of four edges that holds it
   unsigned long long par;   // lanes with an odd number of crossings so far
-  unsigned long long up;    // lanes whose ordinate test holds for the current vertex
+  unsigned long long up;    // lanes with a_y > r_y for the last edge read
+  unsigned long long left;  // the last edge's x-intercept test, for lanes whose row it may cross
+  unsigned long long up0;   // lanes with a_y > r_y for edge 0 (b of the last edge)
 };
 
+// S: the staged edges from edge 0 (float index 1 is a_y of edge 0).
 __device__ __forceinline__ void scan_start(ScanState &st, const float4 *S, float ry) {
   st.best = __float_as_uint(INFINITY);
   st.grp = 0;
   st.par = 0ull;
-  st.up = __ballot(S[0].y > ry);  // a_y of the item's first edge
+  st.up = 0ull;
+  st.left = 0ull;
+  st.up0 = __ballot(S[0].y > ry);
 }
 
-// Squared distance (float) from (rx, ry) to the edge of records r0 = (a_x, a_y, e_x / |e|^2, e_y / |e|^2),
-// r1 = (e_x, e_y, b_y, e_x / e_y).  The scan and the re-decision of the nearest edge both use this one
-// sequence, so they produce the same bits.
-__device__ __forceinline__ float edge_d2(const float4 r0, const float4 r1, float rx, float ry) {
-  const float wx = rx - r0.x, wy = ry - r0.y;
-  const float t = fmaf(wx, r0.z, wy * r0.w);
+// Squared distance (float) from (rx, ry) to the edge (a_x, a_y) + u (e_x, e_y), u clamped to [0, 1], with
+// (e_xs, e_ys) = e / |e|^2.  The scan and the re-decision of the nearest edge both use this one sequence,
+// so they produce the same bits.
+__device__ __forceinline__ float edge_d2(float ax, float ay, float exs, float eys, float ex, float ey, float rx,
+                                         float ry) {
+  const float wx = rx - ax, wy = ry - ay;
+  const float t = fmaf(wx, exs, wy * eys);
   const float u = __builtin_amdgcn_fmed3f(t, 0.0f, 1.0f);
-  const float qx = fmaf(-u, r1.x, wx), qy = fmaf(-u, r1.y, wy);
+  const float qx = fmaf(-u, ex, wx), qy = fmaf(-u, ey, wy);
   return fmaf(qx, qx, qy * qy);
 }
 
-// One edge of the scan: its squared distance, and its crossing of the ray from the pixel towards +x
-// folded into the parity mask (half-open rule on the vertex ordinates, shared with the next edge).
-__device__ __forceinline__ float scan_edge(const float4 r0, const float4 r1, float rx, float ry, ScanState &st) {
-  const float d2 = edge_d2(r0, r1, rx, ry);
-  const unsigned long long up_b = __ballot(r1.z > ry);
-  const unsigned long long left = __ballot(rx - r0.x < (ry - r0.y) * r1.w);
-  st.par ^= (st.up ^ up_b) & left;
-  st.up = up_b;
+// One staged edge f[0..kEdgeFloats): its squared distance; the crossing of the previous edge (whose b_y is
+// this edge's a_y) folded into the parity; this edge's x-intercept test, r_x - a_x < (r_y - a_y) e_x / e_y,
+// kept for the next edge.
+__device__ __forceinline__ float scan_edge(const float *f, float rx, float ry, ScanState &st) {
+  const float wx = rx - f[0], wy = ry - f[1];
+  const float t = fmaf(wx, f[2], wy * f[3]);
+  const float u = __builtin_amdgcn_fmed3f(t, 0.0f, 1.0f);
+  const float qx = fmaf(-u, f[4], wx), qy = fmaf(-u, f[5], wy);
+  const float d2 = fmaf(qx, qx, qy * qy);
+  const unsigned long long up = __ballot(wy < 0.0f);  // a_y > r_y (the subtraction's sign is exact)
+  st.par ^= (st.up ^ up) & st.left;
+  st.left = __ballot(wx < wy * f[6]);
+  st.up = up;
   return d2;
 }
+
+// The last edge's crossing (its b is vertex 0).
+__device__ __forceinline__ void scan_finish(ScanState &st) { st.par ^= (st.up ^ st.up0) & st.left; }
 
 // The minimum of a group of four edges (first edge e) enters the running minimum; strict comparison,
 // so the earliest group holding the minimum is kept.  Squared distances are never negative, so their
@@ -1095,37 +1183,66 @@ __device__ __forceinline__ void scan_group(float d0, float d1, float d2, float d
   st.best = min(st.best, g);
 }
 
-// Edges [0, ne) of the staged slice S, numbered from ebase.  Each step loads four records' worth of
-// LDS slots at once and evaluates them as they arrive (LDS loads complete in order); the other waves
-// of the SIMD cover the remaining latency.  Reads up to eight slots past 2 ne.
+// Edges [0, ne) of the staged slice S, numbered from ebase.  Each step loads a group of four edges
+// (kEdgeFloats slots) at once and evaluates them as they arrive; the other waves of the SIMD cover the
+// remaining latency.  Reads up to one group past ne.
 __device__ __forceinline__ void scan_lds(const float4 *S, int ne, int ebase, float rx, float ry, ScanState &st) {
   int e = 0;
   for (; e + 4 <= ne; e += 4) {
-    const float4 *R = S + 2 * e;
-    const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
-    const float d0 = scan_edge(r0, r1, rx, ry, st);
-    const float d1 = scan_edge(r2, r3, rx, ry, st);
-    const float d2 = scan_edge(r4, r5, rx, ry, st);
-    const float d3 = scan_edge(r6, r7, rx, ry, st);
+    const float4 *R = S + (kEdgeFloats * e) / 4;
+    float f[4 * kEdgeFloats];
+#pragma unroll
+    for (int k = 0; k < kEdgeFloats; ++k) {
+      const float4 r = R[k];
+      f[4 * k] = r.x;
+      f[4 * k + 1] = r.y;
+      f[4 * k + 2] = r.z;
+      f[4 * k + 3] = r.w;
+    }
+    const float d0 = scan_edge(f, rx, ry, st);
+    const float d1 = scan_edge(f + kEdgeFloats, rx, ry, st);
+    const float d2 = scan_edge(f + 2 * kEdgeFloats, rx, ry, st);
+    const float d3 = scan_edge(f + 3 * kEdgeFloats, rx, ry, st);
     scan_group(d0, d1, d2, d3, ebase + e, st);
   }
   if (e < ne) {
-    const float4 *R = S + 2 * e;
-    const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
-    const float d0 = scan_edge(r0, r1, rx, ry, st);
-    const float d1 = e + 1 < ne ? scan_edge(r2, r3, rx, ry, st) : INFINITY;
-    const float d2 = e + 2 < ne ? scan_edge(r4, r5, rx, ry, st) : INFINITY;
+    const float4 *R = S + (kEdgeFloats * e) / 4;
+    float f[4 * kEdgeFloats];
+#pragma unroll
+    for (int k = 0; k < kEdgeFloats; ++k) {
+      const float4 r = R[k];
+      f[4 * k] = r.x;
+      f[4 * k + 1] = r.y;
+      f[4 * k + 2] = r.z;
+      f[4 * k + 3] = r.w;
+    }
+    const float d0 = scan_edge(f, rx, ry, st);
+    const float d1 = e + 1 < ne ? scan_edge(f + kEdgeFloats, rx, ry, st) : INFINITY;
+    const float d2 = e + 2 < ne ? scan_edge(f + 2 * kEdgeFloats, rx, ry, st) : INFINITY;
     scan_group(d0, d1, d2, INFINITY, ebase + e, st);
   }
 }
 
 // The nearest edge within the winning group: the first of its edges (at most four, up to ec) whose
 // recomputed squared distance equals the scan's minimum, i.e. the first edge of the whole outline that
-// attains it.  R holds the item's records from edge 0 (LDS stage or global).
-__device__ __forceinline__ int scan_resolve(const float4 *R, int grp, int ec, float rx, float ry, unsigned best) {
+// attains it.  From the staged slice (S, packed) or from the item's global records (E).
+__device__ __forceinline__ int scan_resolve_lds(const float4 *S, int grp, int ec, float rx, float ry, unsigned best) {
+  const float *D = reinterpret_cast<const float *>(S);
   int bi = grp;
-  for (int j = min(grp + 3, ec - 1); j >= grp; --j)
-    if (__float_as_uint(edge_d2(R[2 * j], R[2 * j + 1], rx, ry)) == best) bi = j;
+  for (int j = min(grp + 3, ec - 1); j >= grp; --j) {
+    const float *f = D + kEdgeFloats * j;
+    if (__float_as_uint(edge_d2(f[0], f[1], f[2], f[3], f[4], f[5], rx, ry)) == best) bi = j;
+  }
+  return bi;
+}
+
+__device__ __forceinline__ int scan_resolve_global(const EdgeRec *E, int grp, int ec, float rx, float ry,
+                                                   unsigned best) {
+  int bi = grp;
+  for (int j = min(grp + 3, ec - 1); j >= grp; --j) {
+    const EdgeRec &r = E[j];
+    if (__float_as_uint(edge_d2(r.ax, r.ay, r.exs, r.eys, r.ex, r.ey, rx, ry)) == best) bi = j;
+  }
   return bi;
 }
 
@@ -1137,7 +1254,7 @@ __device__ __forceinline__ void scan_item(const EdgeRec *E, int ec, bool staged,
   if (staged) {
     scan_start(st, S, ry);
     scan_lds(S, ec, 0, rx, ry, st);
-    bi = scan_resolve(S, st.grp, ec, rx, ry, st.best);
+    bi = scan_resolve_lds(S, st.grp, ec, rx, ry, st.best);
   } else {
     for (int e0 = 0; e0 < ec; e0 += kStageEdges) {
       const int ne = min(kStageEdges, ec - e0);
@@ -1145,8 +1262,9 @@ __device__ __forceinline__ void scan_item(const EdgeRec *E, int ec, bool staged,
       if (e0 == 0) scan_start(st, S, ry);
       scan_lds(S, ne, e0, rx, ry, st);
     }
-    bi = scan_resolve(reinterpret_cast<const float4 *>(E), st.grp, ec, rx, ry, st.best);
+    bi = scan_resolve_global(E, st.grp, ec, rx, ry, st.best);
   }
+  scan_finish(st);
   par = ((st.par >> lane) & 1ull) != 0ull;
 }
 
@@ -1170,6 +1288,8 @@ struct UnitView {
   double cx, cy;
   float cxf, cyf;
   double sw, sw_ds;  // an open item's stroke radius and its derivative in s (0 for a closed item)
+  double inv_s;      // 1 / s (0 when |s| < kScaleFloor)
+  double kc, ks;     // k R(theta), loaded only when |s| < kScaleFloor
 };
 
 __device__ __forceinline__ UnitView unit_view(const KArgs &a, cptr<UnitRec> U) {
@@ -1191,10 +1311,20 @@ __device__ __forceinline__ UnitView unit_view(const KArgs &a, cptr<UnitRec> U) {
   v.cyf = (float)v.cy;
   v.sw = 0.0;
   v.sw_ds = 0.0;
+  cptr<ShapeRec> SR = konst(a.shapes) + U->sid;
   if (v.open) {
-    cptr<ShapeRec> SR = konst(a.shapes) + U->sid;
     v.sw = SR->sw;
     v.sw_ds = SR->sw_ds;
+  }
+  const double s = (double)U->s;
+  v.inv_s = 0.0;
+  v.kc = 0.0;
+  v.ks = 0.0;
+  if (fabs(s) >= kScaleFloor) {
+    v.inv_s = 1.0 / s;
+  } else {
+    v.kc = SR->kc;
+    v.ks = SR->ks;
   }
   return v;
 }
@@ -1299,12 +1429,12 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
         const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
         bi = nr.e;
         if (in) {
-          const double d = sqrt(nr.d2);
-          double al, alp;
-          coverage_pair(a, open ? sw - d : (par ? d : -d), al, alp);
+          const float d = sqrtf((float)nr.d2);
+          float al, alp;
+          coverage_pair(a, open ? (float)sw - d : (par ? d : -d), al, alp);
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
-          if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
-          if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
+          if (al > 0.0f) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint((double)al * kFixScale));
+          if (alp > 0.0f) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint((double)alp * kFixScale));
         }
       }
       if (a.keep_codes && q + j < a.code_cap) a.codes[(q + j) * 64 + lane] = (uint16_t)(bi | (par ? 0x8000 : 0));
@@ -1657,7 +1787,11 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
-  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
+  bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg);
+  // every wave writes its spill slot: zero (right away, off the end of the kernel's path) when its share
+  // is empty or begins at a unit's first chunk
+  if ((!ok || wk.jlo == 0) && lane == 0) a.spill[gw] = make_double4(0.0, 0.0, 0.0, 0.0);
+  for (; ok; ok = walk_next(a, wk, T)) {
     const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
@@ -1668,6 +1802,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
     const double sw = uv.sw, sw_ds = uv.sw_ds;
     // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
+    ScaleDeriv sdv = {uv.inv_s, uv.kc, uv.ks, reinterpret_cast<const float2 *>(a.verts) + eo, 0, uv.nv, open};
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
     if (q + wk.jhi <= a.code_cap) {
       // every chunk of the piece has its nearest-edge codes: a three-stage pipeline over the chunks
@@ -1698,7 +1833,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           const bool par = !open && (c_cur & 0x8000u) != 0u;
           PairD pr = pair_eval(e_cur, rx, ry, par);
           if (open) pr.sd = sw - pr.d;
-          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y, open, sw_ds);
+          sdv.bi = (int)(c_cur & 0x7fffu);
+          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y, open, sw_ds, sdv);
           acc.x += t.x;
           acc.y += t.y;
           acc.z += t.z;
@@ -1736,7 +1872,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           if (open) par = false;
           PairD pr = pair_eval(e, rx, ry, par);
           if (open) pr.sd = sw - pr.d;
-          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y, open, sw_ds);
+          sdv.bi = bi;
+          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y, open, sw_ds, sdv);
           acc.x += t.x;
           acc.y += t.y;
           acc.z += t.z;
@@ -1914,10 +2051,18 @@ __device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g,
   return make_float4(pp[0], pp[1], pp[2], pp[3]);
 }
 
-// The adjoint's waves split the pass's chunks in equal shares: wave w starts at chunk ceil(w tot / W).
-__device__ __forceinline__ long long adjoint_share(long long tot, long long w, long long W) {
-  return (w * tot + W - 1) / W;
+// The adjoint's waves split the pass's chunks in equal shares: wave w's share begins at chunk
+// ceil(w tot / W) (share_bound without taper).  The first wave whose share begins after chunk c: the
+// least w with w tot > c W, from the quotient in double (c W < 2^53) corrected exactly in integers.
+__device__ __forceinline__ long long first_wave_after(long long c, long long W, long long tot, double w_per_chunk) {
+  const long long n = c * W;
+  long long w = (long long)((double)c * w_per_chunk) + 1;
+  while (w > 0 && (w - 1) * tot > n) --w;
+  while (w * tot <= n) ++w;
+  return w;
 }
+
+constexpr int kSpillBatch = 4;  // spill loads an update lane issues together
 
 // ADAM: update the parameters; XFORM (with ADAM): transform the items with the updated parameters.
 // The loads of the update and of the transform are issued first and consumed last, so that they are in
@@ -1933,7 +2078,7 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = a.num_layouts == 1 ? 0 : uniform(SR[sid].layout);  // scalar: the layout's fields are scalar loads
   const float k = LS[b].k;
-  const int4 bb = load_box(konst(a.bbox), sid);
+  const int4 bb = load_box(konst(a.bins), sid);
   const int bad = a.shapes[sid].bad;  // loaded with the others, consumed by lane 0 at the end
   AdamIn ain;
   // every lane (one request): no branch around the loads
@@ -1948,13 +2093,13 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
   const long long tot = uniform_ll(a.tile_pre[(a.total_tiles + 1) + a.total_tiles]);  // chunks of the pass
   const long long W = (long long)a.adjoint_grid * kPersistWaves;
+  const double wpc = (double)W / (double)(tot > 0 ? tot : 1);  // waves per chunk
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
   if (bb.x <= bb.z && bb.y <= bb.w) {
     // every tile that the support box meets lists the item, and its unit there has at least one chunk.
-    // Per unit (one per lane): the head partial, then the spills of the waves whose share begins inside
-    // the unit's chunks [c0, c1), in wave order: waves w with c0 < ceil(w tot / W) < c1 and a non-empty
-    // share.  The head and the unit's map entry share an index, so all of a lane's first loads are
-    // independent.
+    // Per unit (one per lane): the head partial, then the spill slots of the waves whose share begins
+    // inside the unit's chunks [c0, c1), in wave order: waves w with c0 < ceil(w tot / W) < c1.  The head
+    // and the unit's map entry share an index, so all of a lane's first loads are independent.
     const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
     for (int r0 = 0; r0 < nt; r0 += 64) {
@@ -1968,15 +2113,21 @@ __device__ void finalize_grad(const KArgs &a, int per) {
         acc.y += h.y;
         acc.z += h.z;
         acc.w += h.w;
-        for (long long w = c0 * W / tot + 1; w < W; ++w) {
-          const long long bw = adjoint_share(tot, w, W);
-          if (bw >= c1) break;
-          if (adjoint_share(tot, w + 1, W) > bw) {
-            const double4 sp = a.spill[w];
-            acc.x += sp.x;
-            acc.y += sp.y;
-            acc.z += sp.z;
-            acc.w += sp.w;
+        // the waves whose share begins inside the unit: [w0, w1), each slot holding its first piece's
+        // sums or zero; loaded kSpillBatch at a time and added in wave order
+        const long long w0 = first_wave_after(c0, W, tot, wpc);
+        const long long w1 = min(first_wave_after(c1 - 1, W, tot, wpc), W);
+        for (long long w = w0; w < w1; w += kSpillBatch) {
+          double4 sp[kSpillBatch];
+#pragma unroll
+          for (int k = 0; k < kSpillBatch; ++k)
+            sp[k] = w + k < w1 ? a.spill[w + k] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+          for (int k = 0; k < kSpillBatch; ++k) {
+            acc.x += sp[k].x;
+            acc.y += sp[k].y;
+            acc.z += sp[k].z;
+            acc.w += sp[k].w;
           }
         }
       }
@@ -2094,8 +2245,8 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
   const int pix = blockIdx.x * 256 + threadIdx.x;
   if (pix >= W * H) return;
   const int pxi = pix % W, pyi = pix / W;
-  const int4 bb = load_box(konst(a.bbox), q);
-  double al = 0.0, alp = 0.0;
+  const int4 bb = load_box(konst(a.bins), q);
+  float al = 0.0f, alp = 0.0f;
   const int eo = SR[q].edge_off, ec = SR[q].edge_cnt;
   if (ec > 0 && pxi >= bb.x && pxi <= bb.z && pyi >= bb.y && pyi <= bb.w) {
     int bi;
@@ -2103,11 +2254,11 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
     edge_scan(konst(a.edges) + eo, ec, pxi + 0.5f - SR[q].cxf, pyi + 0.5f - SR[q].cyf, bi, par);
     const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
     const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
-    const double d = sqrt(nr.d2);
-    coverage_pair(a, SR[q].open ? SR[q].sw - d : (par ? d : -d), al, alp);
+    const float d = sqrtf((float)nr.d2);
+    coverage_pair(a, SR[q].open ? (float)SR[q].sw - d : (par ? d : -d), al, alp);
   }
-  alpha[off + pix] = (float)al;
-  if (alpha_pad) alpha_pad[off + pix] = (float)alp;
+  alpha[off + pix] = al;
+  if (alpha_pad) alpha_pad[off + pix] = alp;
 }
 
 // ------------------------------------------------------------------------------------------------
