@@ -33,6 +33,9 @@ class LaunchConfig:
 
 
 DEFAULT_SPACE = [LaunchConfig(t, c, 0) for t, c in itertools.product((8, 16, 32), (-1, 0))]
+# candidates whose workspace exceeds this are not tried: the tile lists hold a slot per (tile, item), so
+# small tiles on large canvases with many items need workspaces that grow with canvas area x items
+MAX_WORKSPACE_BYTES = 8 << 30
 
 _CACHE: Dict[str, Tuple[LaunchConfig, Dict[str, float]]] = {}
 
@@ -72,10 +75,16 @@ def time_config(scene: Scene, level: Optional[int], cfg: LaunchConfig, epochs: i
     return times[len(times) // 2]
 
 
+def workspace_bytes(scene: Scene, level: Optional[int], cfg: LaunchConfig, device="cuda") -> int:
+    """The workspace a configuration needs, without allocating it."""
+    return CollageScene(scene, level=level, device=device, allocate_workspace=False, **cfg.scene_kwargs()).workspace_bytes
+
+
 def tune(scene: Scene, level: Optional[int] = None, space: Optional[Iterable[LaunchConfig]] = None,
          epochs: int = 20, repeats: int = 3, device="cuda", cache_path: Optional[str] = None,
-         force: bool = False) -> Tuple[LaunchConfig, Dict[str, float]]:
-    """Fastest configuration of `space` for `scene` at `level`, and the time (ms/epoch) of every one."""
+         force: bool = False, max_workspace_bytes: int = MAX_WORKSPACE_BYTES) -> Tuple[LaunchConfig, Dict[str, float]]:
+    """Fastest configuration of `space` for `scene` at `level`, and the time (ms/epoch) of every one tried
+    (candidates needing more than `max_workspace_bytes` of workspace are skipped)."""
     key = _key(scene, level, device)
     if not force:
         if key in _CACHE:
@@ -90,12 +99,14 @@ def tune(scene: Scene, level: Optional[int] = None, space: Optional[Iterable[Lau
     times: Dict[str, float] = {}
     best, best_t = None, float("inf")
     for cfg in (DEFAULT_SPACE if space is None else list(space)):
+        if workspace_bytes(scene, level, cfg, device) > max_workspace_bytes:
+            continue
         t = time_config(scene, level, cfg, epochs=epochs, repeats=repeats, device=device)
         times[json.dumps(asdict(cfg), sort_keys=True)] = t
         if t < best_t:
             best, best_t = cfg, t
     if best is None:
-        raise ValueError("empty search space")
+        raise ValueError("empty search space (or every candidate's workspace above max_workspace_bytes)")
     _CACHE[key] = (best, times)
     if cache_path:
         disk = {}

@@ -39,7 +39,8 @@ class CollageScene:
     """One level of a batch of layouts, resident on one GPU."""
 
     def __init__(self, scene: Scene, level: Optional[int] = None, device="cuda", tile: int = 0,
-                 code_capacity: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None):
+                 code_capacity: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None,
+                 allocate_workspace: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("CollageScene needs a GPU (the HIP library has no CPU path)")
         self.lib = _lib.load()
@@ -92,7 +93,9 @@ class CollageScene:
         npx, nt = ctypes.c_int64(), ctypes.c_int64()
         _lib.check(self.lib.collage_scene_info(self.handle, ctypes.byref(npx), ctypes.byref(nt)), "collage_scene_info")
         self.num_pixels, self.num_tiles = int(npx.value), int(nt.value)
-        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+        # allocate_workspace=False: only the size (for callers that decide on it), no compute calls
+        self.workspace = (torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+                          if allocate_workspace else None)
         self.tile = tile if tile else 16
 
     def __del__(self):
@@ -103,6 +106,8 @@ class CollageScene:
 
     # ------------------------------------------------------------------------------------------
     def _ws(self):
+        if self.workspace is None:
+            raise RuntimeError("this CollageScene was created without a workspace")
         return _ptr(self.workspace), self.workspace.numel()
 
     def status(self, stream=None) -> np.ndarray:

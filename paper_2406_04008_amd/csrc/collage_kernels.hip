@@ -112,6 +112,72 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 // The sum over a wave's 64 lanes (every lane active), broadcast to all of them.
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
+// DPP controls whose source lane always exists: the partner across lane bit 0 or bit 1 within a quad
+// (quad permutations [1,0,3,2] and [2,3,0,1]), and rotations by 4 and 8 lanes within a row of 16.
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowRor4 = 0x124, kRowRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return __longlong_as_double((long long)dpp_u64<CTRL, 0xf>(b, b));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Wave sums of several values at once (every lane active), in a fixed order.  Each lane gives half of
+// its values to the partner across lane bit 0 and adds the other half from it, then the same across
+// bit 1, so that from there on it sums a quarter of the values: over the 16 lanes of the same quad
+// position, by two rotations within each row of 16 and two exchanges across rows.  Four values cost
+// about a quarter of the instructions of four full reductions.
+// wave_sum4: lane l ends with the total of component comp = 2 (l & 1) + ((l >> 1) & 1) of (x, y, z, w)
+// (lanes 0, 1, 2, 3 hold x, z, y, w).
+__device__ __forceinline__ double wave_sum4(double4 v, int &comp) {
+  const int lane = threadIdx.x & 63;
+  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0;
+  double k0 = o1 ? v.z : v.x, k1 = o1 ? v.w : v.y;  // kept: (x, y) on even lanes, (z, w) on odd ones
+  k0 += dpp_f64<kQuadXor1>(o1 ? v.x : v.z);          // the partner's share of what this lane keeps
+  k1 += dpp_f64<kQuadXor1>(o1 ? v.y : v.w);
+  double m = o2 ? k1 : k0;
+  m += dpp_f64<kQuadXor2>(o2 ? k0 : k1);
+  m += dpp_f64<kRowRor4>(m);
+  m += dpp_f64<kRowRor8>(m);
+  m += __shfl_xor(m, 16, 64);
+  m += __shfl_xor(m, 32, 64);
+  comp = (o1 ? 2 : 0) + (o2 ? 1 : 0);
+  return m;
+}
+
+// wave_sum8: lane l ends with the totals of components c0 = 4 (l & 1) + 2 ((l >> 1) & 1) and c0 + 1 of v
+// (lanes 0-3 hold all eight).
+__device__ __forceinline__ double2 wave_sum8(const double (&v)[8], int &c0) {
+  const int lane = threadIdx.x & 63;
+  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0;
+  double k[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    k[i] = o1 ? v[i + 4] : v[i];
+    k[i] += dpp_f64<kQuadXor1>(o1 ? v[i] : v[i + 4]);
+  }
+  double m0 = o2 ? k[2] : k[0], m1 = o2 ? k[3] : k[1];
+  m0 += dpp_f64<kQuadXor2>(o2 ? k[0] : k[2]);
+  m1 += dpp_f64<kQuadXor2>(o2 ? k[1] : k[3]);
+  m0 += dpp_f64<kRowRor4>(m0);
+  m1 += dpp_f64<kRowRor4>(m1);
+  m0 += dpp_f64<kRowRor8>(m0);
+  m1 += dpp_f64<kRowRor8>(m1);
+  m0 += __shfl_xor(m0, 16, 64);
+  m1 += __shfl_xor(m1, 16, 64);
+  m0 += __shfl_xor(m0, 32, 64);
+  m1 += __shfl_xor(m1, 32, 64);
+  c0 = (o1 ? 4 : 0) + (o2 ? 2 : 0);
+  return make_double2(m0, m1);
+}
+
 __device__ __forceinline__ unsigned long long readlane63_u64(unsigned long long v) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
@@ -692,6 +758,7 @@ struct Walk {
   long long p, end;        // cost prefix of the current unit (in this pass); end of the wave's range
   long long q0;            // first chunk of the tile
   const long long *Q;      // [tiles + 1] chunk prefix of the tiles (LDS or global)
+  const int *C;            // [tiles] units per tile (LDS), or null: tile_count in global memory
   int4 aux;                // (chunks, cost per chunk, chunks and cost of the tile's earlier units) of the unit
   int jlo, jhi;            // the wave's chunks [jlo, jhi) of the current unit
   bool adj;
@@ -714,7 +781,7 @@ __device__ __forceinline__ void walk_tile(const KArgs &a, Walk &w, int T) {
   w.y0 = tyi * T;
   w.pix_off = LS[b].pix_off;
   w.list_base = LS[b].list_off + (int64_t)lt * nb;
-  w.count = konst(a.tile_count)[w.tile];
+  w.count = w.C != nullptr ? uniform(w.C[w.tile]) : konst(a.tile_count)[w.tile];
   w.q0 = uniform_ll(w.Q[w.tile]);
 }
 
@@ -763,6 +830,32 @@ __device__ __forceinline__ int wave_last_le(int n, long long x, F val) {
   return uniform(lo);
 }
 
+// The last unit i in [0, n) of a tile (n >= 1) whose prefix within the tile (entry_aux .z: chunks, for the
+// adjoint passes; .w: cost, for the coverage pass) is <= x, found as wave_last_le finds it, with that
+// unit's entry_aux: the last round loads consecutive entries, so the winner's whole record is in one
+// lane and needs no second load.
+__device__ __forceinline__ int unit_search(const int4 *X, int n, long long x, bool adj, int4 &aux) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, len = n;
+  for (;;) {
+    const int step = (len + 63) >> 6;
+    const int i = lo + lane * step;
+    const bool valid = i < lo + len;
+    int4 v = make_int4(0, 0, 0, 0);
+    if (valid) v = X[i];
+    const bool ok = valid && (long long)(adj ? v.z : v.w) <= x;
+    const int k = 63 - __clzll(__ballot(ok));  // lane 0 (i = lo) always qualifies
+    if (step == 1) {
+      aux = make_int4(__builtin_amdgcn_readlane(v.x, k), __builtin_amdgcn_readlane(v.y, k),
+                      __builtin_amdgcn_readlane(v.z, k), __builtin_amdgcn_readlane(v.w, k));
+      return uniform(lo + k);
+    }
+    const int end = lo + len;
+    lo += k * step;
+    len = min(step, end - lo);
+  }
+}
+
 // Where wave g's share of a pass of total cost tot begins.  Waves with a higher index are dispatched
 // later and, the SIMDs issuing for their oldest waves first, progress more slowly: measured on the
 // coverage pass at 512^2 with equal shares, the last eighth of the waves ended 14 us after the first
@@ -780,11 +873,13 @@ __device__ __forceinline__ long long share_bound(long long tot, int g, int nwave
 }
 
 // First piece of persistent wave gw: returns false when the wave has no work.
-// P: [tiles + 1] prefix of the pass's tile costs (chunks for the adjoint passes); Q: the chunk prefix.
+// P: [tiles + 1] prefix of the pass's tile costs (chunks for the adjoint passes); Q: the chunk prefix;
+// C: the tiles' unit counts in LDS, or null (global).
 __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T,
-                                           const long long *P, const long long *Q) {
+                                           const long long *P, const long long *Q, const int *C) {
   const long long tot = uniform_ll(P[a.total_tiles]);
   w.Q = Q;
+  w.C = C;
   w.adj = adj;
   if (tot <= 0) return false;
   const long long b0 = share_bound(tot, gw, nwaves, adj ? 0.0 : kCoverTaper);
@@ -797,14 +892,16 @@ __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int 
   w.p = uniform_ll(P[w.tile]);
   walk_tile(a, w, T);
   w.slot = 0;
+  bool have = false;  // w.aux holds the record of the unit at w.slot
   if (w.count > 0) {
-    const int4 *X = a.entry_aux + w.list_base;
-    w.slot = wave_last_le(w.count, b0 - w.p, [&](int i) { return (long long)(adj ? X[i].z : X[i].w); });
-    w.p += adj ? load_aux(a, w.list_base + w.slot).z : load_aux(a, w.list_base + w.slot).w;
+    w.slot = unit_search(a.entry_aux + w.list_base, w.count, b0 - w.p, adj, w.aux);
+    w.p += adj ? w.aux.z : w.aux.w;
+    have = true;
   }
   // (the search leaves nothing to skip; the loop only guards the invariant)
   for (;;) {
-    if (!walk_settle(a, w, T)) return false;
+    if (!have && !walk_settle(a, w, T)) return false;
+    have = false;
     const long long c = (long long)w.aux.x * chunk_cost(w);
     if (w.p + c > b0) break;
     w.p += c;
@@ -1292,31 +1389,47 @@ struct UnitView {
   double kc, ks;     // k R(theta), loaded only when |s| < kScaleFloor
 };
 
-__device__ __forceinline__ UnitView unit_view(const KArgs &a, cptr<UnitRec> U) {
+// A unit record by scalar loads (U wave-uniform).
+__device__ __forceinline__ UnitRec load_unit(cptr<UnitRec> U) {
+  UnitRec u;
+  u.eo = U->eo;
+  u.ecnv = U->ecnv;
+  u.flags = U->flags;
+  u.head = U->head;
+  u.xy = U->xy;
+  u.wn = U->wn;
+  u.sid = U->sid;
+  u.s = U->s;
+  u.cx = U->cx;
+  u.cy = U->cy;
+  return u;
+}
+
+__device__ __forceinline__ UnitView unit_view(const KArgs &a, const UnitRec &U) {
   UnitView v;
-  const int xy = U->xy, wn = U->wn, ecnv = U->ecnv, fl = U->flags;
+  const int xy = U.xy, wn = U.wn, ecnv = U.ecnv, fl = U.flags;
   v.r.x0 = xy & 0xffff;
   v.r.y0 = xy >> 16;
   v.r.w = wn & 0xffff;
   v.r.n = wn >> 16;
-  v.eo = U->eo;
+  v.eo = U.eo;
   v.ec = ecnv & 0xffff;
   v.nv = ecnv >> 16;
-  v.head = U->head;
+  v.head = U.head;
   v.open = (fl & kUnitOpen) != 0;
   v.orient = (fl & kUnitClockwise) ? -1.0f : 1.0f;
-  v.cx = U->cx;
-  v.cy = U->cy;
+  v.cx = U.cx;
+  v.cy = U.cy;
   v.cxf = (float)v.cx;
   v.cyf = (float)v.cy;
   v.sw = 0.0;
   v.sw_ds = 0.0;
-  cptr<ShapeRec> SR = konst(a.shapes) + U->sid;
+  cptr<ShapeRec> SR = konst(a.shapes) + U.sid;
   if (v.open) {
     v.sw = SR->sw;
     v.sw_ds = SR->sw_ds;
   }
-  const double s = (double)U->s;
+  const double s = (double)U.s;
   v.inv_s = 0.0;
   v.kc = 0.0;
   v.ks = 0.0;
@@ -1333,12 +1446,14 @@ __device__ __forceinline__ UnitView unit_view(const KArgs &a, cptr<UnitRec> U) {
 // kScanInCoverTiles tiles, by one 256-thread workgroup into LDS (two tiles per thread, DPP wave scans).
 // Workgroup 0 also writes them to tile_pre for the later passes and advances the Adam step counter,
 // which the scan kernel does otherwise.
-__device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq) {
+__device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq, int *cnt) {
   __shared__ unsigned long long s_w[2][4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nt = a.total_tiles, t0 = 2 * tid;
   const int2 c0 = t0 < nt ? a.tile_cost[t0] : make_int2(0, 0);
   const int2 c1 = t0 + 1 < nt ? a.tile_cost[t0 + 1] : make_int2(0, 0);
+  if (t0 < nt) cnt[t0] = a.tile_count[t0];
+  if (t0 + 1 < nt) cnt[t0 + 1] = a.tile_count[t0 + 1];
   const unsigned long long vc = (unsigned long long)c0.x + (unsigned long long)c1.x;
   const unsigned long long vq = (unsigned long long)c0.y + (unsigned long long)c1.y;
   const unsigned long long xc = wave_incl_scan_u64(vc), xq = wave_incl_scan_u64(vq);
@@ -1400,14 +1515,19 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
   // the tiles' cost and chunk prefixes: computed here in LDS by every workgroup for small scenes (no
   // separate scan launch; workgroup 0 publishes them for the later passes), else from the scan kernel
   __shared__ long long s_pre[2][kScanInCoverTiles + 1];
+  __shared__ int s_cnt[kScanInCoverTiles];
   const long long *P = a.tile_pre, *Q = a.tile_pre + (a.total_tiles + 1);
+  const int *C = nullptr;
   if (a.scan_in_cover) {
-    cover_tile_scan(a, s_pre[0], s_pre[1]);
+    cover_tile_scan(a, s_pre[0], s_pre[1], s_cnt);
     P = s_pre[0];
     Q = s_pre[1];
+    C = s_cnt;
   }
-  for (bool ok = walk_begin(a, wk, gw, nwaves, false, T, P, Q); ok; ok = walk_next(a, wk, T)) {
-    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+  bool ok = walk_begin(a, wk, gw, nwaves, false, T, P, Q, C);
+  for (; ok; ok = walk_next(a, wk, T)) {
+    cptr<UnitRec> U = konst(a.units) + (wk.list_base + wk.slot);
+    const UnitView uv = unit_view(a, load_unit(U));
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec;
@@ -1687,12 +1807,20 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
       cptr<ShapeRec> SR = konst(a.shapes);
       for (int q = LS[u.b].shape_begin + tid; q < LS[u.b].shape_end; q += NT) term[8] += (double)u.H - SR[q].cy;
     }
+    // a term with weight 0 is 0; terms 0-7 are summed together, term 8 (only the first tile of a layout
+    // has it) on its own when its weight is not 0 (the branch is the same for the whole grid)
+    static_assert(kLossTerms == 9, "loss terms");
+    double v8[8];
 #pragma unroll
-    for (int t = 0; t < kLossTerms; ++t) {
-      // a term with weight 0 is 0: its reduction is skipped (the branch is the same for the whole grid)
-      const double s = a.w[t] != 0.0f ? wave_sum(wt[t] * term[t]) : 0.0;
-      if (lane == 0) s_loss[w][t] = s;
+    for (int t = 0; t < 8; ++t) v8[t] = a.w[t] != 0.0f ? wt[t] * term[t] : 0.0;
+    int c0;
+    const double2 r8 = wave_sum8(v8, c0);
+    if (lane < 4) {
+      s_loss[w][c0] = r8.x;
+      s_loss[w][c0 + 1] = r8.y;
     }
+    const double s8 = a.w[8] != 0.0f ? wave_sum(wt[8] * term[8]) : 0.0;
+    if (lane == 0) s_loss[w][8] = s8;
     __syncthreads();
     if (tid < kLossTerms) {
       double s = 0.0;
@@ -1787,12 +1915,12 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
-  bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg);
+  bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg, nullptr);
   // every wave writes its spill slot: zero (right away, off the end of the kernel's path) when its share
   // is empty or begins at a unit's first chunk
   if ((!ok || wk.jlo == 0) && lane == 0) a.spill[gw] = make_double4(0.0, 0.0, 0.0, 0.0);
   for (; ok; ok = walk_next(a, wk, T)) {
-    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+    const UnitView uv = unit_view(a, load_unit(konst(a.units) + (wk.list_base + wk.slot)));
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec;
@@ -1881,18 +2009,12 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
         }
       }
     }
-    acc.x = wave_sum(acc.x);
-    acc.y = wave_sum(acc.y);
-    acc.z = wave_sum(acc.z);
-    acc.w = wave_sum(acc.w);
+    int comp;
+    const double tot = wave_sum4(acc, comp);
     // the piece that starts at the unit's first chunk is its head; only a wave's first piece can start
-    // inside a unit, and then it is the wave's spill
-    if (lane == 0) {
-      if (wk.jlo == 0)
-        a.head[uv.head] = acc;
-      else
-        a.spill[gw] = acc;
-    }
+    // inside a unit, and then it is the wave's spill (lanes 0-3 hold the four components)
+    double *dst = reinterpret_cast<double *>(wk.jlo == 0 ? a.head + uv.head : a.spill + gw);
+    if (lane < 4) dst[comp] = tot;
   }
 }
 
@@ -1923,8 +2045,8 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
-  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg); ok; ok = walk_next(a, wk, T)) {
-    const UnitView uv = unit_view(a, konst(a.units) + (wk.list_base + wk.slot));
+  for (bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg, nullptr); ok; ok = walk_next(a, wk, T)) {
+    const UnitView uv = unit_view(a, load_unit(konst(a.units) + (wk.list_base + wk.slot)));
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec, nv = uv.nv;
@@ -2133,10 +2255,11 @@ __device__ void finalize_grad(const KArgs &a, int per) {
       }
     }
   }
-  acc.x = wave_sum(acc.x);
-  acc.y = wave_sum(acc.y);
-  acc.z = wave_sum(acc.z);
-  acc.w = wave_sum(acc.w);
+  {
+    int comp;
+    const double t = wave_sum4(acc, comp);
+    acc = make_double4(readlane_f64(t, 0), readlane_f64(t, 2), readlane_f64(t, 1), readlane_f64(t, 3));
+  }
   float4 pn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (lane == 0) {
     // the object-space downward force adds d(H - k t_y)/dt_y = -k per unit of its weight
