@@ -36,14 +36,26 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # the minimum adds 3 more, reported beside the roofline fraction but not counted in it
 FWD_OPS_PER_PAIR = 17
 ARGMIN_OPS_PER_PAIR = 3
+# algorithmic lane-operations per (pixel, item) of the coverage pass beyond the scan: the nearest edge
+# decided again in float64 among the scan's choice and its two neighbours (3 distances of 11 operations,
+# 2 comparisons), the square root, the sign or the stroke offset (1), alpha and alpha_pad (one exponential,
+# two additions and two reciprocals, the padding factor: 6) and the two accumulations (2).  It matters
+# where items have few edges (open polylines of 2-11 edges), where this epilogue outweighs the scan.
+EPILOGUE_OPS_PER_LANE = 3 * 11 + 2 + 1 + 1 + 6 + 2
 # the timed region stamps the coverage launch of every TIMER_STRIDE-th epoch with a HIP event pair
 TIMER_STRIDE = 8
+WORKLOADS = {
+    "config3": ("512x512 level of the 128-256-512-1024 schedule; 500 closed cubic-Bezier items (4-16 segments, "
+                "8 points each), 10-ellipse container, padding 2 px, downward force 1e-3, seed 0", 512),
+    "config5": ("2048x2048 level of the 256-512-1024-2048 schedule; 2000 open stroked polylines (3-12 vertices, "
+                "half-width 1.5), container of 10 ellipses and 10 rotated rectangles, seed 0", 2048),
+}
 
 
-def support_pairs(scene, params, level):
+def support_pairs(scene, params, level, lanes=False):
     """Algorithmic (pixel, edge) pairs of one scan: for every item, the pixels whose centres lie in its
     vertex bounding box widened by r_cut + r_pad (and an open item's stroke radius), clipped to its
-    canvas, times its edge count."""
+    canvas, times its edge count.  With lanes, also the (pixel, item) pairs themselves."""
     w, h, k, off = scene.layout_arrays(level)
     V = scene.verts.astype(np.float64)
     vo = scene.vert_off.astype(np.int64)
@@ -65,8 +77,9 @@ def support_pairs(scene, params, level):
     i1 = np.minimum(np.floor(np.maximum.reduceat(x, starts) + ext - 0.5), w[lay] - 1)
     j0 = np.maximum(np.ceil(np.minimum.reduceat(y, starts) - ext - 0.5), 0)
     j1 = np.minimum(np.floor(np.maximum.reduceat(y, starts) + ext - 0.5), h[lay] - 1)
-    n = np.where((i1 >= i0) & (j1 >= j0), (i1 - i0 + 1) * (j1 - j0 + 1), 0) * cnt
-    return int(n.sum())
+    px = np.where((i1 >= i0) & (j1 >= j0), (i1 - i0 + 1) * (j1 - j0 + 1), 0)
+    n = px * cnt
+    return (int(n.sum()), int(px[cnt > 0].sum())) if lanes else int(n.sum())
 
 
 def cpu_baseline(scene, level, budget_s=14.0, budget_1core_s=10.0, max_iters=2000):
@@ -103,8 +116,8 @@ def cpu_baseline(scene, level, budget_s=14.0, budget_1core_s=10.0, max_iters=200
     finally:
         orc.set_threads(cores)
     return {"value": n / dt, "unit": "it/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} oracle epochs (forward, backward, Adam; FP64) of the same 512x512 / 500-item "
-                      f"scene from the seed-0 layout on {cores} threads, {dt:.1f} s; then {n1} epochs on 1 "
+            "sample": f"{n} oracle epochs (forward, backward, Adam; FP64) of the same {level}x{level} / "
+                      f"{scene.num_shapes}-item scene from the seed-0 layout on {cores} threads, {dt:.1f} s; then {n1} epochs on 1 "
                       f"thread, {dt1:.1f} s",
             "value_1core": n1 / dt1, "speedup_all_cores": (n / dt) / (n1 / dt1)}
 
@@ -410,7 +423,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--level", type=int, default=512)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="config3",
+                    help="config3: the 500-item Bezier scene (the benchmark); config5: 2000 open polylines")
+    ap.add_argument("--level", type=int, default=0, help="0: the workload's reference level")
     ap.add_argument("--tile", type=int, default=0, help="0: autotuned (tile, code capacity, bin chunk)")
     ap.add_argument("--code-capacity", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -438,7 +453,12 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    sc = scenes.config3(0)
+    sc = getattr(scenes, args.workload)(0)
+    workload_desc, ref_level = WORKLOADS[args.workload]
+    if args.level == 0:
+        args.level = ref_level
+    if args.level != ref_level:
+        workload_desc = workload_desc.replace(f"{ref_level}x{ref_level}", f"{args.level}x{args.level}")
     if args.tile == 0:
         cfg, tune_times = autotune.tune(sc, level=args.level)
     else:
@@ -507,7 +527,8 @@ def main():
     stream.synchronize()
     replay_same = bool(torch.equal(params, torch.from_numpy(p_end).to(params.device)))
     snaps = snaps.cpu().numpy()
-    pairs_each = np.array([support_pairs(sc, snaps[i], args.level) for i in range(args.steps)], np.float64)
+    pl = np.array([support_pairs(sc, snaps[i], args.level, lanes=True) for i in range(args.steps)], np.float64)
+    pairs_each, lanes_each = pl[:, 0], pl[:, 1]
 
     secs = region_ms / 1e3
     its = args.steps / secs
@@ -518,6 +539,9 @@ def main():
     # algorithmic work of the stamped launches over their summed durations
     achieved = FWD_OPS_PER_PAIR * float(stamped.sum()) / (float(np.sum(tiles_ms)) * 1e-3)
     achieved_argmin = (FWD_OPS_PER_PAIR + ARGMIN_OPS_PER_PAIR) * float(stamped.sum()) / (float(np.sum(tiles_ms)) * 1e-3)
+    stamped_lanes = lanes_each[::-(-args.steps // timer.count)]
+    achieved_epi = (FWD_OPS_PER_PAIR * float(stamped.sum()) + EPILOGUE_OPS_PER_LANE * float(stamped_lanes.sum())) / (
+        float(np.sum(tiles_ms)) * 1e-3)
     # the fixed seed-0 layout (its pairs, every epoch) and the form that keeps no codes between passes
     seed0_its, seed0_scans = seed0_layout(cs, p0, args.steps)
     rc = recompute_only(sc, args.level, cfg, args.steps, args.warmup, p_end)
@@ -536,9 +560,7 @@ def main():
         "dtype": "f32",
         "dtype_note": "float32 edge scan; float64 per-(pixel, item) distance, coverage, loss and adjoint (its logistic-derivative factor in float32)",
         "data": "synthetic",
-        "config": {"workload": "512x512 level of the 128-256-512-1024 schedule; 500 closed cubic-Bezier items "
-                               "(4-16 segments, 8 points each), 10-ellipse container, padding 2 px, "
-                               "downward force 1e-3, seed 0", "tile": cfg.tile,
+        "config": {"workload": workload_desc, "tile": cfg.tile,
                    "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk},
         "form": "the coverage pass keeps each (pixel, item)'s nearest-edge code (2 bytes) for the adjoint, "
                 "which evaluates that one edge; recompute_only keeps none and scans again",
@@ -564,6 +586,9 @@ def main():
             "ops_per_pair": FWD_OPS_PER_PAIR,
             "argmin_ops_per_pair": ARGMIN_OPS_PER_PAIR,
             "frac_with_argmin": achieved_argmin / PEAK_LANE_OPS,
+            "epilogue_ops_per_lane": EPILOGUE_OPS_PER_LANE,
+            "pixel_item_lanes_per_scan": float(lanes_each.mean()),
+            "frac_with_epilogue": achieved_epi / PEAK_LANE_OPS,
             "kernel_ms_mean": tile_ms,
             "kernel_launches_timed": int(len(tiles_ms)),
             "kernel_timing": f"HIP events on the coverage launch of every {TIMER_STRIDE}th epoch of the timed region",

@@ -171,6 +171,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.r_cut = s->r_cut;
   a.r_pad = s->r_pad;
   a.inv_tau_d = 1.0 / (double)s->tau;
+  a.log2e_inv_tau = 1.4426950408889634 / (double)s->tau;
   a.pad_factor = std::exp(-(double)s->r_pad / (double)s->tau);
   for (int i = 0; i < kLossTerms; ++i) a.w[i] = s->w[i];
   a.area_mean = (s->flags & COLLAGE_FLAG_AREA_MEAN) ? 1 : 0;

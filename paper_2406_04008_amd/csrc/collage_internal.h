@@ -167,6 +167,7 @@ struct KArgs {
   // constants
   float tau, inv_tau, r_cut, r_pad;
   double inv_tau_d;      // 1 / tau
+  double log2e_inv_tau;  // log2(e) / tau
   double pad_factor;     // e^(-r_pad / tau)
   float w[9];            // overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
   int32_t area_mean;     // 1: overlap, contain, fill, pad and wmse are divided by the layout's W * H

@@ -293,6 +293,16 @@ __device__ __forceinline__ void stream_store(EdgeD *dst, const EdgeD &r) {
   for (int i = 0; i < 3; ++i) __builtin_nontemporal_store(src[i], d + i);
 }
 
+// 1 / x for a positive normal double: the hardware estimate and two Newton steps (each doubles the
+// correct bits; the result is within an ulp or two of the quotient, at a third of the instructions of a
+// correctly rounded division).
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 __device__ __forceinline__ void place_vertex(double c, double sn, double s, double k, float2 v, double &x, double &y) {
   const double sx = s * (double)v.x, sy = s * (double)v.y;
   x = k * (c * sx - sn * sy);
@@ -531,6 +541,7 @@ __device__ __forceinline__ void edge_scan(cptr<EdgeRec> E, int cnt, float rx, fl
 // and (qx, qy) = p - nearest point.
 struct PairD {
   double sd, d, u, qx, qy;
+  double inv_d;  // 1 / d (0 at d = 0)
 };
 
 __device__ __forceinline__ void pair_d2(const EdgeD &e, double rx, double ry, double &d2, double &u, double &qx,
@@ -542,11 +553,16 @@ __device__ __forceinline__ void pair_d2(const EdgeD &e, double rx, double ry, do
   d2 = qx * qx + qy * qy;
 }
 
+// The distance in double; its reciprocal (the unit normal (p - q) / d at an end point) from the hardware
+// estimate refined twice, which is within an ulp or two of the quotient.  (A float32 distance was tried:
+// its error of a few 1e-7, amplified by the cancellation between the pixels of an item, took config 1's
+// gradients past the 1e-4 bar.)
 __device__ __forceinline__ PairD pair_eval(const EdgeD &e, double rx, double ry, bool par) {
   PairD r;
   double d2;
   pair_d2(e, rx, ry, d2, r.u, r.qx, r.qy);
   r.d = sqrt(d2);
+  r.inv_d = r.d > 0.0 ? rcp_refined(r.d) : 0.0;
   r.sd = par ? r.d : -r.d;
   return r;
 }
@@ -595,34 +611,55 @@ __device__ __forceinline__ Nearest nearest_refined(const EdgeD *E, int ec, int b
   return n;
 }
 
-// alpha and alpha_pad of one (pixel, item) from its signed distance, in float32 with one exponential:
-// for x = sd / tau, e^-(x + r_pad / tau) = e^-x pad_factor.  The distance comes from the double-precision
-// evaluation of the nearest edge; alpha is within a few 1e-7 of its double value (the 1e-5 image bar
-// leaves room for the sum of many), and it is exact in the fixed-point sums.  Wherever either is not cut
-// to zero, x >= -(r_cut + r_pad) / tau, so e^-x does not overflow.  (Measured: 37.8 -> 36.9 us per coverage
-// pass against the double-precision version, which also held 24 more VGPRs.)
-__device__ __forceinline__ void coverage_pair(const KArgs &a, float sd, float &al, float &alp) {
-  al = alp = 0.0f;
-  if (sd + a.r_pad < -a.r_cut) return;
-  const float E = __expf(-sd * a.inv_tau);
-  if (sd >= -a.r_cut) al = __frcp_rn(1.0f + E);
-  alp = __frcp_rn(1.0f + E * (float)a.pad_factor);
+// e^(-sd / tau) in double, for the range the coverage uses (sd >= -(r_cut + r_pad), so the result is at
+// most e^((r_cut + r_pad) / tau)): 2^y with y = -sd log2(e) / tau split into an integer n and a fraction
+// f in [-1/2, 1/2]; 2^f = e^g with g = f ln 2, |g| <= 0.347, by the Taylor series of e^g to degree 9
+// (remainder below 1e-11 of the value), then scaled by 2^n.  Fewer instructions and registers than the
+// library exponential, which also handles the whole double range.
+__device__ __forceinline__ double exp_neg_tau(const KArgs &a, double sd) {
+  constexpr double kLn2 = 0.6931471805599453;
+  const double y = -sd * a.log2e_inv_tau;
+  const double n = rint(y);
+  const double g = (y - n) * kLn2;
+  double p = 1.0 / 362880.0;
+  p = fma(p, g, 1.0 / 40320.0);
+  p = fma(p, g, 1.0 / 5040.0);
+  p = fma(p, g, 1.0 / 720.0);
+  p = fma(p, g, 1.0 / 120.0);
+  p = fma(p, g, 1.0 / 24.0);
+  p = fma(p, g, 1.0 / 6.0);
+  p = fma(p, g, 0.5);
+  p = fma(p, g, 1.0);
+  p = fma(p, g, 1.0);
+  return ldexp(p, (int)n);
+}
+
+// alpha and alpha_pad of one (pixel, item) from its signed distance, in double with one exponential:
+// for x = sd / tau, e^-(x + r_pad / tau) = e^-x pad_factor.  Wherever either is not cut to zero,
+// x >= -(r_cut + r_pad) / tau, so e^-x does not overflow and 1 + E is a normal number >= 1.  Double
+// matters here: near convergence an item's gradient is a small remainder of its pixels' contributions,
+// and alpha carried in float32 (errors of 1e-7 to 1e-6 from the float exponential) moved config 1's
+// gradients at some layouts by more than 1e-4 of their size through dLoss/dS.
+__device__ __forceinline__ void coverage_pair(const KArgs &a, double sd, double &al, double &alp) {
+  al = alp = 0.0;
+  if (sd + (double)a.r_pad < -(double)a.r_cut) return;
+  const double E = exp_neg_tau(a, sd);
+  if (sd >= -(double)a.r_cut) al = rcp_refined(1.0 + E);
+  alp = rcp_refined(1.0 + E * a.pad_factor);
 }
 
 // omega = G dalpha/dsd + G_pad dalpha_pad/dsd of one (pixel, item), from one exponential: with
 // E = e^-x (x = sd / tau), sigma'(x) = E / (1 + E)^2, free of cancellation at both ends of the range used
-// (x >= -(r_cut + r_pad) / tau).  The logistic factor is evaluated in float (relative error a few 1e-7,
-// far below the gradient's tolerance): in double its exponential and two divisions were about 40% of the
-// adjoint's float64 instructions.  Within that range E <= e^((r_cut + max(r_pad, 0)) / tau) and
-// E / (1 + E)^2 <= 1/4, so nothing overflows; deep inside, E underflows to 0 where the double value is
-// below 1e-44.
+// (x >= -(r_cut + r_pad) / tau), where E <= e^((r_cut + max(r_pad, 0)) / tau) and E / (1 + E)^2 <= 1/4.
+// In double for the reason given at coverage_pair: in float32 its errors of a few 1e-7 were amplified by
+// the cancellation between an item's pixels beyond the gradient's 1e-4 bar at converged layouts.
 __device__ __forceinline__ double adjoint_omega(const KArgs &a, double sd, double G, double Gp) {
   double dal = 0.0, dalp = 0.0;
   if (sd + (double)a.r_pad >= -(double)a.r_cut) {
-    const float E = expf((float)(-sd * a.inv_tau_d)), Ep = E * (float)a.pad_factor;
-    const float r = 1.0f / (1.0f + E), rp = 1.0f / (1.0f + Ep);
-    if (sd >= -(double)a.r_cut) dal = (double)(E * r * r) * a.inv_tau_d;
-    dalp = (double)(Ep * rp * rp) * a.inv_tau_d;
+    const double E = exp_neg_tau(a, sd), Ep = E * a.pad_factor;
+    const double r = rcp_refined(1.0 + E), rp = rcp_refined(1.0 + Ep);
+    if (sd >= -(double)a.r_cut) dal = E * r * r * a.inv_tau_d;
+    dalp = Ep * rp * rp * a.inv_tau_d;
   }
   return G * dal + Gp * dalp;
 }
@@ -643,7 +680,7 @@ __device__ __forceinline__ void adjoint_normal(const EdgeD &e, const PairD &q, b
     nx = -e.ey * il * sg;
     ny = e.ex * il * sg;
   } else {
-    const double id = (par ? 1.0 : -1.0) / q.d;
+    const double id = par ? q.inv_d : -q.inv_d;
     nx = q.qx * id;
     ny = q.qy * id;
   }
@@ -1375,6 +1412,40 @@ __device__ __forceinline__ void chunk_pixel(const Rect &r, int j, int lane, int 
   py = r.y0 + ly;
 }
 
+// The same pixels for consecutive chunks without a division per chunk: the next chunk is 64 pixels
+// further along the rectangle's rows, i.e. 64 / w rows and 64 mod w columns, with one carry.
+struct ChunkPix {
+  int i, lx, ly;  // the lane's index in the rectangle and its column and row there
+  int dx, dy;     // per chunk (wave-uniform)
+};
+
+__device__ __forceinline__ ChunkPix chunk_start(const Rect &r, int j, int lane) {
+  ChunkPix c;
+  c.i = j * 64 + lane;
+  c.ly = c.i / r.w;
+  c.lx = c.i - c.ly * r.w;
+  c.dy = uniform(64 / r.w);
+  c.dx = 64 - c.dy * r.w;
+  return c;
+}
+
+__device__ __forceinline__ void chunk_step(ChunkPix &c, const Rect &r) {
+  c.i += 64;
+  c.lx += c.dx;
+  c.ly += c.dy;
+  if (c.lx >= r.w) {
+    c.lx -= r.w;
+    ++c.ly;
+  }
+}
+
+// The pixel of the iterator's chunk, as chunk_pixel gives it.
+__device__ __forceinline__ void chunk_at(const ChunkPix &c, const Rect &r, int &px, int &py, bool &in) {
+  in = c.i < r.n;
+  px = r.x0 + (in ? c.lx : 0);
+  py = r.y0 + (in ? c.ly : 0);
+}
+
 // A unit record as the persistent passes use it (scalar loads and unpacking).  The float origin of the
 // scan is the double origin rounded, as the transform rounds it.
 struct UnitView {
@@ -1537,10 +1608,11 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
     const double sw = uv.sw;
     const bool staged = ec <= kStageEdges;
     if (staged) stage_edges(a.edges + eo, ec, S, lane);
-    for (int j = wk.jlo; j < wk.jhi; ++j) {
+    ChunkPix it = chunk_start(r, wk.jlo, lane);
+    for (int j = wk.jlo; j < wk.jhi; ++j, chunk_step(it, r)) {
       int pxi, pyi;
       bool in;
-      chunk_pixel(r, j, lane, pxi, pyi, in);
+      chunk_at(it, r, pxi, pyi, in);
       int bi = 0;
       bool par = false;
       scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
@@ -1549,12 +1621,12 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
         const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
         bi = nr.e;
         if (in) {
-          const float d = sqrtf((float)nr.d2);
-          float al, alp;
-          coverage_pair(a, open ? (float)sw - d : (par ? d : -d), al, alp);
+          const double d = sqrt(nr.d2);
+          double al, alp;
+          coverage_pair(a, open ? sw - d : (par ? d : -d), al, alp);
           const int64_t pix = wk.pix_off + (int64_t)pyi * wk.W + pxi;
-          if (al > 0.0f) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint((double)al * kFixScale));
-          if (alp > 0.0f) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint((double)alp * kFixScale));
+          if (al > 0.0) atomicAdd(&a.acc[2 * pix], (unsigned long long)llrint(al * kFixScale));
+          if (alp > 0.0) atomicAdd(&a.acc[2 * pix + 1], (unsigned long long)llrint(alp * kFixScale));
         }
       }
       if (a.keep_codes && q + j < a.code_cap) a.codes[(q + j) * 64 + lane] = (uint16_t)(bi | (par ? 0x8000 : 0));
@@ -1691,7 +1763,8 @@ __device__ __forceinline__ unsigned long long sat_box(const unsigned long long *
 template <bool GRAD, bool UNI>
 __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
   // without the uniform term a workgroup of 256 threads takes the tile, four pixels per thread with
-  // all their loads in flight together; the window pass needs one thread per pixel (16 waves)
+  // all their loads in flight together (1024 threads of one pixel each were 0.3 us slower at 512^2);
+  // the window pass needs one thread per pixel (16 waves)
   constexpr int NT = UNI ? kPixThreads : 256, PX = kPixTile * kPixTile / NT, NW = NT / 64;
   __shared__ double s_loss[NW][kLossTerms];
   __shared__ unsigned long long T[UNI ? kUniPitch * kUniPitch : 1];
@@ -2377,8 +2450,11 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
     edge_scan(konst(a.edges) + eo, ec, pxi + 0.5f - SR[q].cxf, pyi + 0.5f - SR[q].cyf, bi, par);
     const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
     const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
-    const float d = sqrtf((float)nr.d2);
-    coverage_pair(a, SR[q].open ? (float)SR[q].sw - d : (par ? d : -d), al, alp);
+    const double d = sqrt(nr.d2);
+    double ad, apd;
+    coverage_pair(a, SR[q].open ? SR[q].sw - d : (par ? d : -d), ad, apd);
+    al = (float)ad;
+    alp = (float)apd;
   }
   alpha[off + pix] = al;
   if (alpha_pad) alpha_pad[off + pix] = alp;

@@ -2,11 +2,13 @@
 one epoch per call), compared with the FP64 oracle along the GPU's own trajectory.
 
 Layouts after many epochs are local minima (FP32 and FP64 trajectories part ways at relu kinks), so
-the comparison is step-wise: every 10 epochs the loss and the gradient that the GPU epoch computed are
+the comparison is step-wise: at every epoch the loss and the gradient that the GPU epoch computed are
 checked against the oracle at exactly the parameters that epoch started from, to the workload's
-tolerances.  The end state is checked by bands: the loss falls by more than 5x, and the Sec. 6 quality
-metrics on hard rasters (the oracle's) show over 80% of the disk covered with overlap and excess
-below 5% of it.
+tolerances.  (Near convergence an item's gradient is a small remainder of its pixels' contributions, so
+this is where float rounding in the coverage or its derivative would show: with alpha and the logistic
+derivative in float32 the error passed 1e-4 at some epochs; in double it stays near 1e-7.)  The end
+state is checked by bands: the loss falls by more than 5x, and the Sec. 6 quality metrics on hard
+rasters (the oracle's) show over 80% of the disk covered with overlap and excess below 5% of it.
 """
 import sys
 
@@ -35,18 +37,17 @@ def test_config1_two_hundred_epochs_stepwise_against_the_oracle():
     checked = []
     first = None
     for epoch in range(200):
-        p_before = p.detach().cpu().numpy().copy() if epoch % 10 == 0 else None
+        p_before = p.detach().cpu().numpy().copy()
         cs.iterate(p, m, v, st, loss=loss, grad=grad)
-        if p_before is not None:
-            lg, gg = loss.cpu().numpy(), grad.cpu().numpy()
-            _, _, L = o.forward(p_before)
-            check_loss(lg, L, f"loss at epoch {epoch}")
-            check_grad(gg, o.backward(p_before), f"grad at epoch {epoch}")
-            checked.append(epoch)
-            if first is None:
-                first = float(L.sum())
+        lg, gg = loss.cpu().numpy(), grad.cpu().numpy()
+        _, _, L = o.forward(p_before)
+        check_loss(lg, L, f"loss at epoch {epoch}")
+        check_grad(gg, o.backward(p_before), f"grad at epoch {epoch}")
+        checked.append(epoch)
+        if first is None:
+            first = float(L.sum())
     torch.cuda.synchronize()
-    assert int(st.item()) == 200 and len(checked) == 20
+    assert int(st.item()) == 200 and len(checked) == 200
     p_end = p.cpu().numpy()
     assert np.all(np.isfinite(p_end))
     last = o.loss(p_end)
