@@ -550,31 +550,11 @@ int oracle_signed_distance(const oracle_scene *sc, const double *params, int fir
  *     dv'/dt = k I,   dv'/dtheta = k s R'(theta) v,   dv'/ds = k R(theta) v.
  * A pixel centre lying exactly on the outline (|p - q| = 0) contributes nothing.
  */
-int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
-                         double *grad_verts);
-
-int oracle_backward(const oracle_scene *sc, const double *params, const double *dloss, double *grad) {
-  return oracle_backward_full(sc, params, dloss, grad, NULL);
-}
-
-/*
- * As oracle_backward, and (grad_verts not NULL) the gradient with respect to every item's outline
- * vertices in its own frame, [V*2] canonical px (Sec. 3 "Vector Representation": the outline control
- * points are fitted by differentiable rendering): each pixel's dsd/dv' of the two end points of its
- * nearest edge, mapped back through eq. 2, dv'/dv = k s R(theta):  dL/dv = omega (k s R)^T dsd/dv'.
- */
-int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
-                         double *grad_verts) {
-  if (!sc || !params || !dloss || !grad) return -1;
-  if (sc->use_bbox && !sc->use_cutoff) return -1;
-  prepared pr;
-  prepare(sc, params, &pr);
-  int64_t total = pixel_offset(sc, sc->B);
-  double *S = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
-  double *Sp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
-  double *G = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
-  double *Gp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
-  forward_impl(sc, &pr, S, Sp, NULL);
+/* dLoss/dS and dLoss/dS_pad per pixel (G, Gp) of sum_b sum_t dloss[b][t] loss[b][t], from the coverage
+ * sums S, S_pad of the prepared items (the derivative of each term of the forward pass). */
+static void dloss_images(const oracle_scene *sc, const prepared *pr, const double *dloss, double *S, double *Sp,
+                         double *G, double *Gp) {
+  forward_impl(sc, pr, S, Sp, NULL);
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b], H = sc->height[b];
     const int64_t off = pixel_offset(sc, b);
@@ -602,6 +582,85 @@ int oracle_backward_full(const oracle_scene *sc, const double *params, const dou
       }
     uniform_grad(sc, b, S + off, dloss[NTERMS * b + 5] * sc->w[5], G + off);
   }
+}
+
+/* The terms one pixel (px, py) adds to item q's gradient g[4] and, with gv, to its outline vertices: with r
+ * the pixel's distance result for the item (nearest edge, clamped parameter, nearest point, inside flag)
+ * and G, Gp dLoss/dS and dLoss/dS_pad at the pixel, omega = G dalpha/dsd + Gp dalpha_pad/dsd times dsd with
+ * respect to the two end points of the nearest edge, then through eq. 2.  (c, sn: cos, sin of theta.) */
+static void pixel_terms(const oracle_scene *sc, int q, double k, int n, double c, double sn, double s, int open,
+                        double px, double py, const sd_result *r, double G, double Gp, double *g, double *gv) {
+  double a, da, ap, dap;
+  coverage(sc, r->sd, &a, &da, &ap, &dap);
+  const double omega = G * da + Gp * dap;
+  if (omega == 0.0) return;
+  /* an open item's stroke radius k |s| w grows with |s| */
+  if (open) g[3] += omega * k * sc->stroke[q] * (s > 0.0 ? 1.0 : (s < 0.0 ? -1.0 : 0.0));
+  if (r->d == 0.0) return;
+  const double sgn = r->inside ? 1.0 : -1.0;
+  const double gx = (px - r->qx) / r->d, gy = (py - r->qy) / r->d;
+  /* dsd/d(vertex) for the two end points of the nearest edge */
+  double wa, wb;
+  if (r->u <= 0.0) {
+    wa = 1.0;
+    wb = 0.0;
+  } else if (r->u >= 1.0) {
+    wa = 0.0;
+    wb = 1.0;
+  } else {
+    wa = 1.0 - r->u;
+    wb = r->u;
+  }
+  const int ma = r->edge, mb = open ? (n > 1 ? r->edge + 1 : r->edge) : ((r->edge + 1 == n) ? 0 : r->edge + 1);
+  const int vm[2] = {ma, mb};
+  const double wv[2] = {wa, wb};
+  for (int e = 0; e < 2; ++e) {
+    if (wv[e] == 0.0) continue;
+    const double dvx = -sgn * wv[e] * gx, dvy = -sgn * wv[e] * gy; /* dsd/dv' */
+    const double lx = sc->verts[2 * (sc->vert_off[q] + vm[e])];
+    const double ly = sc->verts[2 * (sc->vert_off[q] + vm[e]) + 1];
+    /* dv'/dt = k I */
+    g[0] += omega * dvx * k;
+    g[1] += omega * dvy * k;
+    /* dv'/dtheta = k s R'(theta) v,  R' = [[-sin, -cos], [cos, -sin]] */
+    const double rtx = k * s * (-sn * lx - c * ly), rty = k * s * (c * lx - sn * ly);
+    g[2] += omega * (dvx * rtx + dvy * rty);
+    /* dv'/ds = k R(theta) v */
+    const double rsx = k * (c * lx - sn * ly), rsy = k * (sn * lx + c * ly);
+    g[3] += omega * (dvx * rsx + dvy * rsy);
+    /* dv'/dv = k s R(theta) */
+    if (gv) {
+      gv[2 * vm[e] + 0] += omega * k * s * (c * dvx + sn * dvy);
+      gv[2 * vm[e] + 1] += omega * k * s * (-sn * dvx + c * dvy);
+    }
+  }
+}
+
+int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
+                         double *grad_verts);
+
+int oracle_backward(const oracle_scene *sc, const double *params, const double *dloss, double *grad) {
+  return oracle_backward_full(sc, params, dloss, grad, NULL);
+}
+
+/*
+ * As oracle_backward, and (grad_verts not NULL) the gradient with respect to every item's outline
+ * vertices in its own frame, [V*2] canonical px (Sec. 3 "Vector Representation": the outline control
+ * points are fitted by differentiable rendering): each pixel's dsd/dv' of the two end points of its
+ * nearest edge, mapped back through eq. 2, dv'/dv = k s R(theta):  dL/dv = omega (k s R)^T dsd/dv'.
+ */
+int oracle_backward_full(const oracle_scene *sc, const double *params, const double *dloss, double *grad,
+                         double *grad_verts) {
+  if (!sc || !params || !dloss || !grad) return -1;
+  if (sc->use_bbox && !sc->use_cutoff) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  int64_t total = pixel_offset(sc, sc->B);
+  double *S = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Sp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *G = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Gp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  dloss_images(sc, &pr, dloss, S, Sp, G, Gp);
   for (int b = 0; b < sc->B; ++b) {
     const int W = sc->width[b];
     const int64_t off = pixel_offset(sc, b);
@@ -624,55 +683,114 @@ int oracle_backward_full(const oracle_scene *sc, const double *params, const dou
             const int64_t idx = off + (int64_t)j * W + i;
             const double px = i + 0.5, py = j + 0.5;
             const sd_result r = item_distance(sc, params, q, k, px, py, P, n);
-            double a, da, ap, dap;
-            coverage(sc, r.sd, &a, &da, &ap, &dap);
-            const double omega = G[idx] * da + Gp[idx] * dap;
-            if (omega == 0.0) continue;
-            /* an open item's stroke radius k |s| w grows with |s| */
-            if (open) g[3] += omega * k * sc->stroke[q] * (s > 0.0 ? 1.0 : (s < 0.0 ? -1.0 : 0.0));
-            if (r.d == 0.0) continue;
-            const double sgn = r.inside ? 1.0 : -1.0;
-            const double gx = (px - r.qx) / r.d, gy = (py - r.qy) / r.d;
-            /* dsd/d(vertex) for the two end points of the nearest edge */
-            double wa, wb;
-            if (r.u <= 0.0) {
-              wa = 1.0;
-              wb = 0.0;
-            } else if (r.u >= 1.0) {
-              wa = 0.0;
-              wb = 1.0;
-            } else {
-              wa = 1.0 - r.u;
-              wb = r.u;
-            }
-            const int ma = r.edge, mb = open ? (n > 1 ? r.edge + 1 : r.edge) : ((r.edge + 1 == n) ? 0 : r.edge + 1);
-            const int vm[2] = {ma, mb};
-            const double wv[2] = {wa, wb};
-            for (int e = 0; e < 2; ++e) {
-              if (wv[e] == 0.0) continue;
-              const double dvx = -sgn * wv[e] * gx, dvy = -sgn * wv[e] * gy; /* dsd/dv' */
-              const double lx = sc->verts[2 * (sc->vert_off[q] + vm[e])];
-              const double ly = sc->verts[2 * (sc->vert_off[q] + vm[e]) + 1];
-              /* dv'/dt = k I */
-              g[0] += omega * dvx * k;
-              g[1] += omega * dvy * k;
-              /* dv'/dtheta = k s R'(theta) v,  R' = [[-sin, -cos], [cos, -sin]] */
-              const double rtx = k * s * (-sn * lx - c * ly), rty = k * s * (c * lx - sn * ly);
-              g[2] += omega * (dvx * rtx + dvy * rty);
-              /* dv'/ds = k R(theta) v */
-              const double rsx = k * (c * lx - sn * ly), rsy = k * (sn * lx + c * ly);
-              g[3] += omega * (dvx * rsx + dvy * rsy);
-              /* dv'/dv = k s R(theta) */
-              if (gv) {
-                gv[2 * vm[e] + 0] += omega * k * s * (c * dvx + sn * dvy);
-                gv[2 * vm[e] + 1] += omega * k * s * (-sn * dvx + c * dvy);
-              }
-            }
+            pixel_terms(sc, q, k, n, c, sn, s, open, px, py, &r, G[idx], Gp[idx], g, gv);
           }
       }
       /* object-space downward force: d(H - k t_y)/dt_y = -k */
       g[1] -= dloss[NTERMS * b + 8] * sc->w[8] * k;
       for (int e = 0; e < 4; ++e) grad[4 * q + e] = g[e];
+    }
+  }
+  free(S);
+  free(Sp);
+  free(G);
+  free(Gp);
+  release(&pr);
+  return 0;
+}
+
+/* Pixel (px, py)'s distance result for item q if edge m were its nearest edge: the clamped parameter,
+ * nearest point and distance on edge m, with the inside flag of the full test kept. */
+static sd_result edge_distance(const oracle_scene *sc, const double *params, int q, double k, double px, double py,
+                               const double *P, int n, int m, int inside) {
+  const int open = is_open(sc, q);
+  const int mn = open ? (n > 1 ? m + 1 : m) : ((m + 1 == n) ? 0 : m + 1);
+  const double ax = P[2 * m], ay = P[2 * m + 1];
+  const double ex = P[2 * mn] - ax, ey = P[2 * mn + 1] - ay;
+  const double ee = ex * ex + ey * ey;
+  double u = 0.0;
+  if (ee > 0.0) {
+    u = ((px - ax) * ex + (py - ay) * ey) / ee;
+    if (u < 0.0) u = 0.0;
+    if (u > 1.0) u = 1.0;
+  }
+  sd_result r;
+  r.qx = ax + u * ex;
+  r.qy = ay + u * ey;
+  r.d = sqrt((px - r.qx) * (px - r.qx) + (py - r.qy) * (py - r.qy));
+  r.edge = m;
+  r.u = u;
+  r.inside = open ? 0 : inside;
+  r.sd = open ? stroke_radius(sc, params, q, k) - r.d : (inside ? r.d : -r.d);
+  return r;
+}
+
+/*
+ * Gradient terms that hang on a nearest-edge decision finer than a given resolution.  Where an edge that
+ * is not a neighbour of a pixel's nearest edge lies within delta(p) = delta_abs + delta_rel |p - k t| of
+ * the nearest distance, an evaluation whose distances carry errors up to delta(p) may take that edge, and
+ * the pixel's terms then come from that edge's nearest point and normal (the loss has a kink there: the
+ * pixel sits on a medial axis of the outline to that resolution).  bound[4 q + c] sums, over item q's
+ * pixels, the largest change |terms(rival) - terms(nearest)| of component c over such rivals; it is 0 for
+ * an item with no such pixel.  The neighbours of the nearest edge are excluded because they share its end
+ * points: where one of them ties, both give the same nearest point.
+ */
+int oracle_nearest_ambiguity(const oracle_scene *sc, const double *params, const double *dloss, double delta_abs,
+                             double delta_rel, double *bound) {
+  if (!sc || !params || !dloss || !bound) return -1;
+  if (sc->use_bbox && !sc->use_cutoff) return -1;
+  prepared pr;
+  prepare(sc, params, &pr);
+  int64_t total = pixel_offset(sc, sc->B);
+  double *S = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Sp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *G = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  double *Gp = (double *)malloc(sizeof(double) * (total > 0 ? total : 1));
+  dloss_images(sc, &pr, dloss, S, Sp, G, Gp);
+  for (int b = 0; b < sc->B; ++b) {
+    const int W = sc->width[b];
+    const int64_t off = pixel_offset(sc, b);
+    const double k = sc->scale[b];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = sc->shape_off[b]; q < sc->shape_off[b + 1]; ++q) {
+      double acc[4] = {0, 0, 0, 0};
+      const int n = sc->vert_off[q + 1] - sc->vert_off[q];
+      const int open = is_open(sc, q);
+      const int ne = open ? (n > 1 ? n - 1 : 1) : n;
+      if (ne > 3) {
+        const double *P = pr.P + 2 * sc->vert_off[q];
+        const double th = params[4 * q + 2], s = params[4 * q + 3];
+        const double c = cos(th), sn = sin(th);
+        const double ox = k * params[4 * q + 0], oy = k * params[4 * q + 1];
+        const int *bx = pr.box + 4 * q;
+        for (int j = bx[1]; j <= bx[3]; ++j)
+          for (int i = bx[0]; i <= bx[2]; ++i) {
+            const int64_t idx = off + (int64_t)j * W + i;
+            const double px = i + 0.5, py = j + 0.5;
+            const sd_result r = item_distance(sc, params, q, k, px, py, P, n);
+            const double delta = delta_abs + delta_rel * sqrt((px - ox) * (px - ox) + (py - oy) * (py - oy));
+            double base[4] = {0, 0, 0, 0}, worst[4] = {0, 0, 0, 0};
+            int have_base = 0;
+            for (int m = 0; m < ne; ++m) {
+              const int dm = m > r.edge ? m - r.edge : r.edge - m;
+              if (dm <= 1 || (!open && dm == ne - 1)) continue;
+              const sd_result rm = edge_distance(sc, params, q, k, px, py, P, n, m, r.inside);
+              if (!(rm.d <= r.d + delta)) continue;
+              if (!have_base) {
+                pixel_terms(sc, q, k, n, c, sn, s, open, px, py, &r, G[idx], Gp[idx], base, NULL);
+                have_base = 1;
+              }
+              double t[4] = {0, 0, 0, 0};
+              pixel_terms(sc, q, k, n, c, sn, s, open, px, py, &rm, G[idx], Gp[idx], t, NULL);
+              for (int e = 0; e < 4; ++e) {
+                const double dv = fabs(t[e] - base[e]);
+                if (dv > worst[e]) worst[e] = dv;
+              }
+            }
+            for (int e = 0; e < 4; ++e) acc[e] += worst[e];
+          }
+      }
+      for (int e = 0; e < 4; ++e) bound[4 * q + e] = acc[e];
     }
   }
   free(S);

@@ -58,6 +58,8 @@ def lib():
         L.oracle_signed_distance.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_int, ctypes.c_int, _dp, _ip]
         L.oracle_backward.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, _dp]
         L.oracle_backward_full.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, _dp, _dp]
+        L.oracle_nearest_ambiguity.argtypes = [ctypes.POINTER(_OracleScene), _dp, _dp, ctypes.c_double,
+                                               ctypes.c_double, _dp]
         L.oracle_adam.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
         L.oracle_collage_lr.argtypes = [ctypes.POINTER(_OracleScene), _dp, ctypes.c_double, _dp]
@@ -161,6 +163,21 @@ class Oracle:
         rc = lib().oracle_backward(ctypes.byref(self._s), _ptr(p), _ptr(dl), _ptr(g))
         assert rc == 0
         return g[: 4 * self.scene.num_shapes].reshape(-1, 4)
+
+    def nearest_ambiguity(self, params, delta_abs, delta_rel, dloss=None):
+        """[N,4]: per item and component, the sum over its pixels of the largest change of the pixel's
+        gradient terms if an edge that is not a neighbour of its nearest edge, within
+        delta_abs + delta_rel |p - k t| of the nearest distance, were taken as the nearest edge."""
+        p = _d(params).reshape(-1)
+        B = self.scene.num_layouts
+        dl = np.ones(NTERMS * B) if dloss is None else _d(dloss).reshape(-1)
+        if dl.size != NTERMS * B:
+            raise ValueError(f"dloss must have {NTERMS} entries per layout")
+        out = np.zeros(4 * max(self.scene.num_shapes, 1))
+        rc = lib().oracle_nearest_ambiguity(ctypes.byref(self._s), _ptr(p), _ptr(dl), float(delta_abs),
+                                            float(delta_rel), _ptr(out))
+        assert rc == 0
+        return out[: 4 * self.scene.num_shapes].reshape(-1, 4)
 
     def backward_vertices(self, params, dloss=None):
         """(grad [N,4], grad_verts [V,2]): the gradient with respect to the parameters and to every

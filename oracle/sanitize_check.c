@@ -57,13 +57,14 @@ int main(void) {
   double S[23 * 17 + 9 * 30], Sp[23 * 17 + 9 * 30], loss[18], dloss[18], grad[20], gv[22];
   double alpha[3 * 23 * 17 + 2 * 9 * 30], alpha_pad[3 * 23 * 17 + 2 * 9 * 30], sd[3 * 23 * 17 + 2 * 9 * 30];
   int32_t edge[3 * 23 * 17 + 2 * 9 * 30];
-  double quality[6], lr[20], p[20], m[20], v[20], rho[5] = {4.3, 4.1, 5.2, 0.0, 0.8};
+  double quality[6], lr[20], p[20], m[20], v[20], amb[20], rho[5] = {4.3, 4.1, 5.2, 0.0, 0.8};
   int64_t counts[8];
   for (int i = 0; i < 18; ++i) dloss[i] = 0.5 + 0.1 * i;
   int rc = 0;
   rc |= oracle_forward(&sc, params, S, Sp, loss);
   rc |= oracle_backward(&sc, params, dloss, grad);
   rc |= oracle_backward_full(&sc, params, dloss, grad, gv);
+  rc |= oracle_nearest_ambiguity(&sc, params, dloss, 1e-3, 1e-3, amb);
   rc |= oracle_render(&sc, params, 0, 5, alpha, alpha_pad);
   rc |= oracle_signed_distance(&sc, params, 0, 5, sd, edge);
   rc |= oracle_quality(&sc, params, quality, counts);
@@ -80,7 +81,7 @@ int main(void) {
     return 1;
   }
   if (!all_finite(S, npix) || !all_finite(Sp, npix) || !all_finite(loss, 18) || !all_finite(grad, 20) ||
-      !all_finite(gv, 22) || !all_finite(quality, 6) || !all_finite(p, 20)) {
+      !all_finite(gv, 22) || !all_finite(quality, 6) || !all_finite(p, 20) || !all_finite(amb, 20)) {
     printf("non-finite result\n");
     return 1;
   }

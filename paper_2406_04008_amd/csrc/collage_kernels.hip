@@ -449,8 +449,6 @@ __device__ void transform_item(const KArgs &a, int sid, int lane, float4 p, cons
     ShapeRec sr;
     sr.cx = cx;
     sr.cy = cy;
-    sr.cxf = (float)cx;
-    sr.cyf = (float)cy;
     sr.k = (float)k;
     sr.s = p.w;
     sr.orient = area2 >= 0.0 ? 1.0f : -1.0f;
@@ -1032,13 +1030,14 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   const int ntiles = ntx * LS[b].nty;
   const int x0 = txi * T, y0 = tyi * T;
   const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
-  for (int q = tid; q < T * T; q += NT) {
-    const int pxi = x0 + q % T, pyi = y0 + q / T;
-    if (pxi < W && pyi < H) {
-      const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
-      __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
+  if (!a.bin_keeps_acc)
+    for (int q = tid; q < T * T; q += NT) {
+      const int pxi = x0 + q % T, pyi = y0 + q / T;
+      if (pxi < W && pyi < H) {
+        const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
+        __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
+      }
     }
-  }
   int slots = 0;
   long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
   // candidates: every item of the layout, or the items listed for the tile's row.  Each thread loads its
@@ -1446,15 +1445,14 @@ __device__ __forceinline__ void chunk_at(const ChunkPix &c, const Rect &r, int &
   py = r.y0 + (in ? c.ly : 0);
 }
 
-// A unit record as the persistent passes use it (scalar loads and unpacking).  The float origin of the
-// scan is the double origin rounded, as the transform rounds it.
+// A unit record as the persistent passes use it (scalar loads and unpacking).  The float scan takes each
+// pixel's position relative to the double origin, computed in double and rounded once.
 struct UnitView {
   Rect r;
   int eo, ec, nv, head;
   bool open;
   float orient;
   double cx, cy;
-  float cxf, cyf;
   double sw, sw_ds;  // an open item's stroke radius and its derivative in s (0 for a closed item)
   double inv_s;      // 1 / s (0 when |s| < kScaleFloor)
   double kc, ks;     // k R(theta), loaded only when |s| < kScaleFloor
@@ -1491,8 +1489,6 @@ __device__ __forceinline__ UnitView unit_view(const KArgs &a, const UnitRec &U) 
   v.orient = (fl & kUnitClockwise) ? -1.0f : 1.0f;
   v.cx = U.cx;
   v.cy = U.cy;
-  v.cxf = (float)v.cx;
-  v.cyf = (float)v.cy;
   v.sw = 0.0;
   v.sw_ds = 0.0;
   cptr<ShapeRec> SR = konst(a.shapes) + U.sid;
@@ -1602,7 +1598,6 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec;
-    const float cxf = uv.cxf, cyf = uv.cyf;
     const double cx = uv.cx, cy = uv.cy;
     const bool open = uv.open;
     const double sw = uv.sw;
@@ -1615,9 +1610,10 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
       chunk_at(it, r, pxi, pyi, in);
       int bi = 0;
       bool par = false;
-      scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+      // the pixel relative to the item's origin, in double, and rounded once for the float scan
+      const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
+      scan_item(a.edges + eo, ec, staged, S, lane, (float)rx, (float)ry, bi, par);
       if (ec > 0) {
-        const double rx = pxi + 0.5 - cx, ry = pyi + 0.5 - cy;
         const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
         bi = nr.e;
         if (in) {
@@ -1788,6 +1784,13 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
       s1[k] = a.acc[2 * pix[k] + 1];
       mk[k] = a.mask[pix[k]];
     }
+  }
+  // within a multi-epoch call the next epoch's accumulators are zeroed here, where they are read last
+  // (not with the uniform term, whose windows read the neighbouring tiles' accumulators)
+  if (!UNI && a.pixel_clears_acc) {
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+      if (mine[k]) __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix[k]));
   }
   unsigned long long v[1][kUniBand];
   if (UNI) {
@@ -1997,7 +2000,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec;
-    const float cxf = uv.cxf, cyf = uv.cyf, orient = uv.orient;
+    const float orient = uv.orient;
     const double cx = uv.cx, cy = uv.cy;
     const bool open = uv.open;
     const double sw = uv.sw, sw_ds = uv.sw_ds;
@@ -2063,7 +2066,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           bi = (int)(code & 0x7fffu);
           par = (code & 0x8000u) != 0u;
         } else {
-          scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+          scan_item(a.edges + eo, ec, staged, S, lane, (float)rx, (float)ry, bi, par);
           bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry).e;
         }
         if (in) {
@@ -2123,7 +2126,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
     const Rect r = uv.r;
     const long long q = walk_chunk0(wk);
     const int eo = uv.eo, ec = uv.ec, nv = uv.nv;
-    const float cxf = uv.cxf, cyf = uv.cyf, orient = uv.orient;
+    const float orient = uv.orient;
     const double cx = uv.cx, cy = uv.cy;
     const bool open = uv.open;
     const double sw = uv.sw;
@@ -2147,7 +2150,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_vgrad(KArgs a) {
         bi = (int)(code & 0x7fffu);
         par = (code & 0x8000u) != 0u;
       } else {
-        scan_item(a.edges + eo, ec, staged, S, lane, pxi + 0.5f - cxf, pyi + 0.5f - cyf, bi, par);
+        scan_item(a.edges + eo, ec, staged, S, lane, (float)rx, (float)ry, bi, par);
         bi = nearest_refined(a.edges_d + eo, ec, bi, rx, ry).e;
       }
       if (in) {
@@ -2447,8 +2450,8 @@ __global__ __launch_bounds__(256) void k_render(KArgs a, int first, float *alpha
   if (ec > 0 && pxi >= bb.x && pxi <= bb.z && pyi >= bb.y && pyi <= bb.w) {
     int bi;
     bool par;
-    edge_scan(konst(a.edges) + eo, ec, pxi + 0.5f - SR[q].cxf, pyi + 0.5f - SR[q].cyf, bi, par);
     const double rx = pxi + 0.5 - SR[q].cx, ry = pyi + 0.5 - SR[q].cy;
+    edge_scan(konst(a.edges) + eo, ec, (float)rx, (float)ry, bi, par);
     const Nearest nr = nearest_refined(a.edges_d + eo, ec, bi, rx, ry);
     const double d = sqrt(nr.d2);
     double ad, apd;

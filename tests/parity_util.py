@@ -31,7 +31,9 @@ def check_loss(gpu, ref, what="loss", rtol=LOSS_RTOL):
     return float((err / np.maximum(np.abs(ref), 1e-30)).max()) if err.size else 0.0
 
 
-def grad_error(gpu, ref):
+def grad_error(gpu, ref, slack=None):
+    """Largest |g - g_ref| / max(|g_ref|, floor) over items and components; with slack ([N,4], >= 0), the
+    part of each difference beyond the slack (a difference within its slack counts as 0)."""
     gpu = np.asarray(gpu, np.float64).reshape(-1, 4)
     ref = np.asarray(ref, np.float64).reshape(-1, 4)
     if ref.size == 0:
@@ -39,16 +41,24 @@ def grad_error(gpu, ref):
     floor = 0.01 * np.abs(ref).max(0)
     denom = np.maximum(np.abs(ref), floor[None, :])
     denom = np.where(denom > 0, denom, 1.0)
-    return float((np.abs(gpu - ref) / denom).max())
+    diff = np.abs(gpu - ref)
+    if slack is not None:
+        diff = np.maximum(diff - np.asarray(slack, np.float64).reshape(-1, 4), 0.0)
+    return float((diff / denom).max())
 
 
-def check_grad(gpu, ref, what="grad", rtol=GRAD_RTOL):
-    e = grad_error(gpu, ref)
+def check_grad(gpu, ref, what="grad", rtol=GRAD_RTOL, slack=None):
+    """The gradient bar; slack ([N,4]) widens it per item and component by an amount the oracle derived
+    (the nearest-edge ambiguity bound: pixels whose nearest edge float32 cannot resolve)."""
+    e = grad_error(gpu, ref, slack)
     if e > rtol:
         g = np.asarray(gpu, np.float64).reshape(-1, 4)
         r = np.asarray(ref, np.float64).reshape(-1, 4)
         floor = 0.01 * np.abs(r).max(0)
-        rel = np.abs(g - r) / np.maximum(np.maximum(np.abs(r), floor[None, :]), 1e-30)
+        diff = np.abs(g - r)
+        if slack is not None:
+            diff = np.maximum(diff - np.asarray(slack, np.float64).reshape(-1, 4), 0.0)
+        rel = diff / np.maximum(np.maximum(np.abs(r), floor[None, :]), 1e-30)
         i, c = np.unravel_index(int(np.argmax(rel)), rel.shape)
         raise AssertionError(f"{what}: relative error {e:.3e} > {rtol} at item {i} component {c}: "
                              f"gpu {g[i, c]!r} ref {r[i, c]!r} floor {floor[c]!r}")

@@ -771,3 +771,40 @@ def test_config1_two_hundred_adam_steps_reach_a_packed_layout():
     q1, _ = o.quality(p)
     assert L1 < L0 / 5, (L0, L1)
     assert q0[0, 0] < 0.3 and q1[0, 0] > 0.8 and q1[0, 1] < 0.05 and q1[0, 2] < 0.05, (q0, q1)
+
+
+def test_nearest_ambiguity_is_the_gradient_jump_across_a_medial_axis():
+    """An axis-aligned 20.6 x 4.5 rectangle centred on a pixel centre: the pixels of its middle row between
+    the short edges are equidistant from the two long edges, which are not neighbours, so the gradient
+    jumps there (the row sits on the outline's medial axis).  Moving the item by +-1e-9 px in y breaks
+    every tie the same way: the t_y bound must equal the jump of the oracle's own gradient, and t_x and s
+    must have none (the normals are vertical; the two nearest points are mirror images).  theta's terms
+    flip sign with the pixel's column, so its bound is the sum of their sizes, 2 omega k |dx| per pixel, while
+    its jump cancels.  (Half-width minus half-height is not an integer, so no corner bisector meets a pixel
+    centre, and no edge passes through one.)"""
+    sc = S.single_shape_scene(S.rectangle(10.3, 2.25), 64, 64, t=(32.5, 32.5))
+    o = Oracle(sc)
+    p = sc.params.astype(np.float64)
+    b = o.nearest_ambiguity(p, 0.0, 0.0)[0]
+    eps = 1e-9
+    gp = o.backward(p + np.array([[0.0, eps, 0.0, 0.0]]))[0]
+    gm = o.backward(p - np.array([[0.0, eps, 0.0, 0.0]]))[0]
+    assert b[1] > 0.5
+    assert abs(b[1] - abs(gp[1] - gm[1])) <= 1e-6 * b[1]
+    assert b[0] <= 1e-12 and b[3] <= 1e-12
+    assert abs(gp[2] - gm[2]) <= 1e-9 * b[2]
+    # theta: the row's pixels within the long edges' reach, each 2 omega |dx| (k = 1, omega the same for all)
+    omega = b[1] / (2.0 * 17)  # 17 pixels (|dx| <= 8) carry the t_y jump of 2 omega each
+    assert abs(b[2] - sum(2.0 * omega * abs(dx) for dx in range(-8, 9))) <= 1e-9 * b[2]
+
+
+def test_nearest_ambiguity_needs_a_rival_within_the_resolution():
+    """The same rectangle 1e-5 px off the tie: the middle row's long edges are 2e-5 px apart in distance, so
+    they count at a resolution of 3e-5 px and not at 1e-5 px; generic layouts have no such pixel."""
+    sc = S.single_shape_scene(S.rectangle(10.3, 2.25), 64, 64, t=(32.5, 32.5))
+    o = Oracle(sc)
+    p = sc.params.astype(np.float64) + np.array([[0.0, 1e-5, 0.0, 0.0]])
+    assert o.nearest_ambiguity(p, 3e-5, 0.0)[0, 1] > 0.5
+    assert not np.any(o.nearest_ambiguity(p, 1e-5, 0.0))
+    for sc in (S.config1(0), S.config2(0)):
+        assert not np.any(Oracle(sc).nearest_ambiguity(sc.params, 2.0 ** -20, 2.0 ** -20))
