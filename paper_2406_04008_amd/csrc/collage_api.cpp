@@ -561,13 +561,8 @@ int iterate_impl(const collage_scene *s, float *params, float *cov, float *cov_p
   const int32_t stride = timer ? (int32_t)((n + (int64_t)timer->start.size() - 1) / (int64_t)timer->start.size()) : 1;
   if (timer) timer->recorded = (n + stride - 1) / stride;
   hipError_t e = launch_transform(a, st);
-  // without the uniform term, each epoch's per-pixel pass zeroes the accumulators for the next epoch of
-  // the call, and binning skips that for every epoch but the first
-  const bool uni = a.w[5] != 0.0f;
   for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
     const bool stamp = timer && i % stride == 0;
-    a.bin_keeps_acc = (!uni && i > 0) ? 1 : 0;
-    a.pixel_clears_acc = (!uni && i + 1 < n) ? 1 : 0;
     e = launch_bin(a, st);
     if (e == hipSuccess) e = launch_scan(a, st);
     if (e == hipSuccess)

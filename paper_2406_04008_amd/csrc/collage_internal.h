@@ -163,8 +163,6 @@ struct KArgs {
   const float *dloss;    // [B,kLossTerms] or null (= 1)
   int32_t write_loss;    // tile loss partials are written (forward and fused calls)
   int32_t keep_codes;    // the coverage pass stores nearest-edge codes (adjoint calls)
-  int32_t pixel_clears_acc;  // 1: the per-pixel pass zeroes S, S_pad after reading them (for the next epoch)
-  int32_t bin_keeps_acc;     // 1: binning leaves S, S_pad as they are (the previous epoch's per-pixel pass zeroed them)
   // constants
   float tau, inv_tau, r_cut, r_pad;
   double inv_tau_d;      // 1 / tau

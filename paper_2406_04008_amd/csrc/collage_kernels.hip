@@ -1030,14 +1030,13 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   const int ntiles = ntx * LS[b].nty;
   const int x0 = txi * T, y0 = tyi * T;
   const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
-  if (!a.bin_keeps_acc)
-    for (int q = tid; q < T * T; q += NT) {
-      const int pxi = x0 + q % T, pyi = y0 + q / T;
-      if (pxi < W && pyi < H) {
-        const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
-        __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
-      }
+  for (int q = tid; q < T * T; q += NT) {
+    const int pxi = x0 + q % T, pyi = y0 + q / T;
+    if (pxi < W && pyi < H) {
+      const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
+      __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
     }
+  }
   int slots = 0;
   long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
   // candidates: every item of the layout, or the items listed for the tile's row.  Each thread loads its
@@ -1784,13 +1783,6 @@ __global__ __launch_bounds__(UNI ? kPixThreads : 256) void k_pixel(KArgs a) {
       s1[k] = a.acc[2 * pix[k] + 1];
       mk[k] = a.mask[pix[k]];
     }
-  }
-  // within a multi-epoch call the next epoch's accumulators are zeroed here, where they are read last
-  // (not with the uniform term, whose windows read the neighbouring tiles' accumulators)
-  if (!UNI && a.pixel_clears_acc) {
-#pragma unroll
-    for (int k = 0; k < PX; ++k)
-      if (mine[k]) __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix[k]));
   }
   unsigned long long v[1][kUniBand];
   if (UNI) {
