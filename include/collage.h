@@ -86,11 +86,16 @@ extern "C" {
  *                               call's last epoch (the units of work of the rasterization).
  *   [COLLAGE_STATUS_RESCANNED]  of those, the chunks whose nearest edges the adjoint found by scanning
  *                               the edges again, beyond the scene's code capacity (0 without a backward).
+ *   [COLLAGE_STATUS_UNIT_OVERFLOW] (epoch, layout) pairs of the call whose work units did not fit the
+ *                               layout's unit capacity.  Such a layout lists no units in that epoch: its
+ *                               coverage is 0 and its items' gradients are 0, so the call's results are
+ *                               not valid and the scene must be created with a larger unit_capacity.
  * The other words are reserved (0).  collage_read_status copies them to the host.
  */
 #define COLLAGE_STATUS_NONFINITE 0
 #define COLLAGE_STATUS_CHUNKS 1
 #define COLLAGE_STATUS_RESCANNED 2
+#define COLLAGE_STATUS_UNIT_OVERFLOW 3
 #define COLLAGE_STATUS_WORDS 8
 
 
@@ -138,6 +143,14 @@ typedef struct collage_scene_desc {
   int32_t bin_chunk;            /* 0..1024, accepted and not used: binning tests each candidate item once and
                                    writes its unit from the testing thread, with no item list in LDS */
   uint32_t flags;               /* 0 or COLLAGE_FLAG_AREA_MEAN; other bits are rejected */
+  int32_t unit_capacity;        /* (screen tile, item) work units the workspace holds per layout and epoch,
+                                   one per item and tile its support box meets (108 bytes each).
+                                   0 = default: every item in every tile of the layout, or, when less, four
+                                   times the units of its items at twice their rim radius (read from verts
+                                   and stroke at creation), at least 65536; -1 = every item in every tile
+                                   (never overflows); > 0 = that many (at most every item in every tile).
+                                   An epoch in which a layout needs more is counted in
+                                   COLLAGE_STATUS_UNIT_OVERFLOW; -2 and below are rejected */
 } collage_scene_desc;
 
 /*

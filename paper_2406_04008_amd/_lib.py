@@ -27,6 +27,7 @@ STATIC_SCRATCH_BYTES = 64 << 20  # the scratch of collage_forward_backward_stati
 STATUS_NONFINITE = 0  # (epoch, item) pairs of the last call whose parameters were not all finite
 STATUS_CHUNKS = 1  # 64-pixel chunks of the last epoch's coverage pass
 STATUS_RESCANNED = 2  # of those, chunks the adjoint rescanned (beyond the code capacity)
+STATUS_UNIT_OVERFLOW = 3  # (epoch, layout) pairs whose work units did not fit the layout's pool (results invalid)
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -44,7 +45,7 @@ class SceneDesc(ctypes.Structure):
         ("w_pad", ctypes.c_float), ("w_down", ctypes.c_float), ("w_uniform", ctypes.c_float),
         ("w_wmse", ctypes.c_float), ("w_centre", ctypes.c_float), ("w_objdown", ctypes.c_float),
         ("tile", ctypes.c_int32), ("code_capacity", ctypes.c_int32), ("bin_chunk", ctypes.c_int32),
-        ("flags", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("unit_capacity", ctypes.c_int32),
     ]
 
 

@@ -33,8 +33,9 @@ class LaunchConfig:
 
 
 DEFAULT_SPACE = [LaunchConfig(t, c, 0) for t, c in itertools.product((8, 16, 32), (-1, 0))]
-# candidates whose workspace exceeds this are not tried: the tile lists hold a slot per (tile, item), so
-# small tiles on large canvases with many items need workspaces that grow with canvas area x items
+# candidates whose workspace exceeds this are not tried (with the default unit pools no standard workload
+# comes near it; a scene created with unit_capacity=-1 holds every item in every tile, which grows with
+# canvas area x items)
 MAX_WORKSPACE_BYTES = 8 << 30
 
 _CACHE: Dict[str, Tuple[LaunchConfig, Dict[str, float]]] = {}

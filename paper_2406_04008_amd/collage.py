@@ -40,7 +40,7 @@ class CollageScene:
 
     def __init__(self, scene: Scene, level: Optional[int] = None, device="cuda", tile: int = 0,
                  code_capacity: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None,
-                 allocate_workspace: bool = True):
+                 allocate_workspace: bool = True, unit_capacity: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("CollageScene needs a GPU (the HIP library has no CPU path)")
         self.lib = _lib.load()
@@ -82,6 +82,7 @@ class CollageScene:
         if getattr(scene, "area_mean", False):
             flags |= _lib.FLAG_AREA_MEAN
         d.tile, d.code_capacity, d.bin_chunk, d.flags = tile, code_capacity, bin_chunk, flags
+        d.unit_capacity = unit_capacity
         self._desc = d
         h_ = ctypes.c_void_p()
         with torch.cuda.device(dev):

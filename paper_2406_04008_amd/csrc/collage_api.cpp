@@ -55,7 +55,8 @@ struct collage_scene {
   LayoutRec *d_layouts = nullptr;
   int32_t *d_vert_off = nullptr;
   // workspace layout
-  int64_t unit_cap = 0;
+  int64_t unit_pool = 0;  // units of all layouts' pools
+  size_t off_ibase = 0, off_rbase = 0;
   size_t off_status = 0, off_shapes = 0, off_bins = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
          off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_head = 0, off_spill = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
@@ -73,6 +74,37 @@ struct collage_timer {
 };
 
 namespace {
+
+// A layout's default unit pool holds four times the units of its items at twice their rim radius, at
+// least this many (and never more than every item in every tile).
+constexpr int64_t kMinUnitCapacity = 65536;
+
+// Per layout, the units of its items at twice their rim radius: per item, the screen tiles that a support
+// box of side 2 (k 2 (rho + w) + r_cut + r_pad) + 2 px can meet, at most the layout's tiles (rho: the
+// largest vertex radius, w: the stroke half-width, both canonical px, read from the device arrays).
+int unit_bounds(const collage_scene_desc *d, const collage_scene *s, std::vector<int64_t> &bound) {
+  bound.assign(s->B, 0);
+  if (s->N == 0) return COLLAGE_OK;
+  std::vector<float> v(2 * (size_t)s->V), w(s->N, 0.0f);
+  hipError_t e = hipSuccess;
+  if (s->V > 0) e = hipMemcpy(v.data(), d->verts, sizeof(float) * v.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && d->stroke) e = hipMemcpy(w.data(), d->stroke, sizeof(float) * w.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(verts, stroke) for the unit capacity");
+  const double ext = (double)d->r_cut + std::max(0.0, (double)d->r_pad);
+  for (int b = 0; b < s->B; ++b) {
+    const LayoutRec &L = s->layouts[b];
+    const int64_t tiles_b = (int64_t)L.ntx * L.nty;
+    for (int i = L.shape_begin; i < L.shape_end; ++i) {
+      double rho = 0.0;
+      for (int m = s->vert_off[i]; m < s->vert_off[i + 1]; ++m)
+        rho = std::max(rho, std::sqrt((double)v[2 * m] * v[2 * m] + (double)v[2 * m + 1] * v[2 * m + 1]));
+      const double side = 2.0 * ((double)L.k * 2.0 * (rho + std::max(0.0f, w[i])) + ext) + 2.0;
+      const double per_axis = std::ceil(side / s->tile) + 1.0;
+      bound[b] += std::min<int64_t>(tiles_b, (int64_t)std::min(per_axis * per_axis, 1e12));
+    }
+  }
+  return COLLAGE_OK;
+}
 
 int validate_desc(const collage_scene_desc *d) {
   if (!d) return fail(COLLAGE_ERR_INVALID, "desc is NULL");
@@ -115,6 +147,7 @@ int validate_desc(const collage_scene_desc *d) {
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32)
     return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8, 16 or 32 (got %d)", d->tile);
   if (d->code_capacity < -1) return fail(COLLAGE_ERR_INVALID, "code_capacity must be -1 or >= 0");
+  if (d->unit_capacity < -1) return fail(COLLAGE_ERR_INVALID, "unit_capacity must be -1, 0 or > 0");
   if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)
     return fail(COLLAGE_ERR_INVALID, "bin_chunk must be 0..%d", kMaxBinChunk);
   if (d->flags & ~(uint32_t)COLLAGE_FLAG_AREA_MEAN) return fail(COLLAGE_ERR_UNSUPPORTED, "unknown flags 0x%x", d->flags);
@@ -135,7 +168,8 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.scan_in_cover = s->total_tiles <= kScanInCoverTiles ? 1 : 0;
   a.tile = s->tile;
   a.bin_chunk = s->bin_chunk;
-  a.unit_cap = (int32_t)s->unit_cap;
+  a.item_base = reinterpret_cast<int32_t *>(w + s->off_ibase);
+  a.row_base = reinterpret_cast<long long *>(w + s->off_rbase);
   a.chunk_cap = s->chunk_cap;
   a.code_cap = s->code_cap;
   a.cover_grid = s->cover_grid;
@@ -150,7 +184,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.bins = reinterpret_cast<BinRec *>(w + s->off_bins);
   a.edges = reinterpret_cast<EdgeRec *>(w + s->off_edges);
   a.edges_d = reinterpret_cast<EdgeD *>(w + s->off_edges_d);
-  a.tile_count = reinterpret_cast<int32_t *>(w + s->off_count);
+  a.tile_units = reinterpret_cast<int2 *>(w + s->off_count);
   a.block_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
   a.item_unit = reinterpret_cast<int2 *>(w + s->off_iunit);
@@ -245,7 +279,6 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
     L.shape_begin = desc->layout_shapes[b];
     L.shape_end = desc->layout_shapes[b + 1];
     L.pix_off = pix;
-    L.list_off = list;
     L.k = desc->layout_scale[b];
     L.ptile_off = (int32_t)ptiles;
     L.row_off = (int32_t)rows;
@@ -268,15 +301,44 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->total_rows = rows;
   s->row_list_total = rlist;
   s->list_total = list;
-  // every (tile, item) pair is one work unit: at most one per list entry
-  s->unit_cap = list;
-  if (s->unit_cap > (int64_t)0x7fffffff) {
-    delete s;
-    return fail(COLLAGE_ERR_INVALID, "too many (tile, item) pairs");
+  // every (tile, item) pair whose support box meets the tile is one work unit; each layout's units live in
+  // a pool of its own, sized by unit_capacity: every item in every tile (-1), the bound above (0), or the
+  // given count (at most every item in every tile)
+  std::vector<int64_t> bound;
+  if (desc->unit_capacity == 0) {
+    rc = unit_bounds(desc, s, bound);
+    if (rc) {
+      delete s;
+      return rc;
+    }
   }
+  int64_t pool = 0;
+  for (int b = 0; b < s->B; ++b) {
+    LayoutRec &L = s->layouts[b];
+    const int64_t dense = (int64_t)L.ntx * L.nty * (L.shape_end - L.shape_begin);
+    int64_t cap = dense;
+    if (desc->unit_capacity > 0)
+      cap = std::min<int64_t>(dense, desc->unit_capacity);
+    else if (desc->unit_capacity == 0)
+      cap = std::min<int64_t>(dense, std::max<int64_t>(4 * bound[b], kMinUnitCapacity));
+    if (cap > (int64_t)0x7fffffff) {
+      delete s;
+      return fail(COLLAGE_ERR_INVALID, "layout %d: %lld units exceed a pool's limit of 2^31 - 1; set unit_capacity", b,
+                  (long long)cap);
+    }
+    L.list_off = pool;
+    L.unit_cap = (int32_t)cap;
+    pool += cap;
+  }
+  if (pool > (int64_t)0x7fffffff) {
+    delete s;
+    return fail(COLLAGE_ERR_INVALID, "the unit pools (%lld units) exceed 2^31 - 1 entries; set unit_capacity",
+                (long long)pool);
+  }
+  s->unit_pool = std::max<int64_t>(pool, 1);
   // nearest-edge codes: one per lane of every 64-pixel chunk of the pass; a unit has at most
   // tile^2 / 64 chunks.  Default: four items per pixel on average (units beyond it are rescanned).
-  const int64_t max_chunks = list * (int64_t)((s->tile * s->tile + 63) / 64);
+  const int64_t max_chunks = s->unit_pool * (int64_t)((s->tile * s->tile + 63) / 64);
   s->chunk_cap = max_chunks;
   int64_t code_cap = desc->code_capacity;
   if (code_cap < 0) code_cap = std::max<int64_t>(65536, 4 * ((pix + 63) / 64));
@@ -284,6 +346,10 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   size_t off = 0;
   s->off_status = off;
   off = align256(off + sizeof(int32_t) * kStatusWords);
+  s->off_ibase = off;
+  off = align256(off + sizeof(int32_t) * (size_t)s->N);
+  s->off_rbase = off;
+  off = align256(off + sizeof(long long) * (size_t)rows);
   s->off_shapes = off;
   off = align256(off + sizeof(ShapeRec) * (size_t)s->N);
   s->off_bins = off;
@@ -293,7 +359,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->off_edges_d = off;
   off = align256(off + sizeof(EdgeD) * (size_t)s->V);
   s->off_count = off;
-  off = align256(off + sizeof(int32_t) * (size_t)tiles);
+  off = align256(off + sizeof(int2) * (size_t)tiles);
   s->off_loss = off;
   off = align256(off + sizeof(double) * kLossTerms * (size_t)ptiles);
   s->off_uflags = off;
@@ -301,9 +367,9 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->off_vacc = off;
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)s->V);
   s->off_list = off;
-  off = align256(off + sizeof(int32_t) * (size_t)list);
+  off = align256(off + sizeof(int32_t) * (size_t)s->unit_pool);
   s->off_iunit = off;
-  off = align256(off + sizeof(int2) * (size_t)list);
+  off = align256(off + sizeof(int2) * (size_t)s->unit_pool);
   s->off_rcount = off;
   off = align256(off + sizeof(int32_t) * (size_t)rows);
   s->off_rlist = off;
@@ -315,15 +381,15 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->cover_grid = cus * kCoverBlocksPerCU;
   s->adjoint_grid = cus * kAdjointBlocksPerCU;
   s->off_aux = off;
-  off = align256(off + sizeof(int4) * (size_t)list);
+  off = align256(off + sizeof(int4) * (size_t)s->unit_pool);
   s->off_units = off;
-  off = align256(off + sizeof(UnitRec) * (size_t)list);
+  off = align256(off + sizeof(UnitRec) * (size_t)s->unit_pool);
   s->off_tcost = off;
   off = align256(off + sizeof(int2) * (size_t)tiles);
   s->off_tpre = off;
   off = align256(off + sizeof(long long) * 2 * ((size_t)tiles + 1));
   s->off_head = off;
-  off = align256(off + sizeof(double4) * (size_t)list);
+  off = align256(off + sizeof(double4) * (size_t)s->unit_pool);
   s->off_spill = off;
   off = align256(off + sizeof(double4) * (size_t)s->adjoint_grid * kPersistWaves);
   s->off_acc = off;

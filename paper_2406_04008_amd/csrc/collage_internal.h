@@ -17,10 +17,11 @@ struct alignas(16) LayoutRec {
   int32_t shape_end;
   int32_t ptile_off;    // first kPixTile x kPixTile pixel tile of the layout (per-pixel and window passes)
   int64_t pix_off;      // first pixel in packed images
-  int64_t list_off;     // first entry of this layout's per-tile item lists (capacity: items of the layout per tile)
+  int64_t list_off;     // first entry of this layout's unit pool (tile lists, unit records, per-item map)
   float k;              // level scale
   int32_t row_off;      // first global tile row of the layout
   int64_t row_list_off; // first entry of this layout's per-row item lists (capacity: items per row)
+  int32_t unit_cap;     // units this layout's pool holds
 };
 
 // Per item, written by the transform kernel every call.
@@ -109,7 +110,10 @@ struct KArgs {
   int32_t total_ptiles;  // pixel tiles over all layouts
   int32_t tile;          // tile edge in px (8, 16 or 32)
   int32_t bin_chunk;     // items binned per pass
-  int32_t unit_cap;      // upper bound of the number of units (list entries)
+  int32_t *item_base;    // [N] each item's first per-item map entry, -1 when its layout's units did not
+                         // fit its pool (written by binning)
+  long long *row_base;   // [rows] the layout's units in earlier tile rows, -1 when they do not fit its
+                         // pool (written by the row pass)
   int64_t chunk_cap;     // upper bound of the number of 64-pixel chunks of a pass (bounds the code capacity)
   int64_t code_cap;      // 64-pixel chunks whose nearest-edge codes are kept between the coverage and
                          // adjoint passes (the first code_cap chunks of the pass)
@@ -128,18 +132,18 @@ struct KArgs {
   EdgeD *edges_d;
   // binning outputs
   int32_t *status;       // [kStatusWords] device status words (workspace offset 0)
-  int32_t *tile_count;
-  int32_t *tile_list;
-  int2 *item_unit;       // per layout [items][tiles]: the item's unit in the tile (its chunks, chunks of the
-                         // tile's earlier units), set where the tile lists the item; the same index holds
-                         // the unit's head partial
+  int2 *tile_units;      // [tiles] each tile's units and its first pool entry
+  int32_t *tile_list;    // pool: each tile's items, in item order, from its first pool entry on
+  int2 *item_unit;       // pool, per-item map: per item from item_base[item] on, per tile of its span in
+                         // row-major order, its unit there (the unit's chunks, chunks of the tile's
+                         // earlier units); the same index holds the unit's head partial
   int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
   int32_t scan_in_cover; // 1: the coverage kernel computes the tile prefixes (no scan launch)
   int32_t total_rows;    // tile rows over all layouts
   int32_t *row_count;    // [rows] items whose support box meets the row band
   int32_t *row_list;     // per layout [tile rows][items]: those items, in item order
-  UnitRec *units;        // per list entry (tile, slot) = unit: its record
-  int4 *entry_aux;       // per list entry (tile, slot) = unit: (64-pixel chunks, coverage cost per chunk,
+  UnitRec *units;        // pool, beside tile_list: each unit's record
+  int4 *entry_aux;       // pool, beside tile_list: (64-pixel chunks, coverage cost per chunk,
                          // chunks of the tile's earlier units, coverage cost of the tile's earlier units)
   int2 *tile_cost;       // [tiles] summed coverage cost and chunks of the tile's units
   long long *tile_pre;   // [2][tiles + 1] exclusive prefix sums of the tile costs and of the tile chunks
@@ -147,7 +151,7 @@ struct KArgs {
   // accumulators
   unsigned long long *acc;  // [pixels][2] fixed-point S and S_pad (2^-40 units)
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
-  double4 *head;            // per layout [items][tiles] (the item_unit index): the adjoint sums (n_x, n_y,
+  double4 *head;            // pool, per-item map (the item_unit index): the adjoint sums (n_x, n_y,
                             // theta, scale terms) of the piece of the unit that starts at its first chunk
   double4 *spill;           // [adjoint waves]: the sums of a wave's first piece when it starts inside a unit
                             // (only a wave's first piece can; the update finds such waves by their shares)
@@ -213,7 +217,7 @@ constexpr int kDefaultBinChunk = 1024;
 constexpr int kMaxBinChunk = 1024;
 constexpr int kEdgePad = 4;  // edge records past the last item that the scalar-cache scan may fetch
 constexpr int kStageEdges = 128;   // edge records a wave stages in LDS at a time (4 KiB)
-constexpr int kScanInCoverTiles = 512;  // up to this many tiles the coverage kernel scans them itself
+constexpr int kScanInCoverTiles = 448;  // up to this many tiles the coverage kernel scans them itself (LDS: 6 resident workgroups per CU)
 constexpr int64_t kRowBinTests = 1 << 21;  // box tests (tiles x items) above which the row pass is used
 constexpr int kLossTerms = 9;   // overlap, contain, fill, pad, down, uniform, wmse, centre, objdown
 constexpr double kWmseIn = 1.0;    // eq. 5 penalty inside the container

@@ -8,7 +8,10 @@
 //                next epoch.)
 //   k_bin        one workgroup per screen tile: the layout's items whose support box meets the tile,
 //                in item order; each (tile, item) is a work unit, the box clipped to the tile, packed
-//                row by row into 64-pixel chunks.  Clears the tile's coverage accumulators.
+//                row by row into 64-pixel chunks, stored in the layout's unit pool without gaps (a
+//                tile's first unit is the number of the layout's units in earlier tiles, summed from
+//                each item's tile span).  Clears the tile's coverage accumulators.  (Large scenes:
+//                k_rowbin first lists each tile row's items and its first unit.)
 //   k_scan       one workgroup: prefix sums of the tiles' work costs and chunk counts (up to
 //                kScanInCoverTiles tiles every coverage workgroup computes them itself instead).
 //   k_cover      persistent waves, each taking an equal share of the pass's cost (split at chunk
@@ -736,42 +739,43 @@ __device__ __forceinline__ double4 adjoint_terms(const KArgs &a, const EdgeD &e,
   return t;
 }
 
-// Bins items [cb, ce) of a layout whose support box meets the tile rectangle, in item order.
-// Candidates are items cb .. ce - 1, or with src the items src[cb] .. src[ce - 1] (in item order).
-template <int NT>
-__device__ int bin_chunk(const KArgs &a, int cb, int ce, int x0, int y0, int x1, int y1, int *s_list, int *s_wcnt,
-                         int32_t *glist, const int32_t *src = nullptr) {
-  constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  int count = 0;
-  for (int base = cb; base < ce; base += NT) {
-    const int pos = base + tid;
-    const int sid = pos < ce ? (src ? src[pos] : pos) : 0;
-    bool hit = false;
-    if (pos < ce) {
-      const int4 bb = a.bins[sid].box;
-      // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
-      hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x1 || bb.z < x0 || bb.y > y1 || bb.w < y0);
-    }
-    const unsigned long long m = __ballot(hit);
-    const int before = __popcll(m & ((1ull << l) - 1ull));
-    if (l == 0) s_wcnt[w] = __popcll(m);
-    __syncthreads();
-    int off = count, tot = count;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const int cj = s_wcnt[j];
-      if (j < w) off += cj;
-      tot += cj;
-    }
-    if (hit) {
-      s_list[off + before] = sid;
-      if (glist) glist[off + before] = sid;
-    }
-    count = tot;
-    __syncthreads();
+// ------------------------------------------------------------------------------------------------
+// Unit numbering.  An item's support box meets the screen tiles [tx0, tx0 + tw) x [ty0, ty0 + th) of its
+// layout (the box lies on the canvas, so these are floor divisions; tw = th = 0 for an empty box), and
+// each of those (tile, item) pairs is one work unit.  A layout's units are numbered twice, both times
+// without gaps from the layout's first pool entry: in row-major tile order and, within a tile, in item
+// order (the tile lists and unit records); and in item order and, within an item, in row-major order
+// of its tiles (the per-item map read by the update).  A tile's first unit is then the number of the
+// layout's units in earlier tiles, and an item's first map entry the number of units of earlier items:
+// sums over the items of closed forms in their tile spans, so binning needs no counters and no
+// separate scan, and the layout needs room for its units only.
+// ------------------------------------------------------------------------------------------------
+struct TileSpan {
+  int tx0, ty0, tw, th;
+};
+
+template <int T>
+__device__ __forceinline__ TileSpan tile_span(int4 bb) {
+  TileSpan t = {0, 0, 0, 0};
+  if (bb.x <= bb.z && bb.y <= bb.w) {
+    t.tx0 = bb.x / T;
+    t.ty0 = bb.y / T;
+    t.tw = bb.z / T - t.tx0 + 1;
+    t.th = bb.w / T - t.ty0 + 1;
   }
-  return count;
+  return t;
+}
+
+// The item's units in the tile rows before row tyi.
+__device__ __forceinline__ long long units_in_rows_before(const TileSpan &t, int tyi) {
+  return (long long)min(max(tyi - t.ty0, 0), t.th) * t.tw;
+}
+
+// The item's units before tile (txi, tyi) in row-major tile order; with in_row_only, only those in
+// row tyi (the rows before are counted per row by the row pass).
+__device__ __forceinline__ long long units_before_tile(const TileSpan &t, int txi, int tyi, bool in_row_only) {
+  const bool in_row = tyi >= t.ty0 && tyi < t.ty0 + t.th;
+  return (in_row_only ? 0ll : units_in_rows_before(t, tyi)) + (in_row ? min(max(txi - t.tx0, 0), t.tw) : 0);
 }
 
 // Work units are the (tile, item) pairs of the per-tile lists, in tile order and slot order.  A unit
@@ -793,7 +797,7 @@ struct Walk {
   long long p, end;        // cost prefix of the current unit (in this pass); end of the wave's range
   long long q0;            // first chunk of the tile
   const long long *Q;      // [tiles + 1] chunk prefix of the tiles (LDS or global)
-  const int *C;            // [tiles] units per tile (LDS), or null: tile_count in global memory
+  const int2 *C;           // [tiles] units and first pool entry per tile (LDS), or null: tile_units
   int4 aux;                // (chunks, cost per chunk, chunks and cost of the tile's earlier units) of the unit
   int jlo, jhi;            // the wave's chunks [jlo, jhi) of the current unit
   bool adj;
@@ -809,14 +813,22 @@ __device__ __forceinline__ void walk_tile(const KArgs &a, Walk &w, int T) {
   const int b = layout_of_tile(LS, a.num_layouts, w.tile);
   w.W = LS[b].W;
   const int ntx = LS[b].ntx;
-  const int nb = LS[b].shape_end - LS[b].shape_begin;
   const int lt = w.tile - LS[b].tile_off;
   const int tyi = lt / ntx;
   w.x0 = (lt - tyi * ntx) * T;
   w.y0 = tyi * T;
   w.pix_off = LS[b].pix_off;
-  w.list_base = LS[b].list_off + (int64_t)lt * nb;
-  w.count = w.C != nullptr ? uniform(w.C[w.tile]) : konst(a.tile_count)[w.tile];
+  int2 tu;
+  if (w.C != nullptr) {
+    tu = w.C[w.tile];
+    tu.x = uniform(tu.x);
+    tu.y = uniform(tu.y);
+  } else {
+    cptr<int> r = (cptr<int>)(konst(a.tile_units) + w.tile);
+    tu = make_int2(r[0], r[1]);
+  }
+  w.count = tu.x;
+  w.list_base = tu.y;
   w.q0 = uniform_ll(w.Q[w.tile]);
 }
 
@@ -909,9 +921,9 @@ __device__ __forceinline__ long long share_bound(long long tot, int g, int nwave
 
 // First piece of persistent wave gw: returns false when the wave has no work.
 // P: [tiles + 1] prefix of the pass's tile costs (chunks for the adjoint passes); Q: the chunk prefix;
-// C: the tiles' unit counts in LDS, or null (global).
+// C: the tiles' unit counts and first pool entries in LDS, or null (global).
 __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int nwaves, bool adj, int T,
-                                           const long long *P, const long long *Q, const int *C) {
+                                           const long long *P, const long long *Q, const int2 *C) {
   const long long tot = uniform_ll(P[a.total_tiles]);
   w.Q = Q;
   w.C = C;
@@ -979,7 +991,9 @@ __device__ __forceinline__ int global_wave() { return uniform((int)(blockIdx.x *
 
 // ------------------------------------------------------------------------------------------------
 // k_rowbin: per tile row of a layout, the ordered list of items whose support box meets the row band
-// (large scenes: the tiles then test only their row's items instead of every item of the layout).
+// (large scenes: the tiles then test only their row's items instead of every item of the layout), and
+// the number of the layout's units in earlier rows (-1 when the layout has more units than its pool
+// holds).  The first row's workgroup also numbers the items' map entries.
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ int layout_of_row(cptr<LayoutRec> L, int B, int row) {
   int lo = 0, hi = B - 1;
@@ -995,41 +1009,105 @@ __device__ __forceinline__ int layout_of_row(cptr<LayoutRec> L, int B, int row) 
 
 template <int T>
 __global__ __launch_bounds__(256) void k_rowbin(KArgs a) {
-  __shared__ int s_list[kMaxBinChunk];
-  __shared__ int s_wcnt[4];
-  const int row = blockIdx.x;
+  constexpr int NW = 4;
+  __shared__ long long s_w[NW][2];  // per wave: its hits, its candidates' units
+  const int row = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_row(LS, a.num_layouts, row);
   const int tyi = row - LS[b].row_off;
   const int sb = LS[b].shape_begin, se = LS[b].shape_end, nb = se - sb;
+  const int y0 = tyi * T, y1 = y0 + T - 1;
+  const bool first_row = tyi == 0;
+  const int64_t pool0 = LS[b].list_off;
   int32_t *out = a.row_list + LS[b].row_list_off + (int64_t)tyi * nb;
   int n = 0;
-  for (int cb = sb; cb < se; cb += kMaxBinChunk) {
-    const int ce = min(cb + kMaxBinChunk, se);
-    n += bin_chunk<256>(a, cb, ce, 0, tyi * T, LS[b].W - 1, tyi * T + T - 1, s_list, s_wcnt, out + n);
+  long long before = 0, carry = 0;  // per thread: units in earlier rows; block: units of earlier items
+  for (int base = sb; base < se; base += 256) {
+    const int sid = base + tid;
+    TileSpan t = {0, 0, 0, 0};
+    bool hit = false;
+    if (sid < se) {
+      const int4 bb = load_box(konst(a.bins), sid);
+      // the box lies on the canvas: it meets the row band where its y range does
+      hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.y > y1 || bb.w < y0);
+      t = tile_span<T>(bb);
+    }
+    const long long nu = (long long)t.tw * t.th;
+    before += units_in_rows_before(t, tyi);
+    const unsigned long long m = __ballot(hit);
+    const unsigned long long us = wave_incl_scan_u64((unsigned long long)nu);
+    if (l == 63) {
+      s_w[w][0] = __popcll(m);
+      s_w[w][1] = (long long)us;
+    }
+    __syncthreads();
+    int off = n, tot = n;
+    long long uoff = carry, utot = carry;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int cj = (int)s_w[j][0];
+      const long long uj = s_w[j][1];
+      if (j < w) {
+        off += cj;
+        uoff += uj;
+      }
+      tot += cj;
+      utot += uj;
+    }
+    if (hit) out[off + __popcll(m & ((1ull << l) - 1ull))] = sid;
+    // first map entry of the item (replaced by -1 below if the layout's units do not fit)
+    if (first_row && sid < se) a.item_base[sid] = (int32_t)(pool0 + uoff + (long long)us - nu);
+    n = tot;
+    carry = utot;
+    __syncthreads();
   }
-  if (threadIdx.x == 0) a.row_count[row] = n;
+  before = wave_sum_ll(before);
+  if (l == 0) s_w[w][0] = before;
+  __syncthreads();
+  long long rb = 0;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) rb += s_w[j][0];
+  const bool fits = carry <= (long long)LS[b].unit_cap;
+  if (tid == 0) {
+    a.row_count[row] = n;
+    a.row_base[row] = fits ? rb : -1ll;
+    if (first_row && !fits) atomicAdd(&a.status[COLLAGE_STATUS_UNIT_OVERFLOW], 1);
+  }
+  if (first_row && !fits)
+    for (int sid = sb + tid; sid < se; sid += 256) a.item_base[sid] = -1;
+}
+
+// Whether an item's support box meets the T x T tile at (x0, y0); an item wholly off its canvas has an
+// empty box (x1 < x0) and is binned nowhere.
+__device__ __forceinline__ bool box_meets_tile(int4 bb, int x0, int y0, int T) {
+  return bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x0 + T - 1 || bb.z < x0 || bb.y > y0 + T - 1 || bb.w < y0);
 }
 
 // ------------------------------------------------------------------------------------------------
-// k_bin: per tile, the ordered item list and one work unit per (tile, item).
+// k_bin: per tile, the ordered item list and one work unit per (tile, item), from the tile's first unit
+// on; without the row pass, the first tile of each layout also numbers the items' map entries.
 // ------------------------------------------------------------------------------------------------
+constexpr int kBinPerThread = 2;  // candidates a binning thread loads per pass (4 measured slower)
+
 template <int T>
 __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
-  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64;
-  __shared__ int s_wcnt[NW];
-  // the first kMaxBinChunk units' item, chunks and cost, for the prefix pass below (later units of a
-  // tile that lists more items are read back from global memory)
-  __shared__ int s_usid[kMaxBinChunk], s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
+  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64, K = kBinPerThread;
+  __shared__ long long s_w[NW][2];  // counting pass, per wave: units before the tile, units
+  // main passes, per candidate index k and wave: hits, units of the candidates; per wave: units before
+  // the tile
+  __shared__ int s_h[K][NW];
+  __shared__ int s_u[K][NW], s_b[NW];
+  // the first kMaxBinChunk units' map entry, chunks and cost, for the prefix pass below (later units of
+  // a tile that lists more items are read back from global memory)
+  __shared__ int s_uhead[kMaxBinChunk], s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
   const int tile = blockIdx.x, tid = threadIdx.x;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_tile(LS, a.num_layouts, tile);
   const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
   const int sb = LS[b].shape_begin, se = LS[b].shape_end, nb = se - sb;
   const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
-  const int ntiles = ntx * LS[b].nty;
   const int x0 = txi * T, y0 = tyi * T;
-  const int64_t list_base = LS[b].list_off + (int64_t)lt * nb;
+  const int64_t pool0 = LS[b].list_off;
   for (int q = tid; q < T * T; q += NT) {
     const int pxi = x0 + q % T, pyi = y0 + q / T;
     if (pxi < W && pyi < H) {
@@ -1037,90 +1115,185 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
     }
   }
-  int slots = 0;
-  long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
   // candidates: every item of the layout, or the items listed for the tile's row.  Each thread loads its
-  // candidate's whole bin record with the box it tests, so that a hit's unit record needs no further
+  // candidates' whole bin records with the boxes it tests, so that a hit's unit record needs no further
   // load: the thread writes it at the item's slot in the tile list.
-  const int32_t *src = a.rowbin ? a.row_list + LS[b].row_list_off + (int64_t)tyi * nb : nullptr;
-  const int c0 = a.rowbin ? 0 : sb, c1 = a.rowbin ? a.row_count[LS[b].row_off + tyi] : se;
+  const bool rowbin = a.rowbin != 0;
+  const int32_t *src = rowbin ? a.row_list + LS[b].row_list_off + (int64_t)tyi * nb : nullptr;
+  const int c0 = rowbin ? 0 : sb, c1 = rowbin ? a.row_count[LS[b].row_off + tyi] : se;
+  const long long row_before = rowbin ? a.row_base[LS[b].row_off + tyi] : 0ll;  // -1: the layout overflows
   const int w = tid >> 6, l = tid & 63;
-  for (int base = c0; base < c1; base += NT) {
-    const int pos = base + tid;
-    const int sid = pos < c1 ? (src ? src[pos] : pos) : 0;
-    BinRec br;
-    bool hit = false;
-    if (pos < c1) {
-      br = a.bins[sid];
-      const int4 bb = br.box;
-      // an item wholly off its canvas has an empty box (x1 < x0) and is binned nowhere
-      hit = bb.x <= bb.z && bb.y <= bb.w && !(bb.x > x0 + T - 1 || bb.z < x0 || bb.y > y0 + T - 1 || bb.w < y0);
+  // the tile's first unit (after the layout's units in earlier tiles) and the layout's units: from the
+  // first pass of candidates when one pass holds them all, else from a counting pass first
+  long long before = 0, layout_units = 0;
+  const bool one_pass = c1 - c0 <= K * NT;
+  if (!one_pass) {
+    long long bt = 0, lu = 0;
+    for (int pos = c0 + tid; pos < c1; pos += NT) {
+      const TileSpan t = tile_span<T>(load_box(konst(a.bins), src ? src[pos] : pos));
+      bt += units_before_tile(t, txi, tyi, rowbin);
+      lu += (long long)t.tw * t.th;
     }
-    const unsigned long long m = __ballot(hit);
-    const int before = __popcll(m & ((1ull << l) - 1ull));
-    if (l == 0) s_wcnt[w] = __popcll(m);
+    bt = wave_sum_ll(bt);
+    lu = wave_sum_ll(lu);
+    if (l == 0) {
+      s_w[w][0] = bt;
+      s_w[w][1] = lu;
+    }
     __syncthreads();
-    int off = slots, tot = slots;
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
-      const int cj = s_wcnt[j];
-      if (j < w) off += cj;
-      tot += cj;
+      before += s_w[j][0];
+      layout_units += s_w[j][1];
     }
-    if (hit) {
-      const int slot = off + before;
-      const Rect r = unit_rect(br.box, x0, y0, T);
-      const int chunks = (r.n + 63) >> 6;
-      const int ec = br.ecnv & 0xffff;
-      UnitRec u;
-      u.eo = br.eo;
-      u.ecnv = br.ecnv;
-      u.flags = br.flags;
-      u.head = (int32_t)(LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt);
-      u.xy = r.x0 | (r.y0 << 16);
-      u.wn = r.w | (r.n << 16);
-      u.sid = sid;
-      u.s = br.s;
-      u.cx = br.cx;
-      u.cy = br.cy;
-      a.units[list_base + slot] = u;
-      a.tile_list[list_base + slot] = sid;
-      const int cpc = ec + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
-      a.entry_aux[list_base + slot] = make_int4(chunks, cpc, 0, 0);
-      if (slot < kMaxBinChunk) {
-        s_usid[slot] = sid;
-        s_uch[slot] = chunks;
-        s_ucost[slot] = chunks * cpc;
-      }
-      my_cost += (long long)chunks * cpc;
-      my_quads += chunks;
-    }
-    slots = tot;
     __syncthreads();
+  }
+  bool fits = true;
+  int64_t list_base = pool0;
+  int slots = 0;
+  int ucarry = 0;  // units of the candidates of earlier passes (in item order without the row pass)
+  long long my_cost = 0, my_quads = 0;  // coverage cost and chunks of the tile's units
+  // K candidates per thread and pass, candidate k of thread tid at base + k NT + tid (coalesced loads);
+  // slots and map entries follow the candidate order.  The pass counts units in 32 bits: without the row
+  // pass a layout has at most tiles x items <= kRowBinTests units, and with it the units before the tile
+  // in its row are used only when the layout fits its pool (< 2^31 units).
+  for (int base = c0; base < c1; base += K * NT) {
+    BinRec br[K];
+    int sid[K], ib[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int pos = base + k * NT + tid;
+      sid[k] = pos < c1 ? (src ? src[pos] : pos) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ib[k] = 0;
+      if (base + k * NT + tid < c1) {
+        br[k] = a.bins[sid[k]];
+        if (rowbin) ib[k] = a.item_base[sid[k]];
+      } else {
+        br[k].box = make_int4(1, 1, 0, 0);
+      }
+    }
+    unsigned long long m[K];
+    int nu[K], us[K], bt = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const TileSpan t = tile_span<T>(br[k].box);
+      m[k] = __ballot(box_meets_tile(br[k].box, x0, y0, T));
+      nu[k] = t.tw * t.th;
+      us[k] = rowbin ? 0 : (int)wave_incl_scan_u32((unsigned)nu[k]);
+      bt += (int)units_before_tile(t, txi, tyi, rowbin);
+    }
+    bt = __builtin_amdgcn_readlane((int)wave_incl_scan_u32((unsigned)bt), 63);
+    if (l == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s_h[k][w] = __popcll(m[k]);
+        s_u[k][w] = us[k];
+      }
+      s_b[w] = bt;
+    }
+    __syncthreads();
+    // per candidate: hits and units of the candidates before it; block totals
+    int hoff[K];
+    int uoff[K];
+    int htot = slots, utot = ucarry, btot = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      hoff[k] = htot;
+      uoff[k] = utot;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int hj = s_h[k][j];
+        const int uj = s_u[k][j];
+        if (j < w) {
+          hoff[k] += hj;
+          uoff[k] += uj;
+        }
+        htot += hj;
+        utot += uj;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NW; ++j) btot += s_b[j];
+    if (base == c0) {
+      if (one_pass) {
+        before = btot;
+        layout_units = utot;
+      }
+      // rows: the row pass checked the layout's units against its pool; otherwise this tile sees them all
+      fits = rowbin ? row_before >= 0 : layout_units <= (long long)LS[b].unit_cap;
+      list_base = pool0 + (rowbin ? row_before : 0ll) + before;
+    }
+    const unsigned long long below = (1ull << l) - 1ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const TileSpan t = tile_span<T>(br[k].box);
+      // the item's first map entry
+      const int64_t item0 = rowbin ? (int64_t)ib[k] : pool0 + (uoff[k] + us[k] - nu[k]);
+      if (!rowbin && lt == 0 && base + k * NT + tid < c1) a.item_base[sid[k]] = fits ? (int32_t)item0 : -1;
+      if (((m[k] >> l) & 1ull) && fits) {
+        const int slot = hoff[k] + __popcll(m[k] & below);
+        const Rect r = unit_rect(br[k].box, x0, y0, T);
+        const int chunks = (r.n + 63) >> 6;
+        const int ec = br[k].ecnv & 0xffff;
+        const int head = (int)(item0 + (int64_t)(tyi - t.ty0) * t.tw + (txi - t.tx0));
+        UnitRec u;
+        u.eo = br[k].eo;
+        u.ecnv = br[k].ecnv;
+        u.flags = br[k].flags;
+        u.head = head;
+        u.xy = r.x0 | (r.y0 << 16);
+        u.wn = r.w | (r.n << 16);
+        u.sid = sid[k];
+        u.s = br[k].s;
+        u.cx = br[k].cx;
+        u.cy = br[k].cy;
+        a.units[list_base + slot] = u;
+        a.tile_list[list_base + slot] = sid[k];
+        const int cpc = ec + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
+        a.entry_aux[list_base + slot] = make_int4(chunks, cpc, 0, 0);
+        if (slot < kMaxBinChunk) {
+          s_uhead[slot] = head;
+          s_uch[slot] = chunks;
+          s_ucost[slot] = chunks * cpc;
+        }
+        my_cost += (long long)chunks * cpc;
+        my_quads += chunks;
+      }
+    }
+    slots = htot;
+    ucarry = utot;
+    __syncthreads();
+  }
+  if (!fits) {
+    slots = 0;
+    if (tid == 0 && !rowbin && lt == 0) atomicAdd(&a.status[COLLAGE_STATUS_UNIT_OVERFLOW], 1);
   }
   // chunks and coverage cost of the tile's earlier units, per unit (first wave, 64 units at a time)
   if (tid < 64) {
     int run = 0, run_cost = 0;
     for (int base = 0; base < slots; base += 64) {
       const int j = base + tid;
-      int c = 0, k = 0, sid = 0;
+      int c = 0, k = 0, head = 0;
       if (j < slots) {
         if (j < kMaxBinChunk) {
           c = s_uch[j];
           k = s_ucost[j];
-          sid = s_usid[j];
+          head = s_uhead[j];
         } else {
           const int4 ax = a.entry_aux[list_base + j];
           c = ax.x;
           k = ax.x * ax.y;
-          sid = a.tile_list[list_base + j];
+          head = a.units[list_base + j].head;
         }
       }
       const int x = (int)wave_incl_scan_u32((unsigned)c), y = (int)wave_incl_scan_u32((unsigned)k);
       if (j < slots) {
         a.entry_aux[list_base + j].z = run + x - c;
         a.entry_aux[list_base + j].w = run_cost + y - k;
-        a.item_unit[LS[b].list_off + (int64_t)(sid - sb) * ntiles + lt] = make_int2(c, run + x - c);
+        a.item_unit[head] = make_int2(c, run + x - c);
       }
       run += __builtin_amdgcn_readlane(x, 63);
       run_cost += __builtin_amdgcn_readlane(y, 63);
@@ -1141,7 +1314,7 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
       c += s_red[j][0];
       q += s_red[j][1];
     }
-    a.tile_count[tile] = slots;
+    a.tile_units[tile] = make_int2(slots, fits ? (int32_t)list_base : 0);
     a.tile_cost[tile] = make_int2((int)c, (int)q);
   }
 }
@@ -1512,14 +1685,14 @@ __device__ __forceinline__ UnitView unit_view(const KArgs &a, const UnitRec &U) 
 // kScanInCoverTiles tiles, by one 256-thread workgroup into LDS (two tiles per thread, DPP wave scans).
 // Workgroup 0 also writes them to tile_pre for the later passes and advances the Adam step counter,
 // which the scan kernel does otherwise.
-__device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq, int *cnt) {
+__device__ void cover_tile_scan(const KArgs &a, long long *pc, long long *pq, int2 *cnt) {
   __shared__ unsigned long long s_w[2][4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nt = a.total_tiles, t0 = 2 * tid;
   const int2 c0 = t0 < nt ? a.tile_cost[t0] : make_int2(0, 0);
   const int2 c1 = t0 + 1 < nt ? a.tile_cost[t0 + 1] : make_int2(0, 0);
-  if (t0 < nt) cnt[t0] = a.tile_count[t0];
-  if (t0 + 1 < nt) cnt[t0 + 1] = a.tile_count[t0 + 1];
+  if (t0 < nt) cnt[t0] = a.tile_units[t0];
+  if (t0 + 1 < nt) cnt[t0 + 1] = a.tile_units[t0 + 1];
   const unsigned long long vc = (unsigned long long)c0.x + (unsigned long long)c1.x;
   const unsigned long long vq = (unsigned long long)c0.y + (unsigned long long)c1.y;
   const unsigned long long xc = wave_incl_scan_u64(vc), xq = wave_incl_scan_u64(vq);
@@ -1581,9 +1754,9 @@ __global__ __launch_bounds__(256, kCoverBlocksPerCU) void k_cover(KArgs a) {
   // the tiles' cost and chunk prefixes: computed here in LDS by every workgroup for small scenes (no
   // separate scan launch; workgroup 0 publishes them for the later passes), else from the scan kernel
   __shared__ long long s_pre[2][kScanInCoverTiles + 1];
-  __shared__ int s_cnt[kScanInCoverTiles];
+  __shared__ int2 s_cnt[kScanInCoverTiles];
   const long long *P = a.tile_pre, *Q = a.tile_pre + (a.total_tiles + 1);
-  const int *C = nullptr;
+  const int2 *C = nullptr;
   if (a.scan_in_cover) {
     cover_tile_scan(a, s_pre[0], s_pre[1], s_cnt);
     P = s_pre[0];
@@ -2269,6 +2442,7 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   const int b = a.num_layouts == 1 ? 0 : uniform(SR[sid].layout);  // scalar: the layout's fields are scalar loads
   const float k = LS[b].k;
   const int4 bb = load_box(konst(a.bins), sid);
+  const int item0 = konst(a.item_base)[sid];  // the item's first map entry (-1: its layout's units did not fit)
   const int bad = a.shapes[sid].bad;  // loaded with the others, consumed by lane 0 at the end
   AdamIn ain;
   // every lane (one request): no branch around the loads
@@ -2277,27 +2451,27 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   if constexpr (do_adam) t_step = uniform(a.step[0]);
   TransformPre tp;
   if constexpr (do_transform) tp = transform_preload(a, sid, lane);
-  const int ntx = LS[b].ntx, ntiles = ntx * LS[b].nty;
+  const int ntx = LS[b].ntx;
   const int tile_off = LS[b].tile_off;
-  const int64_t unit_base = LS[b].list_off + (int64_t)(sid - LS[b].shape_begin) * ntiles;
   const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
   const long long tot = uniform_ll(a.tile_pre[(a.total_tiles + 1) + a.total_tiles]);  // chunks of the pass
   const long long W = (long long)a.adjoint_grid * kPersistWaves;
   const double wpc = (double)W / (double)(tot > 0 ? tot : 1);  // waves per chunk
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (bb.x <= bb.z && bb.y <= bb.w) {
+  if (bb.x <= bb.z && bb.y <= bb.w && item0 >= 0) {
     // every tile that the support box meets lists the item, and its unit there has at least one chunk.
-    // Per unit (one per lane): the head partial, then the spill slots of the waves whose share begins
-    // inside the unit's chunks [c0, c1), in wave order: waves w with c0 < ceil(w tot / W) < c1.  The head
-    // and the unit's map entry share an index, so all of a lane's first loads are independent.
+    // Per unit (one per lane, in the item's row-major tile order, which is its map order): the head
+    // partial, then the spill slots of the waves whose share begins inside the unit's chunks [c0, c1),
+    // in wave order: waves w with c0 < ceil(w tot / W) < c1.  The head and the unit's map entry share an
+    // index, so all of a lane's first loads are independent.
     const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
     const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
     for (int r0 = 0; r0 < nt; r0 += 64) {
       const int j = r0 + lane;
       if (j < nt) {
         const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
-        const int2 u = a.item_unit[unit_base + lt];
-        const double4 h = a.head[unit_base + lt];
+        const int2 u = a.item_unit[item0 + j];
+        const double4 h = a.head[item0 + j];
         const long long c0 = q0[lt] + u.y, c1 = c0 + u.x;
         acc.x += h.x;
         acc.y += h.y;

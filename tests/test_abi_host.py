@@ -62,6 +62,7 @@ def _desc(B=1, N=1, V=4, w=(16,), h=(16,), k=(1.0,), shapes=(0, 1), voff=(0, 4))
     (lambda d: setattr(d, "w_wmse", float("inf")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "w_objdown", float("nan")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "code_capacity", -2), _lib.ERR_INVALID),
+    (lambda d: setattr(d, "unit_capacity", -2), _lib.ERR_INVALID),
     (lambda d: setattr(d, "bin_chunk", 1025), _lib.ERR_INVALID),
     (lambda d: setattr(d, "num_shapes", 2), _lib.ERR_SIZE),
     (lambda d: setattr(d, "num_verts", 5), _lib.ERR_SIZE),
