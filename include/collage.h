@@ -90,12 +90,17 @@ extern "C" {
  *                               layout's unit capacity.  Such a layout lists no units in that epoch: its
  *                               coverage is 0 and its items' gradients are 0, so the call's results are
  *                               not valid and the scene must be created with a larger unit_capacity.
+ *   [COLLAGE_STATUS_GRAD_RANGE] pieces of the adjoint (the chunks of one work unit that one wave sums)
+ *                               whose gradient sums were not finite or reached 2^23 in magnitude, the
+ *                               range of the exact 2^-30 fixed-point sums: they are left out of the
+ *                               gradient, so the call's gradients are not valid.
  * The other words are reserved (0).  collage_read_status copies them to the host.
  */
 #define COLLAGE_STATUS_NONFINITE 0
 #define COLLAGE_STATUS_CHUNKS 1
 #define COLLAGE_STATUS_RESCANNED 2
 #define COLLAGE_STATUS_UNIT_OVERFLOW 3
+#define COLLAGE_STATUS_GRAD_RANGE 4
 #define COLLAGE_STATUS_WORDS 8
 
 
@@ -144,7 +149,7 @@ typedef struct collage_scene_desc {
                                    writes its unit from the testing thread, with no item list in LDS */
   uint32_t flags;               /* 0 or COLLAGE_FLAG_AREA_MEAN; other bits are rejected */
   int32_t unit_capacity;        /* (screen tile, item) work units the workspace holds per layout and epoch,
-                                   one per item and tile its support box meets (108 bytes each).
+                                   one per item and tile its support box meets (100 bytes each).
                                    0 = default: every item in every tile of the layout, or, when less, four
                                    times the units of its items at twice their rim radius (read from verts
                                    and stroke at creation), at least 65536; -1 = every item in every tile

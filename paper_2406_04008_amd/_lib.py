@@ -28,6 +28,7 @@ STATUS_NONFINITE = 0  # (epoch, item) pairs of the last call whose parameters we
 STATUS_CHUNKS = 1  # 64-pixel chunks of the last epoch's coverage pass
 STATUS_RESCANNED = 2  # of those, chunks the adjoint rescanned (beyond the code capacity)
 STATUS_UNIT_OVERFLOW = 3  # (epoch, layout) pairs whose work units did not fit the layout's pool (results invalid)
+STATUS_GRAD_RANGE = 4  # adjoint pieces whose sums were beyond the fixed-point gradient range (gradients invalid)
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)

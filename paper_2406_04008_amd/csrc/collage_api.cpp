@@ -58,7 +58,7 @@ struct collage_scene {
   int64_t unit_pool = 0;  // units of all layouts' pools
   size_t off_ibase = 0, off_rbase = 0;
   size_t off_status = 0, off_shapes = 0, off_bins = 0, off_edges = 0, off_edges_d = 0, off_count = 0, off_loss = 0,
-         off_list = 0, off_iunit = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_head = 0, off_spill = 0, off_acc = 0,
+         off_list = 0, off_rcount = 0, off_rlist = 0, off_aux = 0, off_tcost = 0, off_tpre = 0, off_head = 0, off_acc = 0,
          off_gbuf = 0, off_codes = 0, off_uflags = 0, off_vacc = 0, off_units = 0;
   size_t ws_bytes = 0;
 };
@@ -187,15 +187,13 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.tile_units = reinterpret_cast<int2 *>(w + s->off_count);
   a.block_loss = reinterpret_cast<double *>(w + s->off_loss);
   a.tile_list = reinterpret_cast<int32_t *>(w + s->off_list);
-  a.item_unit = reinterpret_cast<int2 *>(w + s->off_iunit);
   a.row_count = reinterpret_cast<int32_t *>(w + s->off_rcount);
   a.row_list = reinterpret_cast<int32_t *>(w + s->off_rlist);
   a.entry_aux = reinterpret_cast<int4 *>(w + s->off_aux);
   a.units = reinterpret_cast<UnitRec *>(w + s->off_units);
   a.tile_cost = reinterpret_cast<int2 *>(w + s->off_tcost);
   a.tile_pre = reinterpret_cast<long long *>(w + s->off_tpre);
-  a.head = reinterpret_cast<double4 *>(w + s->off_head);
-  a.spill = reinterpret_cast<double4 *>(w + s->off_spill);
+  a.head = reinterpret_cast<unsigned long long *>(w + s->off_head);
   a.acc = reinterpret_cast<unsigned long long *>(w + s->off_acc);
   a.gbuf = reinterpret_cast<double2 *>(w + s->off_gbuf);
   a.codes = reinterpret_cast<uint16_t *>(w + s->off_codes);
@@ -368,8 +366,6 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)s->V);
   s->off_list = off;
   off = align256(off + sizeof(int32_t) * (size_t)s->unit_pool);
-  s->off_iunit = off;
-  off = align256(off + sizeof(int2) * (size_t)s->unit_pool);
   s->off_rcount = off;
   off = align256(off + sizeof(int32_t) * (size_t)rows);
   s->off_rlist = off;
@@ -389,9 +385,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
   s->off_tpre = off;
   off = align256(off + sizeof(long long) * 2 * ((size_t)tiles + 1));
   s->off_head = off;
-  off = align256(off + sizeof(double4) * (size_t)s->unit_pool);
-  s->off_spill = off;
-  off = align256(off + sizeof(double4) * (size_t)s->adjoint_grid * kPersistWaves);
+  off = align256(off + 4 * sizeof(unsigned long long) * (size_t)s->unit_pool);
   s->off_acc = off;
   off = align256(off + 2 * sizeof(unsigned long long) * (size_t)pix);
   s->off_gbuf = off;

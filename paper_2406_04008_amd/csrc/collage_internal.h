@@ -60,7 +60,7 @@ struct alignas(16) UnitRec {
   int32_t eo;      // the item's first edge record (= first vertex)
   int32_t ecnv;    // edges (bits 0-15) and vertices (bits 16-31) of the item
   int32_t flags;   // kUnitOpen: open polyline; kUnitClockwise: the outline's orientation is clockwise
-  int32_t head;    // the unit's entry of the per-(item, tile) map: where the adjoint's head partial goes
+  int32_t head;    // the unit's entry of the per-item map: where the adjoint's sums go
   int32_t xy;      // the unit rectangle (the item's support box clipped to the tile): x0 | y0 << 16
   int32_t wn;      // its width | its pixel count << 16 (w x n / w px)
   int32_t sid;     // the item (an open item's stroke radius is read from its ShapeRec)
@@ -134,9 +134,6 @@ struct KArgs {
   int32_t *status;       // [kStatusWords] device status words (workspace offset 0)
   int2 *tile_units;      // [tiles] each tile's units and its first pool entry
   int32_t *tile_list;    // pool: each tile's items, in item order, from its first pool entry on
-  int2 *item_unit;       // pool, per-item map: per item from item_base[item] on, per tile of its span in
-                         // row-major order, its unit there (the unit's chunks, chunks of the tile's
-                         // earlier units); the same index holds the unit's head partial
   int32_t rowbin;        // 1: items are first binned per tile row (k_rowbin), tiles scan their row's list
   int32_t scan_in_cover; // 1: the coverage kernel computes the tile prefixes (no scan launch)
   int32_t total_rows;    // tile rows over all layouts
@@ -151,10 +148,9 @@ struct KArgs {
   // accumulators
   unsigned long long *acc;  // [pixels][2] fixed-point S and S_pad (2^-40 units)
   double2 *gbuf;            // [pixels] dLoss/dS, dLoss/dS_pad
-  double4 *head;            // pool, per-item map (the item_unit index): the adjoint sums (n_x, n_y,
-                            // theta, scale terms) of the piece of the unit that starts at its first chunk
-  double4 *spill;           // [adjoint waves]: the sums of a wave's first piece when it starts inside a unit
-                            // (only a wave's first piece can; the update finds such waves by their shares)
+  unsigned long long *head;  // [pool][4] per-item map: per item from item_base[item] on, per tile of its
+                             // span in row-major order, its unit's adjoint sums (n_x, n_y, theta, scale
+                             // terms) in 2^-30 fixed point (zeroed by binning, added by the adjoint)
   double *block_loss;       // per pixel tile: the kLossTerms weighted loss-term sums
   uint8_t *uflags;          // [pixels] bit j: M != 0 and A_j < 1 (the uniform term's active windows)
   unsigned long long *vacc; // [V][2] outline-vertex adjoint sums, level frame, 2^-32 fixed point; null

@@ -27,14 +27,15 @@
 //   k_unif_grad  (uniform term on) the same tiles: the term's share of dLoss/dS from window sums of
 //                the pixels' active-window bits.
 //   k_adjoint    persistent waves again: per chunk, the gradient terms of its pixels (double), summed
-//                per piece of a unit: the piece at a unit's first chunk into the unit's head partial,
-//                a piece that starts inside a unit (only a wave's first can) into the wave's spill.
+//                per piece of a unit (the chunks of the unit in one wave's share) and added into the
+//                unit's head partials in 2^-30 fixed point with 64-bit integer atomics (each pixel's
+//                terms rounded first, so every sum is exact).
 //   k_vgrad,     (outline-vertex gradients only) the adjoint's walk once more, adding each pixel's
 //   k_vfinal     d sd / d(end points of its nearest edge) into per-vertex fixed-point sums, then back
 //                through eq. 2 per vertex.
-//   k_finalize   one wave per item (two or four items per workgroup) sums its units' head and spill
-//                partials in a fixed order (gradient, then the optional Adam update and the next
-//                epoch's transform); one workgroup per layout sums the loss blocks in a fixed order.
+//   k_finalize   one wave per item (two or four items per workgroup) sums its units' head partials in
+//                a fixed order (gradient, then the optional Adam update and the next epoch's
+//                transform); one workgroup per layout sums the loss blocks in a fixed order.
 // Bulk outputs that later kernels read are written with nontemporal stores.  Results are bitwise
 // reproducible.
 #include "collage_internal.h"
@@ -132,6 +133,29 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// The value of lane l ^ 16 (ROWS = 16) or l ^ 32 (ROWS = 32) in registers: v_permlane16_swap exchanges
+// the odd rows of 16 lanes of its first operand with the even rows of its second, v_permlane32_swap the
+// upper half of the first with the lower half of the second, so with x in both the partner's value is
+// in one of the two results.  (No LDS round trip, unlike a shuffle.)
+template <int ROWS>
+__device__ __forceinline__ unsigned xor_rows_u32(unsigned x) {
+  const bool upper = ((threadIdx.x & 63) & ROWS) != 0;
+  if constexpr (ROWS == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return upper ? r[0] : r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return upper ? r[0] : r[1];
+  }
+}
+
+template <int ROWS>
+__device__ __forceinline__ double xor_rows_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = xor_rows_u32<ROWS>((unsigned)b), hi = xor_rows_u32<ROWS>((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Wave sums of several values at once (every lane active), in a fixed order.  Each lane gives half of
 // its values to the partner across lane bit 0 and adds the other half from it, then the same across
 // bit 1, so that from there on it sums a quarter of the values: over the 16 lanes of the same quad
@@ -149,8 +173,8 @@ __device__ __forceinline__ double wave_sum4(double4 v, int &comp) {
   m += dpp_f64<kQuadXor2>(o2 ? k0 : k1);
   m += dpp_f64<kRowRor4>(m);
   m += dpp_f64<kRowRor8>(m);
-  m += __shfl_xor(m, 16, 64);
-  m += __shfl_xor(m, 32, 64);
+  m += xor_rows_f64<16>(m);
+  m += xor_rows_f64<32>(m);
   comp = (o1 ? 2 : 0) + (o2 ? 1 : 0);
   return m;
 }
@@ -173,10 +197,10 @@ __device__ __forceinline__ double2 wave_sum8(const double (&v)[8], int &c0) {
   m1 += dpp_f64<kRowRor4>(m1);
   m0 += dpp_f64<kRowRor8>(m0);
   m1 += dpp_f64<kRowRor8>(m1);
-  m0 += __shfl_xor(m0, 16, 64);
-  m1 += __shfl_xor(m1, 16, 64);
-  m0 += __shfl_xor(m0, 32, 64);
-  m1 += __shfl_xor(m1, 32, 64);
+  m0 += xor_rows_f64<16>(m0);
+  m1 += xor_rows_f64<16>(m1);
+  m0 += xor_rows_f64<32>(m0);
+  m1 += xor_rows_f64<32>(m1);
   c0 = (o1 ? 4 : 0) + (o2 ? 2 : 0);
   return make_double2(m0, m1);
 }
@@ -1097,9 +1121,9 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   // the tile
   __shared__ int s_h[K][NW];
   __shared__ int s_u[K][NW], s_b[NW];
-  // the first kMaxBinChunk units' map entry, chunks and cost, for the prefix pass below (later units of
-  // a tile that lists more items are read back from global memory)
-  __shared__ int s_uhead[kMaxBinChunk], s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
+  // the first kMaxBinChunk units' chunks and cost, for the prefix pass below (later units of a tile that
+  // lists more items are read back from global memory)
+  __shared__ int s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
   const int tile = blockIdx.x, tid = threadIdx.x;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_tile(LS, a.num_layouts, tile);
@@ -1254,8 +1278,11 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
         a.tile_list[list_base + slot] = sid[k];
         const int cpc = ec + kEpilogueCost + (kUnitCost + chunks - 1) / chunks;
         a.entry_aux[list_base + slot] = make_int4(chunks, cpc, 0, 0);
+        // the unit's head partials start at zero (the adjoint adds its pieces)
+        ulonglong2 *hp = reinterpret_cast<ulonglong2 *>(a.head + 4 * (int64_t)head);
+        hp[0] = make_ulonglong2(0ull, 0ull);
+        hp[1] = make_ulonglong2(0ull, 0ull);
         if (slot < kMaxBinChunk) {
-          s_uhead[slot] = head;
           s_uch[slot] = chunks;
           s_ucost[slot] = chunks * cpc;
         }
@@ -1276,24 +1303,21 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
     int run = 0, run_cost = 0;
     for (int base = 0; base < slots; base += 64) {
       const int j = base + tid;
-      int c = 0, k = 0, head = 0;
+      int c = 0, k = 0;
       if (j < slots) {
         if (j < kMaxBinChunk) {
           c = s_uch[j];
           k = s_ucost[j];
-          head = s_uhead[j];
         } else {
           const int4 ax = a.entry_aux[list_base + j];
           c = ax.x;
           k = ax.x * ax.y;
-          head = a.units[list_base + j].head;
         }
       }
       const int x = (int)wave_incl_scan_u32((unsigned)c), y = (int)wave_incl_scan_u32((unsigned)k);
       if (j < slots) {
         a.entry_aux[list_base + j].z = run + x - c;
         a.entry_aux[list_base + j].w = run_cost + y - k;
-        a.item_unit[head] = make_int2(c, run + x - c);
       }
       run += __builtin_amdgcn_readlane(x, 63);
       run_cost += __builtin_amdgcn_readlane(y, 63);
@@ -2143,9 +2167,47 @@ __global__ __launch_bounds__(kPixThreads) void k_unif_grad(KArgs a) {
   if (mine && g != 0.0) a.gbuf[pix].x = g0 - cu * g;
 }
 
+// The head partials of a unit.  Every pixel's four gradient terms are rounded to multiples of 2^-30
+// (kept as integer-valued doubles, rint(ldexp(x, 30)): two instructions and no constant registers), so
+// that every later sum is a sum of integers, exact while below 2^53: the per-lane sums over a piece's chunks (the chunks of the unit in one wave's
+// share), the piece's wave sum, and, as 64-bit integers added with atomics, the unit's total over its
+// pieces.  The totals thus depend neither on the order of the pieces nor on where the work partition
+// cuts the unit (a batch of layouts and each layout on its own give the same bits).  A piece whose sums
+// reach 2^23 in magnitude (2^53 units), in any lane or in total, or are not finite, is left out and
+// counted in the status word COLLAGE_STATUS_GRAD_RANGE; a unit has at most 16 pieces, so its totals stay
+// below 2^57 units.
+constexpr int kHeadBits = 30;                      // units of 2^-30
+constexpr double kHeadLimit = 9007199254740992.0;  // 2^53 units
+
+__device__ __forceinline__ double head_round(double x) { return rint(ldexp(x, kHeadBits)); }
+
+__device__ __forceinline__ void head_accumulate(double4 &acc, const double4 &t) {
+  acc.x += head_round(t.x);
+  acc.y += head_round(t.y);
+  acc.z += head_round(t.z);
+  acc.w += head_round(t.w);
+}
+
+// The piece's per-lane sums acc (integer-valued, units of 2^-30) into the unit's head partials.  Every
+// lane must be active.
+__device__ __forceinline__ void piece_to_head(const KArgs &a, int head, double4 acc) {
+  const int lane = threadIdx.x & 63;
+  const bool lane_ok = fabs(acc.x) + fabs(acc.y) + fabs(acc.z) + fabs(acc.w) < kHeadLimit;
+  const bool all_ok = __ballot(!lane_ok) == 0ull;
+  int comp;
+  const double tot = wave_sum4(acc, comp);
+  if (lane < 4) {
+    if (!all_ok || !(fabs(tot) < kHeadLimit)) {
+      if (lane == 0) atomicAdd(&a.status[COLLAGE_STATUS_GRAD_RANGE], 1);
+    } else if (tot != 0.0) {
+      atomicAdd(a.head + 4 * (int64_t)head + comp, (unsigned long long)(long long)tot);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
-// k_adjoint: per unit, the gradient terms of its pixels reduced to a head partial per (tile, item) and a
-// spill per wave.
+// k_adjoint: per unit, the gradient terms of its pixels reduced per piece and added into the unit's head
+// partials.
 // ------------------------------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
@@ -2157,9 +2219,6 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
   Walk wk;
   const long long *Qg = a.tile_pre + (a.total_tiles + 1);
   bool ok = walk_begin(a, wk, gw, nwaves, true, T, Qg, Qg, nullptr);
-  // every wave writes its spill slot: zero (right away, off the end of the kernel's path) when its share
-  // is empty or begins at a unit's first chunk
-  if ((!ok || wk.jlo == 0) && lane == 0) a.spill[gw] = make_double4(0.0, 0.0, 0.0, 0.0);
   for (; ok; ok = walk_next(a, wk, T)) {
     const UnitView uv = unit_view(a, load_unit(konst(a.units) + (wk.list_base + wk.slot)));
     const Rect r = uv.r;
@@ -2172,7 +2231,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
     // (a binned item has at least one edge: an item without vertices has an empty support box)
     const bool staged = ec <= kStageEdges;
     ScaleDeriv sdv = {uv.inv_s, uv.kc, uv.ks, reinterpret_cast<const float2 *>(a.verts) + eo, 0, uv.nv, open};
-    double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);  // the lane's rounded terms (units of 2^-30)
     if (q + wk.jhi <= a.code_cap) {
       // every chunk of the piece has its nearest-edge codes: a three-stage pipeline over the chunks
       // (codes two chunks ahead, the edge record and dLoss/dS one chunk ahead), since each chunk's
@@ -2203,11 +2262,7 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           PairD pr = pair_eval(e_cur, rx, ry, par);
           if (open) pr.sd = sw - pr.d;
           sdv.bi = (int)(c_cur & 0x7fffu);
-          const double4 t = adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y, open, sw_ds, sdv);
-          acc.x += t.x;
-          acc.y += t.y;
-          acc.z += t.z;
-          acc.w += t.w;
+          head_accumulate(acc, adjoint_terms(a, e_cur, pr, rx, ry, par, orient, g_cur.x, g_cur.y, open, sw_ds, sdv));
         }
         c_cur = c_nxt;
         c_nxt = c_far;
@@ -2242,20 +2297,11 @@ __global__ __launch_bounds__(256, kAdjointBlocksPerCU) void k_adjoint(KArgs a) {
           PairD pr = pair_eval(e, rx, ry, par);
           if (open) pr.sd = sw - pr.d;
           sdv.bi = bi;
-          const double4 t = adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y, open, sw_ds, sdv);
-          acc.x += t.x;
-          acc.y += t.y;
-          acc.z += t.z;
-          acc.w += t.w;
+          head_accumulate(acc, adjoint_terms(a, e, pr, rx, ry, par, orient, g.x, g.y, open, sw_ds, sdv));
         }
       }
     }
-    int comp;
-    const double tot = wave_sum4(acc, comp);
-    // the piece that starts at the unit's first chunk is its head; only a wave's first piece can start
-    // inside a unit, and then it is the wave's spill (lanes 0-3 hold the four components)
-    double *dst = reinterpret_cast<double *>(wk.jlo == 0 ? a.head + uv.head : a.spill + gw);
-    if (lane < 4) dst[comp] = tot;
+    piece_to_head(a, uv.head, acc);
   }
 }
 
@@ -2414,19 +2460,6 @@ __device__ __forceinline__ float4 adam_update(const KArgs &a, int sid, float4 g,
   return make_float4(pp[0], pp[1], pp[2], pp[3]);
 }
 
-// The adjoint's waves split the pass's chunks in equal shares: wave w's share begins at chunk
-// ceil(w tot / W) (share_bound without taper).  The first wave whose share begins after chunk c: the
-// least w with w tot > c W, from the quotient in double (c W < 2^53) corrected exactly in integers.
-__device__ __forceinline__ long long first_wave_after(long long c, long long W, long long tot, double w_per_chunk) {
-  const long long n = c * W;
-  long long w = (long long)((double)c * w_per_chunk) + 1;
-  while (w > 0 && (w - 1) * tot > n) --w;
-  while (w * tot <= n) ++w;
-  return w;
-}
-
-constexpr int kSpillBatch = 4;  // spill loads an update lane issues together
-
 // ADAM: update the parameters; XFORM (with ADAM): transform the items with the updated parameters.
 // The loads of the update and of the transform are issued first and consumed last, so that they are in
 // flight while the gradient is gathered.  per: items per workgroup (its first per waves take one each).
@@ -2451,50 +2484,19 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   if constexpr (do_adam) t_step = uniform(a.step[0]);
   TransformPre tp;
   if constexpr (do_transform) tp = transform_preload(a, sid, lane);
-  const int ntx = LS[b].ntx;
-  const int tile_off = LS[b].tile_off;
-  const long long *q0 = a.tile_pre + (a.total_tiles + 1) + tile_off;
-  const long long tot = uniform_ll(a.tile_pre[(a.total_tiles + 1) + a.total_tiles]);  // chunks of the pass
-  const long long W = (long long)a.adjoint_grid * kPersistWaves;
-  const double wpc = (double)W / (double)(tot > 0 ? tot : 1);  // waves per chunk
   double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
   if (bb.x <= bb.z && bb.y <= bb.w && item0 >= 0) {
-    // every tile that the support box meets lists the item, and its unit there has at least one chunk.
-    // Per unit (one per lane, in the item's row-major tile order, which is its map order): the head
-    // partial, then the spill slots of the waves whose share begins inside the unit's chunks [c0, c1),
-    // in wave order: waves w with c0 < ceil(w tot / W) < c1.  The head and the unit's map entry share an
-    // index, so all of a lane's first loads are independent.
-    const int tx0 = bb.x / T, tx1 = bb.z / T, ty0 = bb.y / T, ty1 = bb.w / T;
-    const int tw = tx1 - tx0 + 1, nt = tw * (ty1 - ty0 + 1);
-    for (int r0 = 0; r0 < nt; r0 += 64) {
-      const int j = r0 + lane;
-      if (j < nt) {
-        const int lt = (ty0 + j / tw) * ntx + tx0 + j % tw;
-        const int2 u = a.item_unit[item0 + j];
-        const double4 h = a.head[item0 + j];
-        const long long c0 = q0[lt] + u.y, c1 = c0 + u.x;
-        acc.x += h.x;
-        acc.y += h.y;
-        acc.z += h.z;
-        acc.w += h.w;
-        // the waves whose share begins inside the unit: [w0, w1), each slot holding its first piece's
-        // sums or zero; loaded kSpillBatch at a time and added in wave order
-        const long long w0 = first_wave_after(c0, W, tot, wpc);
-        const long long w1 = min(first_wave_after(c1 - 1, W, tot, wpc), W);
-        for (long long w = w0; w < w1; w += kSpillBatch) {
-          double4 sp[kSpillBatch];
-#pragma unroll
-          for (int k = 0; k < kSpillBatch; ++k)
-            sp[k] = w + k < w1 ? a.spill[w + k] : make_double4(0.0, 0.0, 0.0, 0.0);
-#pragma unroll
-          for (int k = 0; k < kSpillBatch; ++k) {
-            acc.x += sp[k].x;
-            acc.y += sp[k].y;
-            acc.z += sp[k].z;
-            acc.w += sp[k].w;
-          }
-        }
-      }
+    // every tile that the support box meets lists the item: its units' head partials are the item's map
+    // entries [item0, item0 + tiles of its span), one per lane, each converted to double and added in
+    // a fixed order
+    const int nt = (bb.z / T - bb.x / T + 1) * (bb.w / T - bb.y / T + 1);
+    const ulonglong2 *H = reinterpret_cast<const ulonglong2 *>(a.head + 4 * (int64_t)item0);
+    for (int j = lane; j < nt; j += 64) {
+      const ulonglong2 h0 = H[2 * j], h1 = H[2 * j + 1];
+      acc.x += ldexp((double)(long long)h0.x, -kHeadBits);
+      acc.y += ldexp((double)(long long)h0.y, -kHeadBits);
+      acc.z += ldexp((double)(long long)h1.x, -kHeadBits);
+      acc.w += ldexp((double)(long long)h1.y, -kHeadBits);
     }
   }
   {

@@ -39,6 +39,7 @@ def test_default_pool_matches_the_dense_pool_bitwise(name, level, tile):
         cov, cov_pad, l2, g2 = cs.forward_backward(p)
         status = cs.status()
         assert status[_lib.STATUS_UNIT_OVERFLOW] == 0, (cap, status)
+        assert status[_lib.STATUS_GRAD_RANGE] == 0, (cap, status)
         outs.append((cov, cov_pad, l2, g2, p.clone(), loss.clone()))
     for a, b in zip(outs[0], outs[1]):
         assert torch.equal(a, b)
