@@ -2529,24 +2529,30 @@ __device__ void finalize_grad(const KArgs &a, int per) {
   }
 }
 
+// The loss sums of layout b over its pixel tiles in one fixed order for any workgroup size (128 or 256
+// threads): 256 virtual lanes, lane v summing tiles v, v + 256, ..., then each group of 64 virtual lanes
+// by a wave sum, then the four groups in order.
 __device__ void finalize_loss(const KArgs &a, int b) {
   __shared__ double s_part[4][kLossTerms];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int p0 = LS[b].ptile_off;
   const int np = ((LS[b].W + kPixTile - 1) / kPixTile) * ((LS[b].H + kPixTile - 1) / kPixTile);
-  double s[kLossTerms];
+  for (int vb = 0; vb < 256; vb += blockDim.x) {
+    const int v = vb + threadIdx.x;
+    double s[kLossTerms];
 #pragma unroll
-  for (int t = 0; t < kLossTerms; ++t) s[t] = 0.0;
-  for (int j = threadIdx.x; j < np; j += 256) {
-    const double *bl = a.block_loss + (int64_t)(p0 + j) * kLossTerms;
+    for (int t = 0; t < kLossTerms; ++t) s[t] = 0.0;
+    for (int j = v; j < np; j += 256) {
+      const double *bl = a.block_loss + (int64_t)(p0 + j) * kLossTerms;
 #pragma unroll
-    for (int t = 0; t < kLossTerms; ++t) s[t] += bl[t];
-  }
+      for (int t = 0; t < kLossTerms; ++t) s[t] += bl[t];
+    }
 #pragma unroll
-  for (int t = 0; t < kLossTerms; ++t) {
-    const double v = wave_sum(s[t]);
-    if (lane == 0) s_part[wave][t] = v;
+    for (int t = 0; t < kLossTerms; ++t) {
+      const double w = wave_sum(s[t]);
+      if (lane == 0) s_part[v >> 6][t] = w;
+    }
   }
   __syncthreads();
   if (threadIdx.x < kLossTerms) {
@@ -2718,13 +2724,13 @@ hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
                            bool do_transform) {
   // each item's gradient is a short chain of dependent loads: with fewer than 2048 items, two items
-  // per workgroup spread the chains over twice the compute units
+  // per workgroup spread the chains over twice the compute units (one wave per item: 64 per threads)
   const int per = a.num_shapes >= 2048 ? 4 : 2;
   const int gb = do_grad ? (a.num_shapes + per - 1) / per : 0;
   const int lb = do_loss ? a.num_layouts : 0;
   if (gb + lb == 0) return hipSuccess;
   const int flags = (do_adam ? 1 : 0) | (do_loss ? 2 : 0) | (do_adam && do_transform ? 4 : 0);
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, flags, per));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(64 * per), 0, st, a, gb, flags, per));
   return hipGetLastError();
 }
 

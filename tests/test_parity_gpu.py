@@ -551,12 +551,19 @@ def test_edge_cases():
     cs.forward_backward(cs.params_tensor())
     st_ = cs.status()
     assert st_[_lib.STATUS_NONFINITE] == 0 and st_[_lib.STATUS_CHUNKS] > 0 and st_[_lib.STATUS_RESCANNED] == 0
-    assert list(st_[3:]) == [0] * (_lib.STATUS_WORDS - 3)
+    assert list(st_[3:]) == [0] * (_lib.STATUS_WORDS - 3)  # no unit overflow, no gradient beyond range
     # with no kept codes, the adjoint rescans every chunk of the pass
     cs0 = CollageScene(sc2, code_capacity=0)
     cs0.forward_backward(cs0.params_tensor())
     st0 = cs0.status()
     assert st0[_lib.STATUS_RESCANNED] == st0[_lib.STATUS_CHUNKS] == st_[_lib.STATUS_CHUNKS]
+    # gradient pieces beyond the fixed-point range (2^23) are reported: a fill weight of 1e9 makes every
+    # piece of an item that covers container pixels far larger; with the default weight none is
+    big = dataclasses.replace(sc2, w_fill=1e9)
+    csb = CollageScene(big)
+    csb.forward_backward(csb.params_tensor())
+    assert csb.status()[_lib.STATUS_GRAD_RANGE] > 0
+    assert st_[_lib.STATUS_GRAD_RANGE] == 0
 
 
 def test_degenerate_scales():
