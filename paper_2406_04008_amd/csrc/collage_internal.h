@@ -108,7 +108,7 @@ struct KArgs {
   int32_t num_shapes;
   int32_t total_tiles;
   int32_t total_ptiles;  // pixel tiles over all layouts
-  int32_t tile;          // tile edge in px (8, 16 or 32)
+  int32_t tile;          // tile edge in px (8, 16, 32 or 64)
   int32_t bin_chunk;     // items binned per pass
   int32_t *item_base;    // [N] each item's first per-item map entry, -1 when its layout's units did not
                          // fit its pool (written by binning)

@@ -1113,9 +1113,14 @@ __device__ __forceinline__ bool box_meets_tile(int4 bb, int x0, int y0, int T) {
 // ------------------------------------------------------------------------------------------------
 constexpr int kBinPerThread = 2;  // candidates a binning thread loads per pass (4 measured slower)
 
+// Workgroups per screen tile: 64 x 64 tiles spread the clearing of their accumulators over four (only
+// the first bins), so that it is not left to a quarter as many workgroups as compute units.
+template <int T>
+constexpr int kBinParts = T >= 64 ? 4 : 1;
+
 template <int T>
 __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
-  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64, K = kBinPerThread;
+  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64, K = kBinPerThread, ZP = kBinParts<T>;
   __shared__ long long s_w[NW][2];  // counting pass, per wave: units before the tile, units
   // main passes, per candidate index k and wave: hits, units of the candidates; per wave: units before
   // the tile
@@ -1124,7 +1129,7 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   // the first kMaxBinChunk units' chunks and cost, for the prefix pass below (later units of a tile that
   // lists more items are read back from global memory)
   __shared__ int s_uch[kMaxBinChunk], s_ucost[kMaxBinChunk];
-  const int tile = blockIdx.x, tid = threadIdx.x;
+  const int tile = blockIdx.x / ZP, part = blockIdx.x % ZP, tid = threadIdx.x;
   cptr<LayoutRec> LS = konst(a.layouts);
   const int b = layout_of_tile(LS, a.num_layouts, tile);
   const int W = LS[b].W, H = LS[b].H, ntx = LS[b].ntx;
@@ -1132,13 +1137,14 @@ __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
   const int lt = tile - LS[b].tile_off, tyi = lt / ntx, txi = lt - tyi * ntx;
   const int x0 = txi * T, y0 = tyi * T;
   const int64_t pool0 = LS[b].list_off;
-  for (int q = tid; q < T * T; q += NT) {
+  for (int q = part * (T * T / ZP) + tid; q < (part + 1) * (T * T / ZP); q += NT) {
     const int pxi = x0 + q % T, pyi = y0 + q / T;
     if (pxi < W && pyi < H) {
       const int64_t pix = LS[b].pix_off + (int64_t)pyi * W + pxi;
       __builtin_nontemporal_store((nt_u64x2){0ull, 0ull}, reinterpret_cast<nt_u64x2 *>(a.acc + 2 * pix));
     }
   }
+  if (part != 0) return;
   // candidates: every item of the layout, or the items listed for the tile's row.  Each thread loads its
   // candidates' whole bin records with the boxes it tests, so that a hit's unit record needs no further
   // load: the thread writes it at the item's slot in the tile list.
@@ -2657,6 +2663,10 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
       constexpr int T_ = 32;                                                                         \
       STMT;                                                                                          \
     } break;                                                                                         \
+    case 64: {                                                                                       \
+      constexpr int T_ = 64;                                                                         \
+      STMT;                                                                                          \
+    } break;                                                                                         \
     default: {                                                                                       \
       constexpr int T_ = 16;                                                                         \
       STMT;                                                                                          \
@@ -2666,7 +2676,8 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
 hipError_t launch_bin(const KArgs &a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
   if (a.rowbin) COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_rowbin<T>, dim3(a.total_rows), dim3(256), 0, st, a));
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles), dim3(T * T < 256 ? T * T : 256), 0, st, a));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles * kBinParts<T>), dim3(T * T < 256 ? T * T : 256),
+                                              0, st, a));
   return hipGetLastError();
 }
 
