@@ -139,7 +139,7 @@ typedef struct collage_scene_desc {
   float w_uniform;              /* weight of the uniform term, finite; 0 = the term is skipped (no
                                    launches) and reported as 0 */
   float w_wmse, w_centre, w_objdown; /* weights of terms [6]-[8], finite */
-  int32_t tile;                 /* screen tile edge in px: 8, 16, 32 or 64; 0 = default (16) */
+  int32_t tile;                 /* screen tile edge in px: 8, 16, 32, 64 or 128; 0 = default (16) */
   int32_t code_capacity;        /* 64-pixel chunks of (tile, item) work whose nearest-edge codes (2 bytes
                                    per pixel) are kept between the coverage and adjoint passes; the
                                    adjoint rescans the edges of later chunks.  -1 = default (four

@@ -32,7 +32,7 @@ class LaunchConfig:
         return {"tile": self.tile, "code_capacity": self.code_capacity, "bin_chunk": self.bin_chunk}
 
 
-DEFAULT_SPACE = [LaunchConfig(t, c, 0) for t, c in itertools.product((8, 16, 32, 64), (-1, 0))]
+DEFAULT_SPACE = [LaunchConfig(t, c, 0) for t, c in itertools.product((8, 16, 32, 64, 128), (-1, 0))]
 # candidates whose workspace exceeds this are not tried (with the default unit pools no standard workload
 # comes near it; a scene created with unit_capacity=-1 holds every item in every tile, which grows with
 # canvas area x items)

@@ -144,8 +144,8 @@ int validate_desc(const collage_scene_desc *d) {
                                 d->w_uniform, d->w_wmse, d->w_centre, d->w_objdown};
   for (float x : ws)
     if (!std::isfinite(x)) return fail(COLLAGE_ERR_INVALID, "loss weights must be finite");
-  if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32 && d->tile != 64)
-    return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8, 16, 32 or 64 (got %d)", d->tile);
+  if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32 && d->tile != 64 && d->tile != 128)
+    return fail(COLLAGE_ERR_UNSUPPORTED, "tile must be 0, 8, 16, 32, 64 or 128 (got %d)", d->tile);
   if (d->code_capacity < -1) return fail(COLLAGE_ERR_INVALID, "code_capacity must be -1 or >= 0");
   if (d->unit_capacity < -1) return fail(COLLAGE_ERR_INVALID, "unit_capacity must be -1, 0 or > 0");
   if (d->bin_chunk < 0 || d->bin_chunk > kMaxBinChunk)

@@ -55,7 +55,7 @@ static_assert(sizeof(BinRec) == 48, "bin record size");
 // One (tile, item) work unit as the persistent passes read it, written by the binning kernel beside the
 // unit's list entry: a wave loads one record per unit instead of the list entry and then the item's.
 // 48 bytes: the small fields are packed (vertex and edge counts <= 32767, canvas coordinates <= 32767,
-// the rectangle's width <= 32 and its pixel count <= 1024).
+// the rectangle's width <= 128 and its pixel count <= 16384: at most one tile).
 struct alignas(16) UnitRec {
   int32_t eo;      // the item's first edge record (= first vertex)
   int32_t ecnv;    // edges (bits 0-15) and vertices (bits 16-31) of the item
@@ -108,7 +108,7 @@ struct KArgs {
   int32_t num_shapes;
   int32_t total_tiles;
   int32_t total_ptiles;  // pixel tiles over all layouts
-  int32_t tile;          // tile edge in px (8, 16, 32 or 64)
+  int32_t tile;          // tile edge in px (8, 16, 32, 64 or 128)
   int32_t bin_chunk;     // items binned per pass
   int32_t *item_base;    // [N] each item's first per-item map entry, -1 when its layout's units did not
                          // fit its pool (written by binning)

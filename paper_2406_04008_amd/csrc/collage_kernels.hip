@@ -1113,10 +1113,10 @@ __device__ __forceinline__ bool box_meets_tile(int4 bb, int x0, int y0, int T) {
 // ------------------------------------------------------------------------------------------------
 constexpr int kBinPerThread = 2;  // candidates a binning thread loads per pass (4 measured slower)
 
-// Workgroups per screen tile: 64 x 64 tiles spread the clearing of their accumulators over four (only
-// the first bins), so that it is not left to a quarter as many workgroups as compute units.
+// Workgroups per screen tile: 64 x 64 and 128 x 128 tiles spread the clearing of their accumulators
+// over 4 and 16 (only the first bins), so that it is not left to a fraction of the compute units.
 template <int T>
-constexpr int kBinParts = T >= 64 ? 4 : 1;
+constexpr int kBinParts = T >= 128 ? 16 : (T >= 64 ? 4 : 1);
 
 template <int T>
 __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
@@ -2665,6 +2665,10 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
     } break;                                                                                         \
     case 64: {                                                                                       \
       constexpr int T_ = 64;                                                                         \
+      STMT;                                                                                          \
+    } break;                                                                                         \
+    case 128: {                                                                                      \
+      constexpr int T_ = 128;                                                                        \
       STMT;                                                                                          \
     } break;                                                                                         \
     default: {                                                                                       \

@@ -57,6 +57,7 @@ def _desc(B=1, N=1, V=4, w=(16,), h=(16,), k=(1.0,), shapes=(0, 1), voff=(0, 4))
     (lambda d: setattr(d, "w_fill", float("inf")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "w_uniform", float("nan")), _lib.ERR_INVALID),
     (lambda d: setattr(d, "tile", 12), _lib.ERR_UNSUPPORTED),
+    (lambda d: setattr(d, "tile", 256), _lib.ERR_UNSUPPORTED),
     (lambda d: setattr(d, "flags", 0x80), _lib.ERR_UNSUPPORTED),
     (lambda d: setattr(d, "flags", 0x3), _lib.ERR_UNSUPPORTED),
     (lambda d: setattr(d, "w_wmse", float("inf")), _lib.ERR_INVALID),

@@ -61,7 +61,7 @@ def oracles():
     return get
 
 
-@pytest.mark.parametrize("tile", [16, 8, 32, 64])
+@pytest.mark.parametrize("tile", [16, 8, 32, 64, 128])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_forward_parity(name, tile, oracles):
     sc, o = oracles(name)
@@ -74,7 +74,7 @@ def test_forward_parity(name, tile, oracles):
     check_loss(_np(loss), L)
 
 
-@pytest.mark.parametrize("tile", [16, 8, 32, 64])
+@pytest.mark.parametrize("tile", [16, 8, 32, 64, 128])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_backward_parity_autograd(name, tile, oracles):
     sc, o = oracles(name)
@@ -106,7 +106,7 @@ def test_tiles_listing_more_units_than_lds_holds():
 
 
 @pytest.mark.parametrize("code_capacity,bin_chunk", [(-1, 0), (0, 0), (2, 3)])
-@pytest.mark.parametrize("tile", [16, 8, 32, 64])
+@pytest.mark.parametrize("tile", [16, 8, 32, 64, 128])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_fused_parity(name, tile, code_capacity, bin_chunk, oracles):
     sc, o = oracles(name)
@@ -233,7 +233,7 @@ def test_iterate_equals_fused_then_step():
     assert int(s1.item()) == 3 and int(s2.item()) == 3
 
 
-@pytest.mark.parametrize("tile", [8, 32, 64])
+@pytest.mark.parametrize("tile", [8, 32, 128])
 def test_iterate_n_equals_repeated_iterate(tile):
     # inside collage_iterate_n the update kernel transforms the items for the next epoch; the result
     # must be bitwise that of separate epochs
@@ -404,7 +404,7 @@ def test_force_terms_vs_central_differences():
 
 
 @pytest.mark.parametrize("code_capacity", [-1, 0])
-@pytest.mark.parametrize("tile", [16, 8, 32, 64])
+@pytest.mark.parametrize("tile", [16, 8, 32, 64, 128])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_vertex_gradient_parity(name, tile, code_capacity, oracles):
     """dLoss/d(outline vertex) and the parameter gradient of the same call, with a random dloss."""
@@ -520,7 +520,7 @@ def test_edge_cases():
                              w_pad=1, r_pad=2.0, w_down=1e-3)
     sc.rho[:2] = 1.0
     o = Oracle(sc)
-    for tile in (8, 16, 32, 64):
+    for tile in (8, 16, 64, 128):
         cs = CollageScene(sc, tile=tile)
         cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
         S_, Sp, L = o.forward(sc.params)
@@ -574,7 +574,7 @@ def test_tile_sizes_give_the_same_bits(name, level):
     sc = getattr(S, name)(0)
     _say("tile sizes", name, level)
     ref = None
-    for tile in (32, 8, 16, 64):
+    for tile in (32, 8, 16, 64, 128):
         cs = CollageScene(sc, level=level, tile=tile)
         out = [x.clone() for x in cs.forward_backward(cs.params_tensor())]
         assert cs.status()[_lib.STATUS_GRAD_RANGE] == 0
@@ -596,7 +596,7 @@ def test_degenerate_scales():
     o = Oracle(sc)
     S_, Sp, L = o.forward(p)
     g_ref = o.backward(p)
-    for tile in (8, 16, 32, 64):
+    for tile in (8, 16, 64, 128):
         cs = CollageScene(sc, tile=tile)
         cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor(p))
         check_image(_np(cov), S_, "S")
@@ -619,7 +619,7 @@ def test_items_with_more_edges_than_one_lds_stage(code_capacity):
     o = Oracle(sc)
     S_, Sp, L = o.forward(sc.params)
     g_ref = o.backward(sc.params)
-    for tile in (8, 16, 32, 64):
+    for tile in (8, 16, 64, 128):
         _say("long outlines", tile, code_capacity)
         cs = CollageScene(sc, tile=tile, code_capacity=code_capacity)
         cov, cov_pad, loss, grad = cs.forward_backward(cs.params_tensor())
@@ -667,7 +667,7 @@ def test_batched_layouts_match_separate_scenes():
         assert torch.equal(g1, grad[lay.shape_begin:lay.shape_end])
 
 
-@pytest.mark.parametrize("tile", [32, 16, 64])
+@pytest.mark.parametrize("tile", [32, 16, 128])
 def test_full_batch_sampled_layouts(tile):
     # the 64-layout batch at full resolution, in the benchmark's launch; the oracle evaluates a
     # sample of its layouts on their own (layouts are independent)
