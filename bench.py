@@ -558,7 +558,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "dtype_note": "float32 edge scan; float64 per-(pixel, item) distance, coverage, loss and adjoint (its logistic-derivative factor in float32)",
+        "dtype_note": "float32 edge scan; float64 per-(pixel, item) nearest-edge decision, distance, coverage, loss and adjoint; exact fixed-point sums of coverage (2^-40) and gradient terms (2^-30)",
         "data": "synthetic",
         "config": {"workload": workload_desc, "tile": cfg.tile,
                    "code_capacity": cfg.code_capacity, "bin_chunk": cfg.bin_chunk},
