@@ -2549,7 +2549,22 @@ __device__ void finalize_loss(const KArgs &a, int b) {
     double s[kLossTerms];
 #pragma unroll
     for (int t = 0; t < kLossTerms; ++t) s[t] = 0.0;
-    for (int j = v; j < np; j += 256) {
+    // four tiles' loads in flight at a time, added in tile order
+    int j = v;
+    for (; j + 3 * 256 < np; j += 4 * 256) {
+      double r[4][kLossTerms];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double *bl = a.block_loss + (int64_t)(p0 + j + i * 256) * kLossTerms;
+#pragma unroll
+        for (int t = 0; t < kLossTerms; ++t) r[i][t] = bl[t];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < kLossTerms; ++t) s[t] += r[i][t];
+    }
+    for (; j < np; j += 256) {
       const double *bl = a.block_loss + (int64_t)(p0 + j) * kLossTerms;
 #pragma unroll
       for (int t = 0; t < kLossTerms; ++t) s[t] += bl[t];
@@ -2739,13 +2754,14 @@ hipError_t launch_adjoint(const KArgs &a, hipStream_t st) {
 hipError_t launch_finalize(const KArgs &a, bool do_grad, bool do_loss, bool do_adam, hipStream_t st,
                            bool do_transform) {
   // each item's gradient is a short chain of dependent loads: with fewer than 2048 items, two items
-  // per workgroup spread the chains over twice the compute units (one wave per item: 64 per threads)
+  // per workgroup spread the chains over twice the compute units (the workgroups keep 256 threads for
+  // the per-layout loss sums, the other waves of a gradient workgroup exit at once)
   const int per = a.num_shapes >= 2048 ? 4 : 2;
   const int gb = do_grad ? (a.num_shapes + per - 1) / per : 0;
   const int lb = do_loss ? a.num_layouts : 0;
   if (gb + lb == 0) return hipSuccess;
   const int flags = (do_adam ? 1 : 0) | (do_loss ? 2 : 0) | (do_adam && do_transform ? 4 : 0);
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(64 * per), 0, st, a, gb, flags, per));
+  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_finalize<T>, dim3(gb + lb), dim3(256), 0, st, a, gb, flags, per));
   return hipGetLastError();
 }
 
