@@ -1111,16 +1111,18 @@ __device__ __forceinline__ bool box_meets_tile(int4 bb, int x0, int y0, int T) {
 // k_bin: per tile, the ordered item list and one work unit per (tile, item), from the tile's first unit
 // on; without the row pass, the first tile of each layout also numbers the items' map entries.
 // ------------------------------------------------------------------------------------------------
-constexpr int kBinPerThread = 2;  // candidates a binning thread loads per pass (4 measured slower)
+// Candidates a binning thread loads per pass: two when every item of the layout is a candidate (a pass
+// then holds 512 of them; four measured slower), one after the row pass, whose rows list few items
+// (half the registers, so more of a large grid's workgroups are resident at once).
 
 // Workgroups per screen tile: 64 x 64 and 128 x 128 tiles spread the clearing of their accumulators
 // over 4 and 16 (only the first bins), so that it is not left to a fraction of the compute units.
 template <int T>
 constexpr int kBinParts = T >= 128 ? 16 : (T >= 64 ? 4 : 1);
 
-template <int T>
+template <int T, int K>
 __global__ __launch_bounds__(T *T < 256 ? T *T : 256) void k_bin(KArgs a) {
-  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64, K = kBinPerThread, ZP = kBinParts<T>;
+  constexpr int NT = T * T < 256 ? T * T : 256, NW = NT / 64, ZP = kBinParts<T>;
   __shared__ long long s_w[NW][2];  // counting pass, per wave: units before the tile, units
   // main passes, per candidate index k and wave: hits, units of the candidates; per wave: units before
   // the tile
@@ -2695,8 +2697,13 @@ hipError_t launch_transform(const KArgs &a, hipStream_t st) {
 hipError_t launch_bin(const KArgs &a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
   if (a.rowbin) COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_rowbin<T>, dim3(a.total_rows), dim3(256), 0, st, a));
-  COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL(k_bin<T>, dim3(a.total_tiles * kBinParts<T>), dim3(T * T < 256 ? T * T : 256),
-                                              0, st, a));
+  if (a.rowbin) {
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_bin<T, 1>), dim3(a.total_tiles * kBinParts<T>),
+                                                dim3(T * T < 256 ? T * T : 256), 0, st, a));
+  } else {
+    COLLAGE_TILE_DISPATCH(T, hipLaunchKernelGGL((k_bin<T, 2>), dim3(a.total_tiles * kBinParts<T>),
+                                                dim3(T * T < 256 ? T * T : 256), 0, st, a));
+  }
   return hipGetLastError();
 }
 
