@@ -43,6 +43,7 @@ struct collage_scene {
   int64_t chunk_cap = 0;
   int32_t bin_chunk = kDefaultBinChunk;
   int32_t cover_grid = 1, adjoint_grid = 1;
+  double cover_taper = 0.25;  // set at creation from the items' vertex counts
   uint32_t flags = 0;
   std::vector<LayoutRec> layouts;
   std::vector<int32_t> vert_off;
@@ -104,6 +105,20 @@ int unit_bounds(const collage_scene_desc *d, const collage_scene *s, std::vector
     }
   }
   return COLLAGE_OK;
+}
+
+// The coverage pass's taper (the share of its last wave is 1 - taper times the first's) from the mean
+// number of vertices per item, which is about the edges a chunk scans: the longer a chunk keeps a wave
+// busy, the further the waves that the SIMDs issue last fall behind.  Measured best: 0.25 for 2,000
+// polylines of 7.5 vertices (2048^2), 0.5 for the 64-layout batch (49), 0.8 for the 500 Bezier items
+// of 80 (512^2 and 1024^2); a linear ramp between them.
+constexpr double kMinCoverTaper = 0.25, kMaxCoverTaper = 0.8;
+
+double cover_taper_of(const std::vector<int32_t> &vert_off) {
+  const size_t n = vert_off.size() > 0 ? vert_off.size() - 1 : 0;
+  if (n == 0) return kMinCoverTaper;
+  const double mean_v = (double)(vert_off[n] - vert_off[0]) / (double)n;
+  return std::min(kMaxCoverTaper, std::max(kMinCoverTaper, kMinCoverTaper + 0.0075 * (mean_v - 8.0)));
 }
 
 int validate_desc(const collage_scene_desc *d) {
@@ -173,6 +188,7 @@ KArgs base_args(const collage_scene *s, void *ws) {
   a.chunk_cap = s->chunk_cap;
   a.code_cap = s->code_cap;
   a.cover_grid = s->cover_grid;
+  a.cover_taper = s->cover_taper;
   a.adjoint_grid = s->adjoint_grid;
   a.vert_off = s->d_vert_off;
   a.verts = s->verts;
@@ -375,6 +391,7 @@ int collage_scene_create(const collage_scene_desc *desc, collage_scene **out) {
       cus <= 0)
     cus = 256;
   s->cover_grid = cus * kCoverBlocksPerCU;
+  s->cover_taper = cover_taper_of(s->vert_off);
   s->adjoint_grid = cus * kAdjointBlocksPerCU;
   s->off_aux = off;
   off = align256(off + sizeof(int4) * (size_t)s->unit_pool);

@@ -118,6 +118,7 @@ struct KArgs {
   int64_t code_cap;      // 64-pixel chunks whose nearest-edge codes are kept between the coverage and
                          // adjoint passes (the first code_cap chunks of the pass)
   int32_t cover_grid;    // workgroups of the persistent coverage kernel (all resident at once)
+  double cover_taper;    // the coverage pass's last wave gets (1 - cover_taper) times the first's share
   int32_t adjoint_grid;  // and of the persistent adjoint kernel
   const int32_t *vert_off;
   const float *verts;

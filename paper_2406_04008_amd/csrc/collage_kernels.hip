@@ -931,10 +931,9 @@ __device__ __forceinline__ int unit_search(const int4 *X, int n, long long x, bo
 // later and, the SIMDs issuing for their oldest waves first, progress more slowly: measured on the
 // coverage pass at 512^2 with equal shares, the last eighth of the waves ended 14 us after the first
 // eighth.  The coverage pass therefore tapers the shares linearly with the wave index, the last wave's
-// share (1 - taper) times the first's (taper 0.2 to 0.25: 40.6-40.8 us against 42.6 us with equal
-// shares; 0.1 to 0.5 all helped).  The
-// adjoint pass, whose waves were measured not to gain, keeps equal shares.
-constexpr double kCoverTaper = 0.25;
+// share (1 - taper) times the first's, with the scene's taper (KArgs::cover_taper: larger for items
+// with more edges, whose chunks keep a wave busy longer).  The adjoint pass, whose waves were measured
+// not to gain, keeps equal shares.
 
 __device__ __forceinline__ long long share_bound(long long tot, int g, int nwaves, double taper) {
   if (g >= nwaves) return tot;
@@ -953,8 +952,8 @@ __device__ __forceinline__ bool walk_begin(const KArgs &a, Walk &w, int gw, int 
   w.C = C;
   w.adj = adj;
   if (tot <= 0) return false;
-  const long long b0 = share_bound(tot, gw, nwaves, adj ? 0.0 : kCoverTaper);
-  w.end = share_bound(tot, gw + 1, nwaves, adj ? 0.0 : kCoverTaper);
+  const long long b0 = share_bound(tot, gw, nwaves, adj ? 0.0 : a.cover_taper);
+  w.end = share_bound(tot, gw + 1, nwaves, adj ? 0.0 : a.cover_taper);
   if (b0 >= tot || w.end <= b0) return false;
   // the last tile whose prefix is <= b0 (it has work: a tile without any would share its prefix with
   // the next one), then the last of its units whose prefix within the tile is <= b0 (units' prefixes
