@@ -36,7 +36,12 @@ def _need(t: torch.Tensor, shape, name, dtype=torch.float32):
 
 
 class CollageScene:
-    """One level of a batch of layouts, resident on one GPU."""
+    """One level of a batch of layouts, resident on one GPU.
+
+    tile: screen tile edge (8, 16, 32, 64 or 128 px; 0 = 16); code_capacity: 64-pixel chunks whose
+    nearest-edge codes the coverage pass keeps for the adjoint (-1 = default, 0 = none: the adjoint scans
+    again); unit_capacity: (tile, item) work units each layout's pool holds (0 = default bound, -1 = every
+    item in every tile); an epoch that overflows a pool is counted in status()[STATUS_UNIT_OVERFLOW]."""
 
     def __init__(self, scene: Scene, level: Optional[int] = None, device="cuda", tile: int = 0,
                  code_capacity: int = -1, bin_chunk: int = 0, flags: int = 0, mask: Optional[np.ndarray] = None,
