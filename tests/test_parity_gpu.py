@@ -121,7 +121,8 @@ def test_fused_parity(name, tile, code_capacity, bin_chunk, oracles):
 
 
 @pytest.mark.parametrize("level,tile,code_capacity", [(128, 16, -1), (256, 16, -1), (512, 16, -1), (512, 8, -1),
-                                                      (512, 32, -1), (512, 8, 0), (1024, 16, -1)])
+                                                      (512, 32, -1), (512, 8, 0), (1024, 16, -1), (512, 64, -1),
+                                                      (512, 128, -1), (512, 128, 0), (1024, 128, -1)])
 def test_metric_scene_levels(level, tile, code_capacity):
     """500 Bezier items, the coarse-to-fine levels of the metric scene; 512 is the benchmark launch, in
     every tile size the autotuner may pick."""
@@ -494,9 +495,10 @@ def test_uniform_term_is_deterministic_and_forward_matches_fused():
     check_grad(_np(g_u), o.backward(sc.params, dloss=_np(dl).astype(np.float64)))
 
 
-@pytest.mark.parametrize("level,tile", [(256, 16), (2048, 32)])
+@pytest.mark.parametrize("level,tile", [(256, 16), (2048, 32), (256, 64), (1024, 128)])
 def test_open_scene_levels(level, tile):
-    """2000 stroked polylines on the 2048 x 2048 scene at its coarsest and finest levels."""
+    """2000 stroked polylines on the 2048 x 2048 scene at its coarsest and finest levels, and in the tiles
+    the schedule's autotuner picks for its levels."""
     sc = S.config5(0)
     _say("config5 level", level, "tile", tile)
     o = Oracle(sc, level=level)
